@@ -1,0 +1,197 @@
+/*
+ * unifrac_mi.h -- C ABI of the MI355X (gfx950) UniFrac distance library.
+ *
+ * The library computes the condensed matrix of pairwise UniFrac distances between
+ * microbiome samples, given a phylogenetic tree that relates the features (Section 1 of
+ * "Porting and optimizing UniFrac for GPUs", Sfiligoi, McDonald & Knight, 2020) and a
+ * sample x feature count table.  The computation follows the Striped UniFrac structure the
+ * paper ports to GPUs (Sections 2-3, Figs. 1-3): every branch of the tree contributes an
+ * embedding (per-sample abundance below the branch), and every embedding is folded,
+ * weighted by the branch length, into numerator and denominator accumulators laid out as
+ * stripes (stripe s pairs sample k with sample (k+s+1) mod n).  The paper ships its code
+ * as a C shared library linkable from any language (Abstract); this header is that
+ * surface for this implementation.
+ *
+ * Conventions shared by every entry point
+ *  - Status codes: every function returns uf_status (UF_OK = 0).  No C++ exception, abort
+ *    or signal crosses the ABI.  A failing call leaves a message retrievable with
+ *    uf_last_error().
+ *  - Ownership: the caller owns every input array; they are read during the call only and
+ *    never retained, except that uf_plan_create copies what it needs into the plan.
+ *    Output buffers are caller-owned too.  Contexts and plans are library-owned opaque
+ *    objects released with their destroy function.
+ *  - Pointers: tree and table arrays are HOST pointers.  Output pointers are host or device
+ *    pointers as the `out_on_device` flag says (device = memory of the context's GPU).
+ *  - Streams: `stream` is a hipStream_t passed as void* (NULL = the default stream).  All
+ *    device work is enqueued on it; the call returns after the output is complete.
+ *  - Condensed order: pair (i, j), i < j, sits at index n*i - i*(i+1)/2 + (j - i - 1)
+ *    (row i ascending, then j ascending), n = number of samples = CSR rows.
+ *  - Threading: a context and its plans must not be used by two host threads at once.
+ */
+#ifndef UNIFRAC_MI_H
+#define UNIFRAC_MI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    UF_OK = 0,
+    UF_E_ARG = 1,          /* null pointer, bad enum, size out of range                     */
+    UF_E_TREE = 2,         /* parent array: not exactly one root, cycle, index out of range,
+                              or a branch length that is negative / not finite              */
+    UF_E_TABLE = 3,        /* CSR: bad indptr, feature id out of range, negative count,
+                              feature mapped to a non-leaf node, per-sample total > INT32_MAX */
+    UF_E_EMPTY_SAMPLE = 4, /* a sample whose total count is zero                             */
+    UF_E_DEVICE = 5,       /* HIP runtime error                                              */
+    UF_E_OOM = 6,          /* device allocation failed                                       */
+    UF_E_UNSUPPORTED = 7,  /* method/precision combination not provided                      */
+    UF_E_INTERNAL = 8
+} uf_status;
+
+/* UniFrac variant.  Unweighted: per pair, branch length seen in exactly one sample over
+ * branch length seen in either.  Weighted normalized: per pair, sum over branches of
+ * L * |p - q| over sum of L * (p + q), with p, q the fractions of each sample's reads below
+ * the branch.  The root has no branch. */
+typedef enum { UF_UNWEIGHTED = 0, UF_WEIGHTED_NORMALIZED = 1 } uf_method;
+
+/* Arithmetic of the hot path (the fp64 / fp32 code paths of Section 4, plus a matrix-core
+ * form of the unweighted variant):
+ *  UF_PREC_FP64       embeddings, products and accumulation in FP64 (striped kernel).
+ *  UF_PREC_FP32       FP32 embeddings and products, FP32 sums within an embedding batch,
+ *                     FP64 accumulation across batches, FP64 final division.
+ *  UF_PREC_MFMA_BF16X2 unweighted only: shared branch length as P diag(L) P^T over 0/1
+ *                     presence P on bf16 matrix cores, with every length split into two
+ *                     bf16 terms (hi + lo), FP32 accumulation inside chunks of branches and
+ *                     FP64 across chunks; FP64 final division. */
+typedef enum { UF_PREC_FP64 = 0, UF_PREC_FP32 = 1, UF_PREC_MFMA_BF16X2 = 2 } uf_precision;
+
+typedef enum { UF_F64 = 0, UF_F32 = 1 } uf_dtype;
+
+/* Tree as a parent array.  parent[v] in [0, n_nodes) or -1 for the single root; every
+ * node must reach the root.  length[v] >= 0 and finite is the length of the branch above v;
+ * length[root] is ignored. */
+typedef struct {
+    int32_t n_nodes;
+    const int32_t *parent;
+    const double *length;
+} uf_tree;
+
+/* Sample x feature counts in CSR form, one row per sample (row order = sample order).
+ * indptr[0] == 0, indptr non-decreasing, indptr[n_samples] = nnz.  indices[e] in
+ * [0, n_features); duplicates within a row are summed.  counts[e] >= 0.  feature_node[f]
+ * is the tree node of feature f and must be a leaf; NULL means feature f is node f.
+ * Every sample needs a positive total, and a sample's total must fit in int32. */
+typedef struct {
+    int32_t n_samples;
+    int32_t n_features;
+    const int64_t *indptr;
+    const int32_t *indices;
+    const int32_t *counts;
+    const int32_t *feature_node;
+} uf_table;
+
+/* Optional knobs; a NULL pointer or a zero field means "library default / tuned value". */
+typedef struct {
+    int32_t emb_batch;  /* branches per embedding batch streamed through the striped kernel
+                           (the batch depth of Section 3, Fig. 2)                            */
+    int32_t k_chunk;    /* matrix-core path: branches accumulated in FP32 before each FP64
+                           flush (rounded to a multiple of 64)                               */
+    int32_t den_mode;   /* striped path: 0 = numerator and denominator stripes (default);
+                           1 = numerator stripes only, denominator from per-sample sums
+                           (weighted normalized: sum_b L_b p_ib + sum_b L_b p_jb)            */
+    int32_t reserved;
+} uf_tuning;
+
+typedef struct {
+    int32_t n_samples;
+    int32_t n_nodes;
+    int32_t n_branches;  /* n_nodes - 1 */
+    int32_t n_leaves;
+    int32_t n_levels;    /* height of the tree + 1: kernel launches of the propagation    */
+    int32_t n_stripes;   /* floor(n_samples / 2)                                          */
+    int64_t n_pairs;     /* n_samples * (n_samples - 1) / 2                               */
+    int64_t nnz;
+} uf_plan_info;
+
+typedef struct uf_context uf_context;
+typedef struct uf_plan uf_plan;
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char *uf_status_string(uf_status s);
+
+/* Message of the last failure: of `ctx` when non-NULL, else of the calling thread's last
+ * context-free call (uf_validate).  Valid until the next call on the same object/thread. */
+const char *uf_last_error(const uf_context *ctx);
+
+/* Validate a tree and a table on the host; touches no device.  Returns UF_OK or the first
+ * error found (UF_E_TREE, UF_E_TABLE, UF_E_EMPTY_SAMPLE, UF_E_ARG). */
+uf_status uf_validate(const uf_tree *tree, const uf_table *table);
+
+/* Create a context on HIP device `device`.  On success *out owns the device selection and
+ * a message buffer; release with uf_context_destroy. */
+uf_status uf_context_create(int32_t device, uf_context **out);
+void uf_context_destroy(uf_context *ctx);
+
+/* Validate and preprocess (tree levels, child lists, leaf slots of every CSR entry,
+ * per-sample totals), then upload the inputs to the device on `stream`.  After it returns
+ * the plan's inputs are resident in device memory and the host arrays may be freed. */
+uf_status uf_plan_create(uf_context *ctx, const uf_tree *tree, const uf_table *table,
+                         void *stream, uf_plan **out);
+void uf_plan_destroy(uf_plan *plan);
+uf_status uf_plan_query(const uf_plan *plan, uf_plan_info *info);
+
+/* Embedding propagation only (the per-branch input buffers of Section 3): out[v][k] =
+ * reads of sample k on tips at or below node v, for every node v (root row = totals),
+ * as int32 in node-id order, [n_nodes][n_samples] row-major. */
+uf_status uf_plan_embedding_counts(uf_plan *plan, int32_t *out, int32_t out_on_device,
+                                   void *stream);
+
+/* Presence bits of the same embedding: bit (k % 32) of out[v][k / 32] is set iff sample k
+ * has a read at or below node v; [n_nodes][ceil(n_samples / 32)] uint32, node-id order. */
+uf_status uf_plan_embedding_presence(uf_plan *plan, uint32_t *out, int32_t out_on_device,
+                                     void *stream);
+
+/* The full hot path on resident inputs: embedding propagation, transform, striped (or
+ * matrix-core) accumulation, normalize/condense.  `out` receives n*(n-1)/2 values of
+ * `out_dtype` in condensed order.  UF_PREC_MFMA_BF16X2 with UF_WEIGHTED_NORMALIZED returns
+ * UF_E_UNSUPPORTED.  Device scratch is allocated on first use and kept by the plan. */
+uf_status uf_plan_distance(uf_plan *plan, uf_method method, uf_precision prec,
+                           const uf_tuning *tuning, uf_dtype out_dtype, void *out,
+                           int32_t out_on_device, void *stream);
+
+/* Raw stripe accumulators of the striped path (for inspection): num and den, each
+ * [n_stripes][n_samples] FP64 row-major on the host, where row s, column k holds the sums
+ * for the pair (k, (k + s + 1) mod n).  Only UF_PREC_FP64 / UF_PREC_FP32. */
+uf_status uf_plan_stripes(uf_plan *plan, uf_method method, uf_precision prec,
+                          const uf_tuning *tuning, double *num, double *den, void *stream);
+
+/* Release the plan's cached device scratch (embeddings, stripes); inputs stay resident. */
+uf_status uf_plan_trim(uf_plan *plan);
+
+/* Per-kernel timing with HIP events recorded on the launch stream around every device
+ * launch of the plan, grouped by kernel class ("propagate", "transform", "stripe",
+ * "rowdot", "condense", "bits_transpose", "mfma", "normalize").  enable != 0 turns it on
+ * and clears the totals; enable == 0 turns it off.  Costs one event pair per launch. */
+typedef struct {
+    char name[32];
+    int64_t launches;
+    double total_ms;
+} uf_kernel_stat;
+uf_status uf_plan_set_profiling(uf_plan *plan, int32_t enable);
+/* Copies up to `cap` classes with at least one launch into `out`; *n_out = classes copied. */
+uf_status uf_plan_get_profile(uf_plan *plan, uf_kernel_stat *out, int32_t cap, int32_t *n_out);
+
+/* One-shot convenience: plan_create + plan_distance + plan_destroy. */
+uf_status uf_distance(uf_context *ctx, const uf_tree *tree, const uf_table *table,
+                      uf_method method, uf_precision prec, uf_dtype out_dtype, void *out,
+                      int32_t out_on_device, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UNIFRAC_MI_H */

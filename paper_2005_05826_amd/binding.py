@@ -1,0 +1,303 @@
+"""Thin ctypes binding over the C ABI in include/unifrac_mi.h.
+
+Argument marshalling only: every step of the distance computation runs inside
+libunifrac_mi.so.  If the library has not been built this module raises at import time;
+there is no fallback implementation.
+
+Inputs are numpy arrays (host).  Outputs are numpy arrays (host) or, for the distance
+entry point, optionally a device tensor whose data pointer is handed to the library
+(torch is used only for that memory and for the current stream).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libunifrac_mi.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with "
+                      "`python -m paper_2005_05826_amd.build` (or __graft_entry__.build())")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+c_i32, c_i64, c_p = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+
+UF_OK = 0
+STATUS_NAMES = {0: "UF_OK", 1: "UF_E_ARG", 2: "UF_E_TREE", 3: "UF_E_TABLE",
+                4: "UF_E_EMPTY_SAMPLE", 5: "UF_E_DEVICE", 6: "UF_E_OOM",
+                7: "UF_E_UNSUPPORTED", 8: "UF_E_INTERNAL"}
+METHODS = {"unweighted": 0, "weighted_normalized": 1}
+PRECISIONS = {"fp64": 0, "fp32": 1, "mfma_bf16x2": 2}
+DTYPES = {"f64": 0, "f32": 1}
+
+# every entry point declared in include/unifrac_mi.h
+EXPORTED = ["uf_status_string", "uf_last_error", "uf_validate", "uf_context_create",
+            "uf_context_destroy", "uf_plan_create", "uf_plan_destroy", "uf_plan_query",
+            "uf_plan_embedding_counts", "uf_plan_embedding_presence", "uf_plan_distance",
+            "uf_plan_stripes", "uf_plan_trim", "uf_plan_set_profiling",
+            "uf_plan_get_profile", "uf_distance"]
+
+
+class UfTree(ctypes.Structure):
+    _fields_ = [("n_nodes", c_i32), ("parent", c_p), ("length", c_p)]
+
+
+class UfTable(ctypes.Structure):
+    _fields_ = [("n_samples", c_i32), ("n_features", c_i32), ("indptr", c_p),
+                ("indices", c_p), ("counts", c_p), ("feature_node", c_p)]
+
+
+class UfTuning(ctypes.Structure):
+    _fields_ = [("emb_batch", c_i32), ("k_chunk", c_i32), ("den_mode", c_i32),
+                ("reserved", c_i32)]
+
+
+class UfKernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", c_i64), ("total_ms", ctypes.c_double)]
+
+
+class UfPlanInfo(ctypes.Structure):
+    _fields_ = [("n_samples", c_i32), ("n_nodes", c_i32), ("n_branches", c_i32),
+                ("n_leaves", c_i32), ("n_levels", c_i32), ("n_stripes", c_i32),
+                ("n_pairs", c_i64), ("nnz", c_i64)]
+
+
+_lib.uf_status_string.argtypes = [ctypes.c_int]
+_lib.uf_status_string.restype = ctypes.c_char_p
+_lib.uf_last_error.argtypes = [c_p]
+_lib.uf_last_error.restype = ctypes.c_char_p
+_lib.uf_validate.argtypes = [ctypes.POINTER(UfTree), ctypes.POINTER(UfTable)]
+_lib.uf_context_create.argtypes = [c_i32, ctypes.POINTER(c_p)]
+_lib.uf_context_destroy.argtypes = [c_p]
+_lib.uf_context_destroy.restype = None
+_lib.uf_plan_create.argtypes = [c_p, ctypes.POINTER(UfTree), ctypes.POINTER(UfTable), c_p,
+                                ctypes.POINTER(c_p)]
+_lib.uf_plan_destroy.argtypes = [c_p]
+_lib.uf_plan_destroy.restype = None
+_lib.uf_plan_query.argtypes = [c_p, ctypes.POINTER(UfPlanInfo)]
+_lib.uf_plan_embedding_counts.argtypes = [c_p, c_p, c_i32, c_p]
+_lib.uf_plan_embedding_presence.argtypes = [c_p, c_p, c_i32, c_p]
+_lib.uf_plan_distance.argtypes = [c_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(UfTuning),
+                                  ctypes.c_int, c_p, c_i32, c_p]
+_lib.uf_plan_stripes.argtypes = [c_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(UfTuning),
+                                 c_p, c_p, c_p]
+_lib.uf_plan_trim.argtypes = [c_p]
+_lib.uf_plan_set_profiling.argtypes = [c_p, c_i32]
+_lib.uf_plan_get_profile.argtypes = [c_p, ctypes.POINTER(UfKernelStat), c_i32,
+                                     ctypes.POINTER(c_i32)]
+_lib.uf_distance.argtypes = [c_p, ctypes.POINTER(UfTree), ctypes.POINTER(UfTable), ctypes.c_int,
+                             ctypes.c_int, ctypes.c_int, c_p, c_i32, c_p]
+for _name in ("uf_validate", "uf_context_create", "uf_plan_create", "uf_plan_query",
+              "uf_plan_embedding_counts", "uf_plan_embedding_presence", "uf_plan_distance",
+              "uf_plan_stripes", "uf_plan_trim", "uf_plan_set_profiling",
+              "uf_plan_get_profile", "uf_distance"):
+    getattr(_lib, _name).restype = ctypes.c_int
+
+
+class UniFracError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        self.status = status
+        self.status_name = STATUS_NAMES.get(status, str(status))
+        super().__init__(f"{self.status_name}: {message}")
+
+
+def library():
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else c_p(a.ctypes.data)
+
+
+class _Inputs:
+    """Contiguous typed copies of the inputs plus the ABI structs pointing at them."""
+
+    def __init__(self, parent, length, indptr, indices, counts, n_features, feature_node=None):
+        self.parent = np.ascontiguousarray(parent, np.int32)
+        self.length = np.ascontiguousarray(length, np.float64)
+        self.indptr = np.ascontiguousarray(indptr, np.int64)
+        self.indices = np.ascontiguousarray(indices, np.int32)
+        self.counts = np.ascontiguousarray(counts, np.int32)
+        self.feature_node = None if feature_node is None else np.ascontiguousarray(feature_node, np.int32)
+        self.tree = UfTree(self.parent.shape[0], _ptr(self.parent), _ptr(self.length))
+        self.table = UfTable(self.indptr.shape[0] - 1, int(n_features), _ptr(self.indptr),
+                             _ptr(self.indices), _ptr(self.counts), _ptr(self.feature_node))
+
+
+def _problem_args(prob):
+    return (prob.parent, prob.length, prob.indptr, prob.indices, prob.counts, prob.n_features,
+            prob.feature_node)
+
+
+def validate(parent, length, indptr, indices, counts, n_features, feature_node=None):
+    """Host-only validation.  Returns (status, message)."""
+    inp = _Inputs(parent, length, indptr, indices, counts, n_features, feature_node)
+    st = _lib.uf_validate(ctypes.byref(inp.tree), ctypes.byref(inp.table))
+    return st, _lib.uf_last_error(None).decode()
+
+
+def validate_problem(prob):
+    return validate(*_problem_args(prob))
+
+
+def _stream_handle(stream):
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available() and torch.cuda.is_initialized():
+                return c_p(torch.cuda.current_stream().cuda_stream)
+        except ImportError:
+            pass
+        return None
+    if isinstance(stream, int):
+        return c_p(stream)
+    return c_p(stream.cuda_stream)
+
+
+def _tuning(t):
+    if t is None:
+        return None
+    if isinstance(t, UfTuning):
+        return ctypes.byref(t)
+    return ctypes.byref(UfTuning(int(t.get("emb_batch", 0)), int(t.get("k_chunk", 0)),
+                                 int(t.get("den_mode", 0)), 0))
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        h = c_p()
+        st = _lib.uf_context_create(int(device), ctypes.byref(h))
+        if st != UF_OK:
+            raise UniFracError(st, _lib.uf_last_error(None).decode())
+        self._h = h
+        self.device = device
+
+    @property
+    def handle(self):
+        return self._h
+
+    def _check(self, st):
+        if st != UF_OK:
+            raise UniFracError(st, _lib.uf_last_error(self._h).decode())
+
+    def close(self):
+        if self._h:
+            _lib.uf_context_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    """Inputs validated, preprocessed and resident on the device."""
+
+    def __init__(self, ctx: Context, parent, length, indptr, indices, counts, n_features,
+                 feature_node=None, stream=None):
+        self.ctx = ctx
+        inp = _Inputs(parent, length, indptr, indices, counts, n_features, feature_node)
+        h = c_p()
+        ctx._check(_lib.uf_plan_create(ctx.handle, ctypes.byref(inp.tree), ctypes.byref(inp.table),
+                                       _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+        self.info = self.query()
+
+    @classmethod
+    def from_problem(cls, ctx: Context, prob, stream=None):
+        return cls(ctx, *_problem_args(prob), stream=stream)
+
+    def query(self) -> UfPlanInfo:
+        info = UfPlanInfo()
+        self.ctx._check(_lib.uf_plan_query(self._h, ctypes.byref(info)))
+        return info
+
+    def embedding_counts(self, stream=None) -> np.ndarray:
+        out = np.empty((self.info.n_nodes, self.info.n_samples), np.int32)
+        self.ctx._check(_lib.uf_plan_embedding_counts(self._h, _ptr(out), 0, _stream_handle(stream)))
+        return out
+
+    def embedding_presence(self, stream=None) -> np.ndarray:
+        words = (self.info.n_samples + 31) // 32
+        out = np.empty((self.info.n_nodes, words), np.uint32)
+        self.ctx._check(_lib.uf_plan_embedding_presence(self._h, _ptr(out), 0, _stream_handle(stream)))
+        return out
+
+    def distance(self, method="unweighted", precision="fp64", out=None, out_dtype="f64",
+                 tuning=None, stream=None):
+        """Condensed distances.  `out` may be None (a host numpy array is returned), a numpy
+        array, or a device tensor of n*(n-1)/2 elements (torch; its pointer is passed)."""
+        n_pairs = self.info.n_pairs
+        if out is None:
+            out = np.empty(n_pairs, np.float64 if out_dtype == "f64" else np.float32)
+        if isinstance(out, np.ndarray):
+            if out.size != n_pairs or not out.flags.c_contiguous:
+                raise ValueError("out must be a contiguous array of n*(n-1)/2 elements")
+            want = np.float64 if out_dtype == "f64" else np.float32
+            if out.dtype != want:
+                raise ValueError(f"out dtype must be {want}")
+            ptr, on_dev = _ptr(out), 0
+        else:  # device tensor
+            if out.numel() != n_pairs or not out.is_contiguous():
+                raise ValueError("out must be a contiguous tensor of n*(n-1)/2 elements")
+            import torch
+            want = torch.float64 if out_dtype == "f64" else torch.float32
+            if out.dtype != want:
+                raise ValueError(f"out dtype must be {want}")
+            ptr, on_dev = c_p(out.data_ptr()), 1
+        self.ctx._check(_lib.uf_plan_distance(self._h, METHODS[method], PRECISIONS[precision],
+                                              _tuning(tuning), DTYPES[out_dtype], ptr, on_dev,
+                                              _stream_handle(stream)))
+        return out
+
+    def stripes(self, method="unweighted", precision="fp64", tuning=None, stream=None):
+        S, n = self.info.n_stripes, self.info.n_samples
+        num = np.empty((S, n), np.float64)
+        den = np.empty((S, n), np.float64)
+        self.ctx._check(_lib.uf_plan_stripes(self._h, METHODS[method], PRECISIONS[precision],
+                                             _tuning(tuning), _ptr(num), _ptr(den),
+                                             _stream_handle(stream)))
+        return num, den
+
+    def trim(self):
+        self.ctx._check(_lib.uf_plan_trim(self._h))
+
+    def set_profiling(self, enable: bool = True):
+        self.ctx._check(_lib.uf_plan_set_profiling(self._h, 1 if enable else 0))
+
+    def profile(self) -> dict:
+        """{kernel class: (launches, total_ms)} timed with HIP events on the launch stream."""
+        cap = 16
+        buf = (UfKernelStat * cap)()
+        n = c_i32(0)
+        self.ctx._check(_lib.uf_plan_get_profile(self._h, buf, cap, ctypes.byref(n)))
+        return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms))
+                for i in range(n.value)}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.uf_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def distance(ctx: Context, prob, method="unweighted", precision="fp64", out_dtype="f64"):
+    """One-shot uf_distance on a host output array."""
+    inp = _Inputs(*_problem_args(prob))
+    n = inp.indptr.shape[0] - 1
+    out = np.empty(n * (n - 1) // 2, np.float64 if out_dtype == "f64" else np.float32)
+    ctx._check(_lib.uf_distance(ctx.handle, ctypes.byref(inp.tree), ctypes.byref(inp.table),
+                                METHODS[method], PRECISIONS[precision], DTYPES[out_dtype],
+                                _ptr(out), 0, None))
+    return out

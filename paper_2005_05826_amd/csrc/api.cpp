@@ -1,0 +1,638 @@
+// C ABI: contexts, plans, and the orchestration of the device hot path.
+//
+// A plan validates and preprocesses the inputs once and keeps them resident in device
+// memory; uf_plan_distance then runs every step of the path on the GPU:
+//   (a)  embedding propagation: scatter tip reads, one launch per height level;
+//   (a2) embedding transform of a batch of branches into wrap-padded rows;
+//   (b)  striped accumulation of the batch into the numerator/denominator stripes;
+//   (d)  normalize/condense into the caller's condensed output.
+// The matrix-core form of the unweighted variant replaces (a2)-(b) by presence bits and a
+// bf16 MFMA product (k_mfma.hip).
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+
+#include "uf_internal.h"
+
+using namespace ufmi;
+
+namespace {
+
+thread_local std::string g_tls_err;
+
+struct DevMem {
+    void *p = nullptr;
+    size_t bytes = 0;
+    hipError_t ensure(size_t want)
+    {
+        if (want == 0) want = 256;
+        if (bytes >= want) return hipSuccess;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+        hipError_t e = hipMalloc(&p, want);
+        if (e == hipSuccess) bytes = want;
+        return e;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <typename T>
+    T *as() const { return static_cast<T *>(p); }
+};
+
+// Event-pair timing of launches, grouped by kernel class.
+struct Profiler {
+    bool on = false;
+    struct Pending {
+        std::string cls;
+        hipEvent_t a, b;
+    };
+    std::vector<hipEvent_t> pool;
+    std::vector<Pending> pending;
+    std::map<std::string, std::pair<int64_t, double>> totals;
+
+    hipEvent_t take()
+    {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    void collect()
+    {
+        for (Pending &p : pending) {
+            float ms = 0.f;
+            if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+                auto &t = totals[p.cls];
+                t.first += 1;
+                t.second += ms;
+            }
+            pool.push_back(p.a);
+            pool.push_back(p.b);
+        }
+        pending.clear();
+    }
+    void release()
+    {
+        collect();
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+        pool.clear();
+    }
+};
+
+}  // namespace
+
+struct uf_context {
+    int32_t device = 0;
+    std::string err;
+};
+
+struct uf_plan {
+    uf_context *ctx = nullptr;
+    HostPrep hp;
+    // resident inputs
+    DevMem indptr, entry_slot, entry_count, totals, child_ptr, child_slot, len_slot, slot_of_node;
+    // scratch, allocated on first use
+    DevMem counts, bits, emb, num, den, D, out_tmp, gather_tmp;
+    DevMem mfma_scratch[4];
+    Profiler prof;
+    int64_t cstride = 0;  // int32 elements per count row (multiple of 64)
+    int64_t bstride = 0;  // uint32 words per presence row (multiple of 4)
+};
+
+namespace {
+
+uf_status set_err(uf_context *ctx, uf_status code, const std::string &msg)
+{
+    if (ctx)
+        ctx->err = msg;
+    else
+        g_tls_err = msg;
+    return code;
+}
+
+uf_status hip_fail(uf_context *ctx, hipError_t e, const char *what)
+{
+    std::string msg = std::string(what) + ": " + hipGetErrorString(e);
+    return set_err(ctx, e == hipErrorOutOfMemory ? UF_E_OOM : UF_E_DEVICE, msg);
+}
+
+#define UF_TRY(expr, what)                                       \
+    do {                                                         \
+        hipError_t _e = (expr);                                  \
+        if (_e != hipSuccess) return hip_fail(ctx, _e, (what));  \
+    } while (0)
+
+template <typename T>
+hipError_t upload(DevMem &m, const std::vector<T> &v, hipStream_t st)
+{
+    hipError_t e = m.ensure(v.size() * sizeof(T));
+    if (e != hipSuccess || v.empty()) return e;
+    return hipMemcpyAsync(m.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st);
+}
+
+inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+// Launch `fn` on `st`, bracketed by timing events when the plan's profiler is on.
+template <typename F>
+hipError_t timed(uf_plan *plan, const char *cls, hipStream_t st, F &&fn)
+{
+    Profiler &P = plan->prof;
+    if (!P.on) return fn();
+    hipEvent_t a = P.take(), b = P.take();
+    if (!a || !b) return fn();
+    hipError_t e = hipEventRecord(a, st);
+    if (e != hipSuccess) return e;
+    e = fn();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(b, st);
+    if (e == hipSuccess) P.pending.push_back({cls, a, b});
+    return e;
+}
+
+// (a) embedding propagation, count form.
+uf_status propagate_counts(uf_plan *plan, hipStream_t st)
+{
+    uf_context *ctx = plan->ctx;
+    const HostPrep &hp = plan->hp;
+    UF_TRY(plan->counts.ensure((size_t)hp.n_nodes * plan->cstride * sizeof(int32_t)),
+           "allocating embedding counts");
+    int32_t *C = plan->counts.as<int32_t>();
+    UF_TRY(launch_fill_u32(C, 0u, (size_t)hp.n_leaf * plan->cstride, st), "clearing tip rows");
+    UF_TRY(timed(plan, "propagate", st, [&] {
+               hipError_t r = launch_scatter_counts(plan->indptr.as<int64_t>(),
+                                                    plan->entry_slot.as<int32_t>(),
+                                                    plan->entry_count.as<int32_t>(), C,
+                                                    plan->cstride, hp.n_samples, st);
+               for (int32_t h = 1; h < hp.n_levels && r == hipSuccess; ++h) {
+                   const int32_t b = hp.level_ptr[h], e = hp.level_ptr[h + 1];
+                   r = launch_level_sum(C, plan->cstride, b, e - b, hp.n_leaf,
+                                        plan->child_ptr.as<int32_t>(),
+                                        plan->child_slot.as<int32_t>(), st);
+               }
+               return r;
+           }), "propagating counts");
+    return UF_OK;
+}
+
+// (a) embedding propagation, presence-bit form.
+uf_status propagate_bits(uf_plan *plan, hipStream_t st)
+{
+    uf_context *ctx = plan->ctx;
+    const HostPrep &hp = plan->hp;
+    UF_TRY(plan->bits.ensure((size_t)hp.n_nodes * plan->bstride * sizeof(uint32_t)),
+           "allocating presence bits");
+    uint32_t *B = plan->bits.as<uint32_t>();
+    UF_TRY(launch_fill_u32(B, 0u, (size_t)hp.n_leaf * plan->bstride, st), "clearing tip rows");
+    UF_TRY(timed(plan, "propagate", st, [&] {
+               hipError_t r = launch_scatter_bits(plan->indptr.as<int64_t>(),
+                                                  plan->entry_slot.as<int32_t>(),
+                                                  plan->entry_count.as<int32_t>(), B,
+                                                  plan->bstride, hp.n_samples, st);
+               for (int32_t h = 1; h < hp.n_levels && r == hipSuccess; ++h) {
+                   const int32_t b = hp.level_ptr[h], e = hp.level_ptr[h + 1];
+                   r = launch_level_or(B, plan->bstride, b, e - b, hp.n_leaf,
+                                       plan->child_ptr.as<int32_t>(),
+                                       plan->child_slot.as<int32_t>(), st);
+               }
+               return r;
+           }), "propagating presence");
+    return UF_OK;
+}
+
+struct Knobs {
+    int32_t emb_batch, k_chunk, den_mode;
+};
+
+Knobs resolve_knobs(const uf_tuning *t, uf_precision prec, int32_t n_branches)
+{
+    Knobs k;
+    // FP32 sums inside a batch: worst-case relative error ~ E * 2^-24 of the denominator,
+    // so the FP32 default batch is kept at 128 (< 1e-5); FP64 batches only trade stripe
+    // traffic against embedding-buffer size.
+    k.emb_batch = (t && t->emb_batch > 0) ? t->emb_batch : (prec == UF_PREC_FP32 ? 128 : 1024);
+    k.emb_batch = std::min(k.emb_batch, 4096);
+    if (n_branches > 0) k.emb_batch = std::min(k.emb_batch, n_branches);
+    k.emb_batch = std::max(k.emb_batch, 1);
+    k.k_chunk = (t && t->k_chunk > 0) ? t->k_chunk : 4096;
+    k.den_mode = (t ? t->den_mode : 0);
+    return k;
+}
+
+// (a)-(b): fills plan->num / den (den_mode 0) or num / D (den_mode 1).
+uf_status run_striped(uf_plan *plan, uf_method method, uf_precision prec, const Knobs &kn,
+                      StripeGeom *geom, hipStream_t st)
+{
+    uf_context *ctx = plan->ctx;
+    const HostPrep &hp = plan->hp;
+    const bool fp64 = (prec == UF_PREC_FP64);
+    const StripeGeom g = stripe_geometry(hp.n_samples, fp64);
+    *geom = g;
+    const int32_t B = hp.n_nodes - 1;
+    const size_t tsz = fp64 ? sizeof(double) : sizeof(float);
+    const size_t state = (size_t)g.spad * g.sstride * sizeof(double);
+    UF_TRY(plan->num.ensure(state), "allocating numerator stripes");
+    if (kn.den_mode == 0) UF_TRY(plan->den.ensure(state), "allocating denominator stripes");
+    UF_TRY(plan->D.ensure((size_t)hp.n_samples * sizeof(double)), "allocating per-sample sums");
+    double *num = plan->num.as<double>();
+    double *den = kn.den_mode == 0 ? plan->den.as<double>() : nullptr;
+    double *D = plan->D.as<double>();
+    if (B == 0) {  // single-node tree: no branches, every distance is 0
+        UF_TRY(launch_fill_u32(num, 0u, state / 4, st), "clearing stripes");
+        if (den) UF_TRY(launch_fill_u32(den, 0u, state / 4, st), "clearing stripes");
+        UF_TRY(launch_fill_u32(D, 0u, (size_t)hp.n_samples * 2, st), "clearing sums");
+        return UF_OK;
+    }
+    uf_status s = propagate_counts(plan, st);
+    if (s != UF_OK) return s;
+    const int32_t E = kn.emb_batch;
+    UF_TRY(plan->emb.ensure((size_t)E * g.estride * tsz), "allocating embedding batch");
+    const int32_t *C = plan->counts.as<int32_t>();
+    const double *len = plan->len_slot.as<double>();
+    for (int32_t b0 = 0; b0 < B; b0 += E) {
+        const int32_t eb = std::min(E, B - b0);
+        UF_TRY(timed(plan, "transform", st, [&] {
+                   return launch_transform(fp64, method, C, plan->cstride, b0, eb,
+                                           plan->totals.as<int32_t>(), g.n, g.S, plan->emb.p,
+                                           g.estride, st);
+               }), "embedding transform");
+        UF_TRY(timed(plan, "stripe", st, [&] {
+                   return launch_stripe(fp64, method, kn.den_mode, plan->emb.p, g.estride,
+                                        len + b0, eb, num, den, g, b0 == 0, st);
+               }), "striped accumulation");
+        if (kn.den_mode != 0)
+            UF_TRY(timed(plan, "rowdot", st, [&] {
+                       return launch_rowdot(method, C, plan->cstride, b0, eb,
+                                            plan->totals.as<int32_t>(), len + b0, g.n, D,
+                                            b0 == 0, st);
+                   }), "per-sample sums");
+    }
+    return UF_OK;
+}
+
+uf_status check_enums(uf_context *ctx, uf_method method, uf_precision prec)
+{
+    if (method != UF_UNWEIGHTED && method != UF_WEIGHTED_NORMALIZED)
+        return set_err(ctx, UF_E_ARG, "unknown method");
+    if (prec != UF_PREC_FP64 && prec != UF_PREC_FP32 && prec != UF_PREC_MFMA_BF16X2)
+        return set_err(ctx, UF_E_ARG, "unknown precision");
+    if (prec == UF_PREC_MFMA_BF16X2 && method != UF_UNWEIGHTED)
+        return set_err(ctx, UF_E_UNSUPPORTED,
+                       "the matrix-core form exists for unweighted UniFrac only");
+    return UF_OK;
+}
+
+}  // namespace
+
+namespace {
+// Matrix-core form of the unweighted variant: fills `out_dev` with condensed distances.
+// Scratch: [0] presence bytes, [1] hi/lo splits, [2] tile list, [3] T and (for FP32 or
+// host output) the FP64 shared-length array S.
+uf_status run_mfma_unweighted(uf_plan *plan, int32_t k_chunk, int32_t out_f32, void *out_dev,
+                              hipStream_t st)
+{
+    uf_context *ctx = plan->ctx;
+    const HostPrep &hp = plan->hp;
+    const int32_t n = hp.n_samples, B = hp.n_nodes - 1;
+    const MfmaGeom g = mfma_geometry(n, B);
+    const int64_t n_pairs = (int64_t)n * (n - 1) / 2;
+    k_chunk = std::max(g.kstep, k_chunk / g.kstep * g.kstep);
+    uf_status s = propagate_bits(plan, st);
+    if (s != UF_OK) return s;
+    DevMem &Pm = plan->mfma_scratch[0], &HL = plan->mfma_scratch[1];
+    DevMem &TL = plan->mfma_scratch[2], &TS = plan->mfma_scratch[3];
+    UF_TRY(Pm.ensure((size_t)g.n_pad * g.k_pad), "allocating presence bytes");
+    UF_TRY(HL.ensure((size_t)2 * g.k_pad * sizeof(uint16_t)), "allocating length splits");
+    std::vector<int32_t> xy;
+    mfma_tile_list(n, &xy);
+    UF_TRY(TL.ensure(xy.size() * sizeof(int32_t)), "allocating tile list");
+    UF_TRY(hipMemcpyAsync(TL.p, xy.data(), xy.size() * sizeof(int32_t), hipMemcpyHostToDevice, st),
+           "uploading tile list");
+    const bool s_in_out = !out_f32;   // FP64 output doubles as the S array
+    const size_t t_bytes = (size_t)g.n_pad * sizeof(double);
+    UF_TRY(TS.ensure(t_bytes + (s_in_out ? 0 : (size_t)n_pairs * sizeof(double))),
+           "allocating shared lengths");
+    double *T = TS.as<double>();
+    double *S = s_in_out ? static_cast<double *>(out_dev) : T + g.n_pad;
+    uint16_t *hi = HL.as<uint16_t>(), *lo = hi + g.k_pad;
+    UF_TRY(timed(plan, "bits_transpose", st, [&] {
+               hipError_t r = launch_split_lengths(plan->len_slot.as<double>(), B, g.k_pad, hi, lo, st);
+               if (r == hipSuccess)
+                   r = launch_bits_to_bytes(plan->bits.as<uint32_t>(), plan->bstride, g,
+                                            Pm.as<uint8_t>(), st);
+               return r;
+           }), "presence transpose");
+    UF_TRY(timed(plan, "mfma", st, [&] {
+               return launch_mfma_gemm(Pm.as<uint8_t>(), hi, lo, k_chunk, TL.as<int32_t>(), g, S,
+                                       T, st);
+           }), "matrix-core product");
+    UF_TRY(timed(plan, "normalize", st, [&] {
+               return launch_mfma_normalize(S, T, n, out_f32, out_dev, st);
+           }), "normalize");
+    return UF_OK;
+}
+}  // namespace
+
+extern "C" {
+
+const char *uf_status_string(uf_status s)
+{
+    switch (s) {
+    case UF_OK: return "UF_OK";
+    case UF_E_ARG: return "UF_E_ARG";
+    case UF_E_TREE: return "UF_E_TREE";
+    case UF_E_TABLE: return "UF_E_TABLE";
+    case UF_E_EMPTY_SAMPLE: return "UF_E_EMPTY_SAMPLE";
+    case UF_E_DEVICE: return "UF_E_DEVICE";
+    case UF_E_OOM: return "UF_E_OOM";
+    case UF_E_UNSUPPORTED: return "UF_E_UNSUPPORTED";
+    case UF_E_INTERNAL: return "UF_E_INTERNAL";
+    }
+    return "UF_E_UNKNOWN";
+}
+
+const char *uf_last_error(const uf_context *ctx)
+{
+    return ctx ? ctx->err.c_str() : g_tls_err.c_str();
+}
+
+uf_status uf_validate(const uf_tree *tree, const uf_table *table)
+{
+    HostPrep hp;
+    std::string err;
+    uf_status s = validate_and_prepare(tree, table, &hp, &err);
+    g_tls_err = (s == UF_OK) ? std::string() : err;
+    return s;
+}
+
+uf_status uf_context_create(int32_t device, uf_context **out)
+{
+    if (!out) return set_err(nullptr, UF_E_ARG, "out must not be NULL");
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count == 0)
+        return set_err(nullptr, UF_E_DEVICE, "no HIP device available");
+    if (device < 0 || device >= count) return set_err(nullptr, UF_E_ARG, "device out of range");
+    e = hipSetDevice(device);
+    if (e != hipSuccess) return set_err(nullptr, UF_E_DEVICE, hipGetErrorString(e));
+    uf_context *ctx = new (std::nothrow) uf_context;
+    if (!ctx) return set_err(nullptr, UF_E_OOM, "host allocation failed");
+    ctx->device = device;
+    *out = ctx;
+    return UF_OK;
+}
+
+void uf_context_destroy(uf_context *ctx) { delete ctx; }
+
+uf_status uf_plan_create(uf_context *ctx, const uf_tree *tree, const uf_table *table,
+                         void *stream, uf_plan **out)
+{
+    if (!ctx || !out) return set_err(ctx, UF_E_ARG, "ctx and out must not be NULL");
+    *out = nullptr;
+    uf_plan *plan = new (std::nothrow) uf_plan;
+    if (!plan) return set_err(ctx, UF_E_OOM, "host allocation failed");
+    plan->ctx = ctx;
+    std::string err;
+    uf_status s = validate_and_prepare(tree, table, &plan->hp, &err);
+    if (s != UF_OK) {
+        delete plan;
+        return set_err(ctx, s, err);
+    }
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) {
+        delete plan;
+        return hip_fail(ctx, e, "hipSetDevice");
+    }
+    const HostPrep &hp = plan->hp;
+    plan->cstride = round_up(hp.n_samples, 64);
+    plan->bstride = round_up((hp.n_samples + 31) / 32, 4);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t r = hipSuccess;
+    if (r == hipSuccess) r = upload(plan->indptr, hp.indptr, st);
+    if (r == hipSuccess) r = upload(plan->entry_slot, hp.entry_slot, st);
+    if (r == hipSuccess) r = upload(plan->entry_count, hp.entry_count, st);
+    if (r == hipSuccess) r = upload(plan->totals, hp.totals, st);
+    if (r == hipSuccess) r = upload(plan->child_ptr, hp.child_ptr, st);
+    if (r == hipSuccess) r = upload(plan->child_slot, hp.child_slot, st);
+    if (r == hipSuccess) r = upload(plan->len_slot, hp.length_slot, st);
+    if (r == hipSuccess) r = upload(plan->slot_of_node, hp.slot_of_node, st);
+    if (r == hipSuccess) r = hipStreamSynchronize(st);
+    if (r != hipSuccess) {
+        uf_plan_destroy(plan);
+        return hip_fail(ctx, r, "uploading inputs");
+    }
+    *out = plan;
+    return UF_OK;
+}
+
+void uf_plan_destroy(uf_plan *plan)
+{
+    if (!plan) return;
+    (void)hipSetDevice(plan->ctx->device);
+    for (DevMem *m : {&plan->indptr, &plan->entry_slot, &plan->entry_count, &plan->totals,
+                      &plan->child_ptr, &plan->child_slot, &plan->len_slot, &plan->slot_of_node,
+                      &plan->counts, &plan->bits, &plan->emb, &plan->num, &plan->den, &plan->D,
+                      &plan->out_tmp, &plan->gather_tmp})
+        m->release();
+    for (DevMem &m : plan->mfma_scratch) m.release();
+    plan->prof.release();
+    delete plan;
+}
+
+uf_status uf_plan_trim(uf_plan *plan)
+{
+    if (!plan) return set_err(nullptr, UF_E_ARG, "plan must not be NULL");
+    (void)hipSetDevice(plan->ctx->device);
+    for (DevMem *m : {&plan->counts, &plan->bits, &plan->emb, &plan->num, &plan->den, &plan->D,
+                      &plan->out_tmp, &plan->gather_tmp})
+        m->release();
+    for (DevMem &m : plan->mfma_scratch) m.release();
+    return UF_OK;
+}
+
+uf_status uf_plan_query(const uf_plan *plan, uf_plan_info *info)
+{
+    if (!plan || !info) return set_err(nullptr, UF_E_ARG, "plan and info must not be NULL");
+    const HostPrep &hp = plan->hp;
+    info->n_samples = hp.n_samples;
+    info->n_nodes = hp.n_nodes;
+    info->n_branches = hp.n_nodes - 1;
+    info->n_leaves = hp.n_leaf;
+    info->n_levels = hp.n_levels;
+    info->n_stripes = hp.n_samples / 2;
+    info->n_pairs = (int64_t)hp.n_samples * (hp.n_samples - 1) / 2;
+    info->nnz = hp.nnz;
+    return UF_OK;
+}
+
+static uf_status emit_rows(uf_plan *plan, const void *src, int64_t sstride, int32_t width,
+                           void *out, int32_t out_on_device, hipStream_t st)
+{
+    uf_context *ctx = plan->ctx;
+    const HostPrep &hp = plan->hp;
+    const size_t bytes = (size_t)hp.n_nodes * width * sizeof(uint32_t);
+    void *dst = out;
+    if (!out_on_device) {
+        UF_TRY(plan->gather_tmp.ensure(bytes), "allocating output staging");
+        dst = plan->gather_tmp.p;
+    }
+    UF_TRY(launch_gather_rows_u32(static_cast<const uint32_t *>(src), sstride,
+                                  plan->slot_of_node.as<int32_t>(), hp.n_nodes, width,
+                                  static_cast<uint32_t *>(dst), st), "gathering rows");
+    if (!out_on_device)
+        UF_TRY(hipMemcpyAsync(out, dst, bytes, hipMemcpyDeviceToHost, st), "copying rows out");
+    UF_TRY(hipStreamSynchronize(st), "synchronizing");
+    return UF_OK;
+}
+
+uf_status uf_plan_embedding_counts(uf_plan *plan, int32_t *out, int32_t out_on_device,
+                                   void *stream)
+{
+    if (!plan || !out) return set_err(plan ? plan->ctx : nullptr, UF_E_ARG, "NULL argument");
+    uf_context *ctx = plan->ctx;
+    UF_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    uf_status s = propagate_counts(plan, st);
+    if (s != UF_OK) return s;
+    return emit_rows(plan, plan->counts.p, plan->cstride, plan->hp.n_samples, out, out_on_device, st);
+}
+
+uf_status uf_plan_embedding_presence(uf_plan *plan, uint32_t *out, int32_t out_on_device,
+                                     void *stream)
+{
+    if (!plan || !out) return set_err(plan ? plan->ctx : nullptr, UF_E_ARG, "NULL argument");
+    uf_context *ctx = plan->ctx;
+    UF_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    uf_status s = propagate_bits(plan, st);
+    if (s != UF_OK) return s;
+    return emit_rows(plan, plan->bits.p, plan->bstride, (plan->hp.n_samples + 31) / 32, out,
+                     out_on_device, st);
+}
+
+uf_status uf_plan_distance(uf_plan *plan, uf_method method, uf_precision prec,
+                           const uf_tuning *tuning, uf_dtype out_dtype, void *out,
+                           int32_t out_on_device, void *stream)
+{
+    if (!plan) return set_err(nullptr, UF_E_ARG, "plan must not be NULL");
+    uf_context *ctx = plan->ctx;
+    uf_status s = check_enums(ctx, method, prec);
+    if (s != UF_OK) return s;
+    if (out_dtype != UF_F64 && out_dtype != UF_F32) return set_err(ctx, UF_E_ARG, "unknown dtype");
+    const HostPrep &hp = plan->hp;
+    const int64_t n_pairs = (int64_t)hp.n_samples * (hp.n_samples - 1) / 2;
+    if (n_pairs == 0) return UF_OK;
+    if (!out) return set_err(ctx, UF_E_ARG, "out must not be NULL");
+    const Knobs kn = resolve_knobs(tuning, prec, hp.n_nodes - 1);
+    if (kn.den_mode != 0 && kn.den_mode != 1) return set_err(ctx, UF_E_ARG, "den_mode must be 0 or 1");
+    UF_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t esz = out_dtype == UF_F32 ? sizeof(float) : sizeof(double);
+    void *dst = out;
+    if (!out_on_device) {
+        UF_TRY(plan->out_tmp.ensure((size_t)n_pairs * esz), "allocating output staging");
+        dst = plan->out_tmp.p;
+    }
+    if (prec == UF_PREC_MFMA_BF16X2) {
+        s = run_mfma_unweighted(plan, kn.k_chunk, out_dtype == UF_F32, dst, st);
+        if (s != UF_OK) return s;
+    } else {
+        StripeGeom g;
+        s = run_striped(plan, method, prec, kn, &g, st);
+        if (s != UF_OK) return s;
+        UF_TRY(timed(plan, "condense", st, [&] {
+                   return launch_condense(method, plan->num.as<double>(),
+                                          kn.den_mode == 0 ? plan->den.as<double>() : nullptr,
+                                          kn.den_mode == 0 ? nullptr : plan->D.as<double>(),
+                                          g.sstride, g.n, g.S, out_dtype == UF_F32, dst, st);
+               }), "condense");
+    }
+    if (!out_on_device)
+        UF_TRY(hipMemcpyAsync(out, dst, (size_t)n_pairs * esz, hipMemcpyDeviceToHost, st),
+               "copying distances out");
+    UF_TRY(hipStreamSynchronize(st), "synchronizing");
+    if (plan->prof.on) plan->prof.collect();
+    return UF_OK;
+}
+
+uf_status uf_plan_set_profiling(uf_plan *plan, int32_t enable)
+{
+    if (!plan) return set_err(nullptr, UF_E_ARG, "plan must not be NULL");
+    (void)hipSetDevice(plan->ctx->device);
+    plan->prof.collect();
+    plan->prof.totals.clear();
+    plan->prof.on = enable != 0;
+    return UF_OK;
+}
+
+uf_status uf_plan_get_profile(uf_plan *plan, uf_kernel_stat *out, int32_t cap, int32_t *n_out)
+{
+    if (!plan || !n_out || (cap > 0 && !out))
+        return set_err(plan ? plan->ctx : nullptr, UF_E_ARG, "NULL argument");
+    (void)hipSetDevice(plan->ctx->device);
+    plan->prof.collect();
+    int32_t n = 0;
+    for (const auto &kv : plan->prof.totals) {
+        if (n >= cap) break;
+        std::memset(out[n].name, 0, sizeof out[n].name);
+        std::strncpy(out[n].name, kv.first.c_str(), sizeof out[n].name - 1);
+        out[n].launches = kv.second.first;
+        out[n].total_ms = kv.second.second;
+        ++n;
+    }
+    *n_out = n;
+    return UF_OK;
+}
+
+uf_status uf_plan_stripes(uf_plan *plan, uf_method method, uf_precision prec,
+                          const uf_tuning *tuning, double *num, double *den, void *stream)
+{
+    if (!plan || !num || !den) return set_err(plan ? plan->ctx : nullptr, UF_E_ARG, "NULL argument");
+    uf_context *ctx = plan->ctx;
+    uf_status s = check_enums(ctx, method, prec);
+    if (s != UF_OK) return s;
+    if (prec == UF_PREC_MFMA_BF16X2)
+        return set_err(ctx, UF_E_ARG, "stripes exist for the striped precisions only");
+    const HostPrep &hp = plan->hp;
+    Knobs kn = resolve_knobs(tuning, prec, hp.n_nodes - 1);
+    if (kn.den_mode != 0) return set_err(ctx, UF_E_ARG, "stripes need den_mode 0");
+    if (hp.n_samples / 2 == 0) return UF_OK;
+    UF_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    StripeGeom g;
+    s = run_striped(plan, method, prec, kn, &g, st);
+    if (s != UF_OK) return s;
+    const size_t pitch = (size_t)g.sstride * sizeof(double);
+    const size_t width = (size_t)hp.n_samples * sizeof(double);
+    UF_TRY(hipMemcpy2DAsync(num, width, plan->num.p, pitch, width, g.S, hipMemcpyDeviceToHost, st),
+           "copying numerator stripes");
+    UF_TRY(hipMemcpy2DAsync(den, width, plan->den.p, pitch, width, g.S, hipMemcpyDeviceToHost, st),
+           "copying denominator stripes");
+    UF_TRY(hipStreamSynchronize(st), "synchronizing");
+    return UF_OK;
+}
+
+uf_status uf_distance(uf_context *ctx, const uf_tree *tree, const uf_table *table,
+                      uf_method method, uf_precision prec, uf_dtype out_dtype, void *out,
+                      int32_t out_on_device, void *stream)
+{
+    uf_plan *plan = nullptr;
+    uf_status s = uf_plan_create(ctx, tree, table, stream, &plan);
+    if (s != UF_OK) return s;
+    s = uf_plan_distance(plan, method, prec, nullptr, out_dtype, out, out_on_device, stream);
+    uf_plan_destroy(plan);
+    return s;
+}
+
+}  // extern "C"

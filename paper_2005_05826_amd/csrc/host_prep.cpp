@@ -1,0 +1,170 @@
+// Host-side validation and preprocessing of the tree and the count table.
+//
+// Everything here runs before any device work so that a malformed input is rejected with
+// a status code and never reaches a kernel.  The products are the level schedule used by
+// the level-synchronous embedding propagation (children of a node always sit in an earlier
+// level) and the leaf slot of every CSR entry.
+#include <cmath>
+#include <cstdio>
+#include <limits>
+
+#include "uf_internal.h"
+
+namespace ufmi {
+
+namespace {
+uf_status fail(std::string *err, uf_status code, const char *fmt, long long a = 0,
+               long long b = 0)
+{
+    char buf[256];
+    std::snprintf(buf, sizeof buf, fmt, a, b);
+    if (err) *err = buf;
+    return code;
+}
+}  // namespace
+
+uf_status validate_and_prepare(const uf_tree *tree, const uf_table *table, HostPrep *hp,
+                               std::string *err)
+{
+    if (!tree || !table) return fail(err, UF_E_ARG, "tree and table must not be NULL");
+    const int32_t N = tree->n_nodes;
+    if (N < 1) return fail(err, UF_E_ARG, "n_nodes must be >= 1 (got %lld)", N);
+    if (!tree->parent || !tree->length)
+        return fail(err, UF_E_ARG, "tree parent/length must not be NULL");
+    const int32_t n = table->n_samples;
+    if (n < 1) return fail(err, UF_E_ARG, "n_samples must be >= 1 (got %lld)", n);
+    if (table->n_features < 0) return fail(err, UF_E_ARG, "n_features must be >= 0");
+    if (!table->indptr) return fail(err, UF_E_ARG, "table indptr must not be NULL");
+
+    // ---- tree: one root, parents in range, finite non-negative lengths
+    const int32_t *par = tree->parent;
+    int32_t root = -1;
+    for (int32_t v = 0; v < N; ++v) {
+        int32_t p = par[v];
+        if (p == -1) {
+            if (root >= 0) return fail(err, UF_E_TREE, "two roots: nodes %lld and %lld", root, v);
+            root = v;
+        } else if (p < 0 || p >= N) {
+            return fail(err, UF_E_TREE, "parent[%lld] = %lld out of range", v, p);
+        } else if (p == v) {
+            return fail(err, UF_E_TREE, "node %lld is its own parent", v);
+        } else {
+            double L = tree->length[v];
+            if (!std::isfinite(L) || L < 0.0)
+                return fail(err, UF_E_TREE, "length of node %lld is negative or not finite", v);
+        }
+    }
+    if (root < 0) return fail(err, UF_E_TREE, "no root (no parent == -1)");
+
+    // children CSR in node-id order
+    std::vector<int32_t> cptr(N + 1, 0), cidx(N > 0 ? N - 1 : 0);
+    for (int32_t v = 0; v < N; ++v)
+        if (par[v] >= 0) cptr[par[v] + 1]++;
+    for (int32_t v = 0; v < N; ++v) cptr[v + 1] += cptr[v];
+    {
+        std::vector<int32_t> fillp(cptr.begin(), cptr.end() - 1);
+        for (int32_t v = 0; v < N; ++v)
+            if (par[v] >= 0) cidx[fillp[par[v]]++] = v;
+    }
+    // breadth-first order from the root; a node not reached sits on a cycle
+    std::vector<int32_t> order;
+    order.reserve(N);
+    order.push_back(root);
+    for (size_t h = 0; h < order.size(); ++h) {
+        int32_t v = order[h];
+        for (int32_t q = cptr[v]; q < cptr[v + 1]; ++q) order.push_back(cidx[q]);
+    }
+    if ((int32_t)order.size() != N)
+        return fail(err, UF_E_TREE, "%lld nodes do not reach the root (cycle)", N - (long long)order.size());
+
+    // heights, children before parents in reverse BFS order
+    std::vector<int32_t> height(N, 0);
+    for (int32_t h = N - 1; h >= 0; --h) {
+        int32_t v = order[h];
+        int32_t p = par[v];
+        if (p >= 0 && height[p] < height[v] + 1) height[p] = height[v] + 1;
+    }
+    const int32_t n_levels = height[root] + 1;
+
+    // ---- table: CSR structure, feature ids, leaf mapping, totals
+    const int64_t *ip = table->indptr;
+    if (ip[0] != 0) return fail(err, UF_E_TABLE, "indptr[0] must be 0 (got %lld)", ip[0]);
+    for (int32_t k = 0; k < n; ++k)
+        if (ip[k + 1] < ip[k]) return fail(err, UF_E_TABLE, "indptr decreases at row %lld", k);
+    const int64_t nnz = ip[n];
+    if (nnz > 0 && (!table->indices || !table->counts))
+        return fail(err, UF_E_ARG, "table indices/counts must not be NULL");
+    if (nnz > (int64_t)std::numeric_limits<int32_t>::max() * 8)
+        return fail(err, UF_E_TABLE, "too many entries (%lld)", nnz);
+    const int32_t F = table->n_features;
+    const int32_t *fnode = table->feature_node;
+    if (!fnode && F > N)
+        return fail(err, UF_E_TABLE, "feature_node is NULL but n_features %lld > n_nodes %lld", F, N);
+    if (fnode)
+        for (int32_t f = 0; f < F; ++f)
+            if (fnode[f] < 0 || fnode[f] >= N)
+                return fail(err, UF_E_TABLE, "feature_node[%lld] = %lld out of range", f, fnode[f]);
+
+    // ---- slots by (height, id)
+    hp->n_nodes = N;
+    hp->n_samples = n;
+    hp->n_features = F;
+    hp->root = root;
+    hp->n_levels = n_levels;
+    hp->nnz = nnz;
+    hp->level_ptr.assign(n_levels + 1, 0);
+    for (int32_t v = 0; v < N; ++v) hp->level_ptr[height[v] + 1]++;
+    for (int32_t h = 0; h < n_levels; ++h) hp->level_ptr[h + 1] += hp->level_ptr[h];
+    hp->n_leaf = hp->level_ptr[1];
+    hp->slot_of_node.assign(N, 0);
+    hp->node_of_slot.assign(N, 0);
+    {
+        std::vector<int32_t> next(hp->level_ptr.begin(), hp->level_ptr.end() - 1);
+        for (int32_t v = 0; v < N; ++v) {
+            int32_t s = next[height[v]]++;
+            hp->slot_of_node[v] = s;
+            hp->node_of_slot[s] = v;
+        }
+    }
+    const int32_t n_int = N - hp->n_leaf;
+    hp->child_ptr.assign(n_int + 1, 0);
+    hp->child_slot.clear();
+    hp->child_slot.reserve(N > 0 ? N - 1 : 0);
+    for (int32_t s = hp->n_leaf; s < N; ++s) {
+        int32_t v = hp->node_of_slot[s];
+        for (int32_t q = cptr[v]; q < cptr[v + 1]; ++q)
+            hp->child_slot.push_back(hp->slot_of_node[cidx[q]]);
+        hp->child_ptr[s - hp->n_leaf + 1] = (int32_t)hp->child_slot.size();
+    }
+    hp->length_slot.assign(N, 0.0);
+    for (int32_t v = 0; v < N; ++v)
+        if (v != root) hp->length_slot[hp->slot_of_node[v]] = tree->length[v];
+
+    hp->indptr.assign(ip, ip + n + 1);
+    hp->entry_slot.resize(nnz);
+    hp->entry_count.resize(nnz);
+    hp->totals.assign(n, 0);
+    for (int32_t k = 0; k < n; ++k) {
+        int64_t tot = 0;
+        for (int64_t e = ip[k]; e < ip[k + 1]; ++e) {
+            int32_t f = table->indices[e];
+            if (f < 0 || f >= F)
+                return fail(err, UF_E_TABLE, "feature id %lld out of range in row %lld", f, k);
+            int32_t c = table->counts[e];
+            if (c < 0) return fail(err, UF_E_TABLE, "negative count in row %lld entry %lld", k, e);
+            int32_t v = fnode ? fnode[f] : f;
+            if (cptr[v + 1] != cptr[v])
+                return fail(err, UF_E_TABLE, "feature %lld sits on internal node %lld", f, v);
+            hp->entry_slot[e] = hp->slot_of_node[v];
+            hp->entry_count[e] = c;
+            tot += c;
+        }
+        if (tot == 0) return fail(err, UF_E_EMPTY_SAMPLE, "sample %lld has no reads", k);
+        if (tot > std::numeric_limits<int32_t>::max())
+            return fail(err, UF_E_TABLE, "sample %lld total %lld exceeds int32", k, tot);
+        hp->totals[k] = (int32_t)tot;
+    }
+    return UF_OK;
+}
+
+}  // namespace ufmi

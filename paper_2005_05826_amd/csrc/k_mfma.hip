@@ -1,0 +1,339 @@
+// (c) Matrix-core form of unweighted UniFrac.
+//
+// For 0/1 presence P (samples x branches) and branch lengths L, the branch length shared by
+// samples i and j is S_ij = sum_b L_b P_ib P_jb, the entries of P diag(L) P^T; the length
+// observed in sample i alone is T_i = S_ii.  Then
+//   unique(i, j)   = T_i + T_j - 2 S_ij         (numerator: length seen in exactly one)
+//   observed(i, j) = T_i + T_j -   S_ij         (denominator: length seen in either)
+// so the pairwise work is one symmetric product, run on bf16 MFMA.  Each length is split
+// into two bf16 terms, hi = bf16(L) and lo = bf16(L - hi) (the subtraction is exact in
+// FP32), so S = P diag(hi) P^T + P diag(lo) P^T with 0/1 operands exact in bf16.  Products
+// accumulate in FP32 inside chunks of k_chunk branches and are flushed into FP64 registers
+// between chunks; the final division is FP64.
+//
+// Layout: presence is stored once per sample as one byte per branch (0x00 or 0xFF),
+// [n_pad][k_pad].  A byte pair becomes a pair of 16-bit masks with one byte permute, and a
+// mask ANDed with the bf16 pattern of hi, lo or 1.0 is exactly the MFMA operand, so
+// operand construction costs two VALU ops per 32-bit register.
+#include "uf_internal.h"
+
+namespace ufmi {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int GM = 128;            // work-group tile: GM x GM outputs, 4 waves of 64 x 64
+constexpr int GK = 64;             // branches per LDS stage
+constexpr int LDK = GK + 8;        // padded LDS row (bytes)
+constexpr uint32_t kOne2 = 0x3F803F80u;  // two bf16 1.0
+
+// round-to-nearest-even FP32 -> bf16 (finite, non-negative inputs)
+__device__ inline uint16_t bf16_rne(float x)
+{
+    const uint32_t u = __float_as_uint(x);
+    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+__global__ void k_split_lengths(const double *__restrict__ len, int32_t B, int32_t k_pad,
+                                uint16_t *__restrict__ hi, uint16_t *__restrict__ lo)
+{
+    const int32_t b = blockIdx.x * 256 + threadIdx.x;
+    if (b >= k_pad) return;
+    uint16_t h = 0, l = 0;
+    if (b < B) {
+        const float L32 = (float)len[b];
+        h = bf16_rne(L32);
+        const float rest = L32 - __uint_as_float((uint32_t)h << 16);
+        l = bf16_rne(rest < 0.f ? -rest : rest);
+        if (rest < 0.f) l |= 0x8000u;
+    }
+    hi[b] = h;
+    lo[b] = l;
+}
+
+// Presence bits [slot][bstride] (bit k%32 of word k/32 = sample k) -> bytes
+// P[k][b] (0xFF if sample k has a read below branch slot b), one 256-sample x 64-branch
+// tile per work-group, transposed through LDS.
+__global__ void k_bits_to_bytes(const uint32_t *__restrict__ bits, int64_t bstride, int32_t B,
+                                int32_t n_pad, int64_t k_pad, uint8_t *__restrict__ P)
+{
+    __shared__ uint32_t w[64][8];
+    const int32_t b0 = blockIdx.x * 64;
+    const int32_t k0 = blockIdx.y * 256;
+    const int tid = threadIdx.x;
+    {   // 64 branch rows x 8 words
+        const int r = tid >> 2, c = (tid & 3) * 2;
+        const int32_t b = b0 + r;
+        for (int q = 0; q < 2; ++q) {
+            const int64_t word = k0 / 32 + c + q;
+            w[r][c + q] = (b < B && word < bstride) ? bits[(int64_t)b * bstride + word] : 0u;
+        }
+    }
+    __syncthreads();
+    const int32_t k = k0 + tid;
+    if (k >= n_pad) return;
+    const uint32_t sh = tid & 31, wc = tid >> 5;
+    uint32_t out[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        uint32_t v = 0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) v |= (((w[q * 4 + t][wc] >> sh) & 1u) * 0xFFu) << (8 * t);
+        out[q] = v;
+    }
+    uint4 *dst = reinterpret_cast<uint4 *>(P + (int64_t)k * k_pad + b0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dst[q] = make_uint4(out[4 * q], out[4 * q + 1], out[4 * q + 2], out[4 * q + 3]);
+}
+
+__device__ inline bf16x8 as_bf16x8(uint32_t a, uint32_t b, uint32_t c, uint32_t d)
+{
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    u32x4 v = {a, b, c, d};
+    return __builtin_bit_cast(bf16x8, v);
+}
+
+// Upper-triangular tiles of S = P diag(hi + lo) P^T.  Tile t covers rows tiles[t].x*GM ..
+// and columns tiles[t].y*GM .. (x <= y).  Work-group b takes tile (b % 8) * per + b / 8, so
+// the 8 XCDs (which receive work-groups round-robin) each sweep a contiguous run of tiles
+// that share A panels in their L2.  Writes S_ij (i < j) into the condensed array and S_ii
+// into T.
+__global__ __launch_bounds__(256, 1) void k_mfma_gemm(
+    const uint8_t *__restrict__ P, int64_t k_pad, int32_t n_kstep,
+    const uint16_t *__restrict__ hi, const uint16_t *__restrict__ lo, int32_t chunk_steps,
+    const int2 *__restrict__ tiles, int32_t n_tiles, int32_t n, double *__restrict__ S,
+    double *__restrict__ T)
+{
+    // two LDS stages: the next stage's global loads are in flight while this one computes
+    __shared__ __align__(16) uint8_t sA[2][GM * LDK];
+    __shared__ __align__(16) uint8_t sB[2][GM * LDK];
+    __shared__ __align__(16) uint16_t sh[2][GK];
+    __shared__ __align__(16) uint16_t sl[2][GK];
+
+    const int32_t per = (n_tiles + 7) / 8;
+    const int32_t t = (int32_t)(blockIdx.x % 8) * per + (int32_t)(blockIdx.x / 8);
+    if (t >= n_tiles) return;
+    const int2 tile = tiles[t];
+    const int32_t row0 = tile.x * GM, col0 = tile.y * GM;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = tid >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    const int lrow = lane & 31;
+    const int kg = lane >> 5;
+
+    f32x16 acc[2][2];
+    double acc64[2][2][16];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                acc[a][b][r] = 0.f;
+                acc64[a][b][r] = 0.0;
+            }
+        }
+
+    // each thread stages 32 bytes of one A row and one B row, and (64 threads) one dword
+    // of the hi or lo splits
+    const uint8_t *pa = P + (int64_t)(row0 + (tid >> 1)) * k_pad + (tid & 1) * 32;
+    const uint8_t *pb = P + (int64_t)(col0 + (tid >> 1)) * k_pad + (tid & 1) * 32;
+    const int soff = (tid >> 1) * LDK + (tid & 1) * 32;
+    uint4 ra0, ra1, rb0, rb1;
+    uint32_t rhl = 0;
+    auto gload = [&](int32_t ks) {
+        const int64_t k0 = (int64_t)ks * GK;
+        ra0 = *reinterpret_cast<const uint4 *>(pa + k0);
+        ra1 = *reinterpret_cast<const uint4 *>(pa + k0 + 16);
+        rb0 = *reinterpret_cast<const uint4 *>(pb + k0);
+        rb1 = *reinterpret_cast<const uint4 *>(pb + k0 + 16);
+        if (tid < 32)
+            rhl = reinterpret_cast<const uint32_t *>(hi + k0)[tid];
+        else if (tid < 64)
+            rhl = reinterpret_cast<const uint32_t *>(lo + k0)[tid - 32];
+    };
+    auto lstore = [&](int buf) {
+        uint2 *da = reinterpret_cast<uint2 *>(sA[buf] + soff);
+        uint2 *db = reinterpret_cast<uint2 *>(sB[buf] + soff);
+        da[0] = make_uint2(ra0.x, ra0.y); da[1] = make_uint2(ra0.z, ra0.w);
+        da[2] = make_uint2(ra1.x, ra1.y); da[3] = make_uint2(ra1.z, ra1.w);
+        db[0] = make_uint2(rb0.x, rb0.y); db[1] = make_uint2(rb0.z, rb0.w);
+        db[2] = make_uint2(rb1.x, rb1.y); db[3] = make_uint2(rb1.z, rb1.w);
+        if (tid < 32)
+            reinterpret_cast<uint32_t *>(sh[buf])[tid] = rhl;
+        else if (tid < 64)
+            reinterpret_cast<uint32_t *>(sl[buf])[tid - 32] = rhl;
+    };
+
+    if (n_kstep > 0) {
+        gload(0);
+        lstore(0);
+    }
+    __syncthreads();
+    for (int32_t ks = 0; ks < n_kstep; ++ks) {
+        const int buf = ks & 1;
+        const bool more = ks + 1 < n_kstep;
+        if (more) gload(ks + 1);
+        const uint8_t *cA = sA[buf];
+        const uint8_t *cB = sB[buf];
+#pragma unroll
+        for (int kk = 0; kk < GK / 16; ++kk) {
+            const int koff = kk * 16 + kg * 8;
+            const uint4 h = *reinterpret_cast<const uint4 *>(sh[buf] + koff);
+            const uint4 l = *reinterpret_cast<const uint4 *>(sl[buf] + koff);
+            bf16x8 ahi[2], alo[2], bo[2];
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb) {
+                const uint2 m = *reinterpret_cast<const uint2 *>(cA + (wm * 64 + mb * 32 + lrow) * LDK + koff);
+                const uint32_t m0 = __builtin_amdgcn_perm(m.x, m.x, 0x01010000u);
+                const uint32_t m1 = __builtin_amdgcn_perm(m.x, m.x, 0x03030202u);
+                const uint32_t m2 = __builtin_amdgcn_perm(m.y, m.y, 0x01010000u);
+                const uint32_t m3 = __builtin_amdgcn_perm(m.y, m.y, 0x03030202u);
+                ahi[mb] = as_bf16x8(m0 & h.x, m1 & h.y, m2 & h.z, m3 & h.w);
+                alo[mb] = as_bf16x8(m0 & l.x, m1 & l.y, m2 & l.z, m3 & l.w);
+            }
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) {
+                const uint2 m = *reinterpret_cast<const uint2 *>(cB + (wn * 64 + nb * 32 + lrow) * LDK + koff);
+                bo[nb] = as_bf16x8(__builtin_amdgcn_perm(m.x, m.x, 0x01010000u) & kOne2,
+                                   __builtin_amdgcn_perm(m.x, m.x, 0x03030202u) & kOne2,
+                                   __builtin_amdgcn_perm(m.y, m.y, 0x01010000u) & kOne2,
+                                   __builtin_amdgcn_perm(m.y, m.y, 0x03030202u) & kOne2);
+            }
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                for (int nb = 0; nb < 2; ++nb) {
+                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[mb], bo[nb], acc[mb][nb], 0, 0, 0);
+                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo[mb], bo[nb], acc[mb][nb], 0, 0, 0);
+                }
+        }
+        if ((ks + 1) % chunk_steps == 0 || !more) {
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        acc64[a][b][r] += (double)acc[a][b][r];
+                        acc[a][b][r] = 0.f;
+                    }
+        }
+        if (more) lstore(buf ^ 1);
+        __syncthreads();
+    }
+
+    // 32x32 accumulator layout: lane l, register r holds row 8*(r/4) + 4*(l/32) + r%4 and
+    // column l%32 of the block.
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int32_t i = row0 + wm * 64 + mb * 32 + 8 * (r >> 2) + 4 * kg + (r & 3);
+                const int32_t j = col0 + wn * 64 + nb * 32 + lrow;
+                if (i < n && j < n) {
+                    if (i < j)
+                        S[(int64_t)n * i - (int64_t)i * (i + 1) / 2 + (j - i - 1)] = acc64[mb][nb][r];
+                    else if (i == j)
+                        T[i] = acc64[mb][nb][r];
+                }
+            }
+}
+
+// d_ij = (T_i + T_j - 2 S_ij) / (T_i + T_j - S_ij), 0 when the denominator is 0.
+// S may alias out (FP64 output): each element is read before it is written by one thread.
+template <typename OUT>
+__global__ void k_mfma_normalize(const double *S, const double *__restrict__ T, int32_t n,
+                                 OUT *out)
+{
+    const int32_t i = blockIdx.x;
+    const int64_t row0 = (int64_t)n * i - (int64_t)i * (i + 1) / 2 - i - 1;
+    const double ti = T[i];
+    for (int32_t j = i + 1 + threadIdx.x; j < n; j += 256) {
+        const double s = S[row0 + j];
+        const double tt = ti + T[j];
+        const double u = tt - s;
+        const double d = (u == 0.0) ? 0.0 : (tt - 2.0 * s) / u;
+        out[row0 + j] = (OUT)d;
+    }
+}
+
+inline unsigned grid1(int64_t n, int64_t per) { return (unsigned)((n + per - 1) / per); }
+
+}  // namespace
+
+MfmaGeom mfma_geometry(int32_t n, int32_t n_branches)
+{
+    MfmaGeom g;
+    g.n = n;
+    g.B = n_branches;
+    g.n_pad = (int32_t)((n + 255) / 256 * 256);
+    g.k_pad = (int64_t)(n_branches + GK - 1) / GK * GK;
+    g.tile = GM;
+    g.kstep = GK;
+    const int32_t nb = (n + GM - 1) / GM;
+    g.n_tiles = nb * (nb + 1) / 2;
+    return g;
+}
+
+void mfma_tile_list(int32_t n, std::vector<int32_t> *xy)
+{
+    const int32_t nb = (n + GM - 1) / GM;
+    xy->clear();
+    xy->reserve((size_t)nb * (nb + 1));
+    for (int32_t I = 0; I < nb; ++I)
+        for (int32_t J = I; J < nb; ++J) {
+            xy->push_back(I);
+            xy->push_back(J);
+        }
+}
+
+hipError_t launch_split_lengths(const double *len, int32_t B, int64_t k_pad, uint16_t *hi,
+                                uint16_t *lo, hipStream_t st)
+{
+    if (k_pad <= 0) return hipSuccess;
+    k_split_lengths<<<grid1(k_pad, 256), 256, 0, st>>>(len, B, (int32_t)k_pad, hi, lo);
+    return hipGetLastError();
+}
+
+hipError_t launch_bits_to_bytes(const uint32_t *bits, int64_t bstride, const MfmaGeom &g,
+                                uint8_t *P, hipStream_t st)
+{
+    if (g.k_pad <= 0) return hipSuccess;
+    dim3 grid((unsigned)(g.k_pad / 64), (unsigned)(g.n_pad / 256));
+    k_bits_to_bytes<<<grid, 256, 0, st>>>(bits, bstride, g.B, g.n_pad, g.k_pad, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_mfma_gemm(const uint8_t *P, const uint16_t *hi, const uint16_t *lo,
+                            int32_t k_chunk, const int32_t *tiles_xy, const MfmaGeom &g,
+                            double *S, double *T, hipStream_t st)
+{
+    const int32_t n_kstep = (int32_t)(g.k_pad / GK);
+    int32_t chunk_steps = k_chunk / GK;
+    if (chunk_steps < 1) chunk_steps = 1;
+    const int32_t per = (g.n_tiles + 7) / 8;
+    k_mfma_gemm<<<(unsigned)(8 * per), 256, 0, st>>>(P, g.k_pad, n_kstep, hi, lo, chunk_steps,
+                                                     reinterpret_cast<const int2 *>(tiles_xy),
+                                                     g.n_tiles, g.n, S, T);
+    return hipGetLastError();
+}
+
+hipError_t launch_mfma_normalize(const double *S, const double *T, int32_t n, int32_t out_f32,
+                                 void *out, hipStream_t st)
+{
+    if (n < 2) return hipSuccess;
+    if (out_f32)
+        k_mfma_normalize<float><<<n - 1, 256, 0, st>>>(S, T, n, (float *)out);
+    else
+        k_mfma_normalize<double><<<n - 1, 256, 0, st>>>(S, T, n, (double *)out);
+    return hipGetLastError();
+}
+
+}  // namespace ufmi

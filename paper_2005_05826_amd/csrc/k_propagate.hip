@@ -1,0 +1,163 @@
+// (a) Level-synchronous embedding propagation.
+//
+// The paper's kernels consume one input buffer per branch, an embedding of how much of
+// every sample sits below that branch, produced by a CPU section (Section 3).  Here the
+// embeddings are built on the GPU: tip rows are scattered from the CSR table, then every
+// height level of the tree is one launch in which each internal node gathers the sum of
+// its children's rows.  Children always live in lower levels, so each level only reads
+// finished rows and writes its own: no atomics between levels and a deterministic result.
+// Rows are sample-contiguous, so every gather is a coalesced 16-byte-per-lane stream.
+#include "uf_internal.h"
+
+namespace ufmi {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__global__ void k_fill_u32(uint32_t *__restrict__ p, uint32_t value, size_t n)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = value;
+}
+
+// One wave per sample; its lanes stride over the sample's CSR entries.  Duplicate
+// features in a row land on the same element, hence the (exact, integer) atomic add.
+__global__ void k_scatter_counts(const int64_t *__restrict__ indptr,
+                                 const int32_t *__restrict__ entry_slot,
+                                 const int32_t *__restrict__ entry_count,
+                                 int32_t *__restrict__ C, int64_t cstride, int32_t n_samples)
+{
+    const int32_t k = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (k >= n_samples) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t e1 = indptr[k + 1];
+    for (int64_t e = indptr[k] + lane; e < e1; e += 64)
+        atomicAdd(C + (int64_t)entry_slot[e] * cstride + k, entry_count[e]);
+}
+
+__global__ void k_scatter_bits(const int64_t *__restrict__ indptr,
+                               const int32_t *__restrict__ entry_slot,
+                               const int32_t *__restrict__ entry_count,
+                               uint32_t *__restrict__ B, int64_t bstride, int32_t n_samples)
+{
+    const int32_t k = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (k >= n_samples) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t e1 = indptr[k + 1];
+    const uint32_t bit = 1u << (k & 31);
+    for (int64_t e = indptr[k] + lane; e < e1; e += 64)
+        if (entry_count[e] > 0)
+            atomicOr(B + (int64_t)entry_slot[e] * bstride + (k >> 5), bit);
+}
+
+// Rows [slot_begin, slot_begin + n_rows) are the internal nodes of one height level.
+// blockIdx.x walks 16-byte columns of a row, blockIdx.y (strided) walks the rows.
+template <bool OR>
+__global__ void k_level(uint32_t *__restrict__ X, int64_t stride, int32_t n_vec,
+                        int32_t slot_begin, int32_t n_rows, int32_t n_leaf,
+                        const int32_t *__restrict__ child_ptr,
+                        const int32_t *__restrict__ child_slot)
+{
+    const int32_t c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= n_vec) return;
+    for (int32_t r = blockIdx.y; r < n_rows; r += gridDim.y) {
+        const int32_t slot = slot_begin + r;
+        const int32_t i = slot - n_leaf;
+        const int32_t q0 = child_ptr[i], q1 = child_ptr[i + 1];
+        uint4 acc = make_uint4(0u, 0u, 0u, 0u);
+        for (int32_t q = q0; q < q1; ++q) {
+            const uint4 v = reinterpret_cast<const uint4 *>(X + (int64_t)child_slot[q] * stride)[c];
+            if (OR) {
+                acc.x |= v.x; acc.y |= v.y; acc.z |= v.z; acc.w |= v.w;
+            } else {
+                acc.x += v.x; acc.y += v.y; acc.z += v.z; acc.w += v.w;
+            }
+        }
+        reinterpret_cast<uint4 *>(X + (int64_t)slot * stride)[c] = acc;
+    }
+}
+
+__global__ void k_gather_rows(const uint32_t *__restrict__ src, int64_t sstride,
+                              const int32_t *__restrict__ slot_of_node, int32_t n_nodes,
+                              int32_t width, uint32_t *__restrict__ out)
+{
+    const int32_t x = blockIdx.x * kBlock + threadIdx.x;
+    if (x >= width) return;
+    for (int32_t v = blockIdx.y; v < n_nodes; v += gridDim.y)
+        out[(int64_t)v * width + x] = src[(int64_t)slot_of_node[v] * sstride + x];
+}
+
+inline unsigned grid1(size_t n, size_t per) { return (unsigned)((n + per - 1) / per); }
+
+}  // namespace
+
+hipError_t launch_fill_u32(void *p, uint32_t value, size_t n_words, hipStream_t st)
+{
+    if (n_words == 0) return hipSuccess;
+    size_t blocks = grid1(n_words, kBlock * 8);
+    if (blocks > 65536) blocks = 65536;
+    k_fill_u32<<<(unsigned)blocks, kBlock, 0, st>>>((uint32_t *)p, value, n_words);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_counts(const int64_t *indptr, const int32_t *entry_slot,
+                                 const int32_t *entry_count, int32_t *C, int64_t cstride,
+                                 int32_t n_samples, hipStream_t st)
+{
+    k_scatter_counts<<<grid1(n_samples, kBlock / 64), kBlock, 0, st>>>(
+        indptr, entry_slot, entry_count, C, cstride, n_samples);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_bits(const int64_t *indptr, const int32_t *entry_slot,
+                               const int32_t *entry_count, uint32_t *B, int64_t bstride,
+                               int32_t n_samples, hipStream_t st)
+{
+    k_scatter_bits<<<grid1(n_samples, kBlock / 64), kBlock, 0, st>>>(
+        indptr, entry_slot, entry_count, B, bstride, n_samples);
+    return hipGetLastError();
+}
+
+static hipError_t launch_level(bool is_or, uint32_t *X, int64_t stride, int32_t slot_begin,
+                               int32_t n_rows, int32_t n_leaf, const int32_t *child_ptr,
+                               const int32_t *child_slot, hipStream_t st)
+{
+    if (n_rows <= 0) return hipSuccess;
+    const int32_t n_vec = (int32_t)(stride / 4);
+    dim3 grid(grid1(n_vec, kBlock), (unsigned)(n_rows < 65535 ? n_rows : 65535));
+    if (is_or)
+        k_level<true><<<grid, kBlock, 0, st>>>(X, stride, n_vec, slot_begin, n_rows, n_leaf,
+                                               child_ptr, child_slot);
+    else
+        k_level<false><<<grid, kBlock, 0, st>>>(X, stride, n_vec, slot_begin, n_rows, n_leaf,
+                                                child_ptr, child_slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_level_sum(int32_t *C, int64_t cstride, int32_t slot_begin, int32_t n_rows,
+                            int32_t n_leaf, const int32_t *child_ptr, const int32_t *child_slot,
+                            hipStream_t st)
+{
+    return launch_level(false, reinterpret_cast<uint32_t *>(C), cstride, slot_begin, n_rows,
+                        n_leaf, child_ptr, child_slot, st);
+}
+
+hipError_t launch_level_or(uint32_t *B, int64_t bstride, int32_t slot_begin, int32_t n_rows,
+                           int32_t n_leaf, const int32_t *child_ptr, const int32_t *child_slot,
+                           hipStream_t st)
+{
+    return launch_level(true, B, bstride, slot_begin, n_rows, n_leaf, child_ptr, child_slot, st);
+}
+
+hipError_t launch_gather_rows_u32(const uint32_t *src, int64_t sstride, const int32_t *slot_of_node,
+                                  int32_t n_nodes, int32_t width, uint32_t *out, hipStream_t st)
+{
+    if (n_nodes <= 0 || width <= 0) return hipSuccess;
+    dim3 grid(grid1(width, kBlock), (unsigned)(n_nodes < 65535 ? n_nodes : 65535));
+    k_gather_rows<<<grid, kBlock, 0, st>>>(src, sstride, slot_of_node, n_nodes, width, out);
+    return hipGetLastError();
+}
+
+}  // namespace ufmi

@@ -1,0 +1,107 @@
+// Internal declarations shared by the host runtime and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "unifrac_mi.h"
+
+namespace ufmi {
+
+// ------------------------------------------------------------------ host preprocessing
+
+// Node slots: nodes are renumbered by height (0 = leaf, else 1 + max child height), ties
+// by node id.  Leaves occupy slots [0, n_leaf); height level h occupies slots
+// [level_ptr[h], level_ptr[h+1]); the root is the last slot (it alone has the maximum
+// height).  Branch slots are [0, n_nodes - 1).
+struct HostPrep {
+    int32_t n_nodes = 0, n_samples = 0, n_features = 0;
+    int32_t root = -1, n_leaf = 0, n_levels = 0;
+    int64_t nnz = 0;
+    std::vector<int32_t> slot_of_node, node_of_slot;
+    std::vector<int32_t> level_ptr;          // n_levels + 1
+    std::vector<int32_t> child_ptr;          // per internal slot (slot - n_leaf), + 1
+    std::vector<int32_t> child_slot;
+    std::vector<double> length_slot;         // branch length per slot; 0 at the root slot
+    std::vector<int64_t> indptr;             // n_samples + 1
+    std::vector<int32_t> entry_slot;         // leaf slot of every CSR entry
+    std::vector<int32_t> entry_count;
+    std::vector<int32_t> totals;             // per-sample total reads (> 0, fits int32)
+};
+
+uf_status validate_and_prepare(const uf_tree *tree, const uf_table *table, HostPrep *hp,
+                               std::string *err);
+
+// ------------------------------------------------------------------ device launches
+
+// All launches are asynchronous on `st` and return the launch status.
+hipError_t launch_fill_u32(void *p, uint32_t value, size_t n_words, hipStream_t st);
+
+// Embedding propagation (count form): C is [n_nodes][cstride] int32 in slot order.
+hipError_t launch_scatter_counts(const int64_t *indptr, const int32_t *entry_slot,
+                                 const int32_t *entry_count, int32_t *C, int64_t cstride,
+                                 int32_t n_samples, hipStream_t st);
+hipError_t launch_level_sum(int32_t *C, int64_t cstride, int32_t slot_begin, int32_t n_rows,
+                            int32_t n_leaf, const int32_t *child_ptr, const int32_t *child_slot,
+                            hipStream_t st);
+// Presence form: B is [n_nodes][bstride] uint32, bit k%32 of word k/32.
+hipError_t launch_scatter_bits(const int64_t *indptr, const int32_t *entry_slot,
+                               const int32_t *entry_count, uint32_t *B, int64_t bstride,
+                               int32_t n_samples, hipStream_t st);
+hipError_t launch_level_or(uint32_t *B, int64_t bstride, int32_t slot_begin, int32_t n_rows,
+                           int32_t n_leaf, const int32_t *child_ptr, const int32_t *child_slot,
+                           hipStream_t st);
+// out[v][0..width) = src[slot_of_node[v]][0..width), for node-ordered output.
+hipError_t launch_gather_rows_u32(const uint32_t *src, int64_t sstride, const int32_t *slot_of_node,
+                                  int32_t n_nodes, int32_t width, uint32_t *out, hipStream_t st);
+
+// Striped path.  Embedding rows: emb[e][x], x in [0, estride); x < n + S holds the sample
+// x mod n (the wrap copy lets k + s + 1 run past n without a modulo); the rest is zero.
+struct StripeGeom {
+    int32_t n, S;            // samples, stripes
+    int32_t tkw, tsw;        // work-group tile: samples x stripes
+    int64_t sstride;         // row stride of num/den (multiple of tkw)
+    int32_t spad;            // stripes rounded up to tsw
+    int64_t estride;         // embedding row stride
+};
+StripeGeom stripe_geometry(int32_t n, bool fp64);
+
+hipError_t launch_transform(bool fp64, int32_t method, const int32_t *C, int64_t cstride,
+                            int32_t slot0, int32_t E, const int32_t *totals, int32_t n, int32_t S,
+                            void *emb, int64_t estride, hipStream_t st);
+hipError_t launch_stripe(bool fp64, int32_t method, int32_t den_mode, const void *emb,
+                         int64_t estride, const double *len, int32_t E, double *num, double *den,
+                         const StripeGeom &g, bool first, hipStream_t st);
+// Per-sample sums D_k = sum_b L_b u_kb over a batch (separable denominator).
+hipError_t launch_rowdot(int32_t method, const int32_t *C, int64_t cstride, int32_t slot0,
+                         int32_t E, const int32_t *totals, const double *len, int32_t n,
+                         double *D, bool first, hipStream_t st);
+hipError_t launch_condense(int32_t method, const double *num, const double *den, const double *D,
+                           int64_t sstride, int32_t n, int32_t S, int32_t out_f32, void *out,
+                           hipStream_t st);
+
+// Matrix-core path (unweighted).  Presence bytes P[n_pad][k_pad] (0x00 / 0xFF per branch
+// slot), bf16 length splits hi/lo[k_pad], upper-triangular GM x GM output tiles.
+struct MfmaGeom {
+    int32_t n, B;
+    int32_t n_pad;      // samples rounded up to 256
+    int64_t k_pad;      // branches rounded up to the K stage (64)
+    int32_t tile, kstep;
+    int32_t n_tiles;    // upper-triangular tiles including the diagonal
+};
+MfmaGeom mfma_geometry(int32_t n, int32_t n_branches);
+void mfma_tile_list(int32_t n, std::vector<int32_t> *xy);   // (I, J) pairs, I <= J
+hipError_t launch_split_lengths(const double *len, int32_t B, int64_t k_pad, uint16_t *hi,
+                                uint16_t *lo, hipStream_t st);
+hipError_t launch_bits_to_bytes(const uint32_t *bits, int64_t bstride, const MfmaGeom &g,
+                                uint8_t *P, hipStream_t st);
+hipError_t launch_mfma_gemm(const uint8_t *P, const uint16_t *hi, const uint16_t *lo,
+                            int32_t k_chunk, const int32_t *tiles_xy, const MfmaGeom &g,
+                            double *S, double *T, hipStream_t st);
+hipError_t launch_mfma_normalize(const double *S, const double *T, int32_t n, int32_t out_f32,
+                                 void *out, hipStream_t st);
+
+}  // namespace ufmi

@@ -1,0 +1,158 @@
+"""CPU-side checks of the C ABI: the library loads, exports every declared entry point,
+and rejects malformed inputs with the documented status codes (host-only validation, no
+device needed)."""
+from __future__ import annotations
+
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2005_05826_amd as uf
+from paper_2005_05826_amd import binding
+from synth import config_problem
+
+from helpers import tiny_problem
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "unifrac_mi.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(uf_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = uf.library()
+    declared = _declared_functions()
+    assert declared, "no declarations parsed"
+    for name in declared:
+        assert hasattr(lib, name), f"{name} declared in the header but not exported"
+    assert sorted(binding.EXPORTED) == declared
+
+
+def test_status_strings():
+    lib = uf.library()
+    for code, name in binding.STATUS_NAMES.items():
+        assert lib.uf_status_string(code).decode() == name
+
+
+def _prob():
+    return tiny_problem(7, max_nodes=12, max_samples=5)
+
+
+def _args(p, **over):
+    a = dict(parent=p.parent.copy(), length=p.length.copy(), indptr=p.indptr.copy(),
+             indices=p.indices.copy(), counts=p.counts.copy(), n_features=p.n_features,
+             feature_node=p.feature_node.copy())
+    a.update(over)
+    return a
+
+
+def _status(**kw):
+    st, msg = uf.validate(**kw)
+    return binding.STATUS_NAMES[st], msg
+
+
+def test_valid_inputs_pass():
+    p = _prob()
+    assert _status(**_args(p))[0] == "UF_OK"
+    assert uf.validate_problem(config_problem(1, n=16))[0] == 0
+
+
+def test_tree_errors():
+    p = _prob()
+    root = int(np.flatnonzero(p.parent < 0)[0])
+    other = (root + 1) % p.n_nodes
+    par = p.parent.copy()
+    par[other] = -1
+    assert _status(**_args(p, parent=par))[0] == "UF_E_TREE"           # two roots
+    par = p.parent.copy()
+    par[0] = p.n_nodes + 3
+    assert _status(**_args(p, parent=par))[0] == "UF_E_TREE"           # out of range
+    par = p.parent.copy()
+    par[root] = root
+    assert _status(**_args(p, parent=par))[0] == "UF_E_TREE"           # self parent, no root
+    # cycle: a -> b -> a, unreachable from the root
+    par = np.array([-1, 2, 1, 0], np.int32)
+    st, msg = _status(parent=par, length=np.ones(4), indptr=np.array([0, 1], np.int64),
+                      indices=np.array([0], np.int32), counts=np.array([1], np.int32),
+                      n_features=1, feature_node=np.array([3], np.int32))
+    assert st == "UF_E_TREE" and "cycle" in msg
+    for bad in (-0.5, np.nan, np.inf):
+        ln = p.length.copy()
+        ln[other] = bad
+        assert _status(**_args(p, length=ln))[0] == "UF_E_TREE"
+    ln = p.length.copy()
+    ln[root] = np.nan                                                  # root length ignored
+    assert _status(**_args(p, length=ln))[0] == "UF_OK"
+
+
+def test_table_errors():
+    p = _prob()
+    ip = p.indptr.copy()
+    ip[0] = 1
+    assert _status(**_args(p, indptr=ip))[0] == "UF_E_TABLE"
+    ip = p.indptr.copy()
+    ip[1], ip[2] = ip[2], ip[1] - 1 if ip[1] > 0 else 0
+    if np.any(np.diff(ip) < 0):
+        assert _status(**_args(p, indptr=ip))[0] == "UF_E_TABLE"
+    ind = p.indices.copy()
+    ind[0] = p.n_features
+    assert _status(**_args(p, indices=ind))[0] == "UF_E_TABLE"
+    ind[0] = -1
+    assert _status(**_args(p, indices=ind))[0] == "UF_E_TABLE"
+    cnt = p.counts.copy()
+    cnt[0] = -2
+    assert _status(**_args(p, counts=cnt))[0] == "UF_E_TABLE"
+    fn = p.feature_node.copy()
+    root = int(np.flatnonzero(p.parent < 0)[0])
+    fn[p.indices[0]] = root                                            # feature on internal node
+    if np.any(p.parent == root):
+        assert _status(**_args(p, feature_node=fn))[0] == "UF_E_TABLE"
+    fn = p.feature_node.copy()
+    fn[0] = p.n_nodes
+    assert _status(**_args(p, feature_node=fn))[0] == "UF_E_TABLE"
+    # a sample whose entries are all zero
+    cnt = p.counts.copy()
+    cnt[p.indptr[1]:p.indptr[2]] = 0
+    assert _status(**_args(p, counts=cnt))[0] == "UF_E_EMPTY_SAMPLE"
+    # a sample with no entries at all
+    ip = np.concatenate([p.indptr, [p.indptr[-1]]])
+    assert _status(**_args(p, indptr=ip))[0] == "UF_E_EMPTY_SAMPLE"
+    # total beyond int32
+    big = np.array([2**31 - 1, 5], np.int32)
+    st = _status(parent=np.array([2, 2, -1], np.int32), length=np.ones(3),
+                 indptr=np.array([0, 2], np.int64), indices=np.array([0, 1], np.int32),
+                 counts=big, n_features=2, feature_node=np.array([0, 1], np.int32))[0]
+    assert st == "UF_E_TABLE"
+
+
+def test_arg_errors():
+    p = _prob()
+    assert _status(**_args(p, indptr=np.array([0], np.int64), indices=np.zeros(0, np.int32),
+                           counts=np.zeros(0, np.int32)))[0] == "UF_E_ARG"   # no samples
+    lib = uf.library()
+    assert lib.uf_validate(None, None) == 1
+
+
+def test_duplicates_and_null_feature_node_accepted():
+    # feature f sits on node f when feature_node is NULL; duplicates in a row are summed
+    parent = np.array([2, 2, -1], np.int32)
+    st, _ = uf.validate(parent, np.array([1.0, 2.0, 0.0]), np.array([0, 3, 4], np.int64),
+                        np.array([1, 0, 1, 0], np.int32), np.array([1, 2, 3, 1], np.int32), 2)
+    assert st == 0
+
+
+def test_context_without_gpu_reports_device_error():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is present")
+    except ImportError:
+        pass
+    with pytest.raises(uf.UniFracError) as ei:
+        uf.Context(0)
+    assert ei.value.status_name == "UF_E_DEVICE"

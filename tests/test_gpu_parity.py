@@ -1,0 +1,262 @@
+"""GPU parity of the striped hot path against the FP64 CPU oracle, through the C ABI.
+
+Bars: embedding counts bit-exact; FP64 path within 1e-12 absolute; FP32 path within 1e-5
+absolute; dyadic inputs (exactly representable partial sums) bit-identical in both."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from oracle import oracle
+from synth import Problem, config_problem, make_rng
+
+from helpers import condensed_index, tiny_problem
+
+pytestmark = pytest.mark.gpu
+
+UW, WN = "unweighted", "weighted_normalized"
+OMETHOD = {UW: oracle.UNWEIGHTED, WN: oracle.WEIGHTED_NORMALIZED}
+TOL = {"fp64": 1e-12, "fp32": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def uf():
+    import paper_2005_05826_amd as uf
+    return uf
+
+
+@pytest.fixture(scope="module")
+def ctx(uf):
+    return uf.Context(0)
+
+
+def _plan(uf, ctx, prob):
+    return uf.Plan.from_problem(ctx, prob)
+
+
+def _report(tag, got, want):
+    err = np.abs(np.asarray(got, np.float64) - want)
+    print(f"[{tag}] n_pairs={want.size} max_abs_err={err.max() if err.size else 0:.3e} "
+          f"mean_abs_err={err.mean() if err.size else 0:.3e}", flush=True)
+    return err
+
+
+CASES = {
+    "tiny_a": lambda: tiny_problem(31, max_nodes=16, max_samples=6),
+    "tiny_b": lambda: tiny_problem(32, max_nodes=40, max_samples=9),
+    "cfg1": lambda: config_problem(1),
+    "cfg1_ragged_257": lambda: config_problem(1, n=257, seed=71),
+    "cfg2_shape_600": lambda: config_problem(2, n=600, tips=4000, k=300, depth=1500, seed=72),
+    "cfg2_shape_513": lambda: config_problem(2, n=513, tips=3000, k=200, depth=1000, seed=73),
+}
+
+
+@pytest.fixture(scope="module")
+def problems():
+    return {name: f() for name, f in CASES.items()}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_embedding_counts_bit_exact(uf, ctx, problems, case):
+    prob = problems[case]
+    plan = _plan(uf, ctx, prob)
+    got = plan.embedding_counts()
+    want = oracle.problem_counts(prob).T
+    assert got.shape == want.shape
+    np.testing.assert_array_equal(got.astype(np.int64), want)
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_presence_bits_bit_exact(uf, ctx, problems, case):
+    prob = problems[case]
+    plan = _plan(uf, ctx, prob)
+    got = plan.embedding_presence()
+    pres = oracle.problem_counts(prob).T > 0                  # [n_nodes][n]
+    n = prob.n_samples
+    words = (n + 31) // 32
+    padded = np.zeros((pres.shape[0], words * 32), bool)
+    padded[:, :n] = pres
+    # bit k % 32 of word k // 32
+    want = (padded.reshape(pres.shape[0], words, 32).astype(np.uint64)
+            << np.arange(32, dtype=np.uint64)).sum(-1)
+    np.testing.assert_array_equal(got.astype(np.uint64), want)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("method", [UW, WN])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_distance_matches_oracle(uf, ctx, problems, case, method, prec):
+    prob = problems[case]
+    plan = _plan(uf, ctx, prob)
+    got = plan.distance(method, prec)
+    want = oracle.problem_condensed(prob, OMETHOD[method])
+    err = _report(f"{case} {method} {prec}", got, want)
+    assert err.max(initial=0.0) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("method", [UW, WN])
+def test_separable_denominator(uf, ctx, problems, method, prec):
+    prob = problems["cfg2_shape_600"]
+    plan = _plan(uf, ctx, prob)
+    got = plan.distance(method, prec, tuning=dict(den_mode=1))
+    want = oracle.problem_condensed(prob, OMETHOD[method])
+    err = _report(f"den_mode=1 {method} {prec}", got, want)
+    assert err.max() <= TOL[prec]
+
+
+@pytest.mark.parametrize("emb_batch", [1, 7, 128])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("method", [UW, WN])
+def test_dyadic_inputs_bit_identical(uf, ctx, method, prec, emb_batch):
+    # lengths m/256 and rarefaction depth 256: every product and every partial sum of a
+    # batch is exactly representable, so all paths must equal the oracle bit for bit
+    prob = config_problem(1, n=300, tips=600, p_nonzero=0.3, depth=256, dyadic=True, seed=90)
+    plan = _plan(uf, ctx, prob)
+    got = plan.distance(method, prec, tuning=dict(emb_batch=emb_batch))
+    want = oracle.problem_condensed(prob, OMETHOD[method])
+    np.testing.assert_array_equal(got, want)
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 64, 255, 256])
+def test_stripe_layout(uf, ctx, n):
+    prob = config_problem(1, n=n, tips=300, p_nonzero=0.3, seed=100 + n)
+    plan = _plan(uf, ctx, prob)
+    for method in (UW, WN):
+        num, den = plan.stripes(method, "fp64")
+        S = n // 2
+        s, k = np.meshgrid(np.arange(S), np.arange(n), indexing="ij")
+        j = (k + s + 1) % n
+        with np.errstate(invalid="ignore", divide="ignore"):
+            d = np.where(den == 0, 0.0, num / den)
+        want = oracle.problem_pairs(prob, OMETHOD[method], k.ravel(), j.ravel()).reshape(S, n)
+        assert np.abs(d - want).max(initial=0.0) <= 1e-12
+        if n % 2 == 0 and S > 0:     # the doubled last stripe holds equal copies
+            np.testing.assert_array_equal(num[S - 1, : n // 2], num[S - 1, n // 2:])
+
+
+def _single(parent, length, rows, fnode):
+    indptr = np.zeros(len(rows) + 1, np.int64)
+    indptr[1:] = np.cumsum([len(r) for r in rows])
+    idx = np.array([f for r in rows for f, _ in r], np.int32)
+    cnt = np.array([c for r in rows for _, c in r], np.int32)
+    return Problem(parent=np.array(parent, np.int32), length=np.array(length, np.float64),
+                   feature_node=np.array(fnode, np.int32), indptr=indptr, indices=idx,
+                   counts=cnt, n_features=len(fnode))
+
+
+EDGE = {
+    "single_node_tree": lambda: _single([-1], [0.0], [[(0, 3)], [(0, 1)], [(0, 2)]], [0]),
+    "two_samples": lambda: _single([2, 2, -1], [1.0, 2.0, 0.0], [[(0, 1)], [(1, 5)]], [0, 1]),
+    "zero_lengths": lambda: _single([2, 2, -1], [0.0, 0.0, 0.0], [[(0, 1)], [(1, 5)], [(0, 2), (1, 2)]], [0, 1]),
+    "dups_unsorted": lambda: _single([3, 3, 4, 4, -1], [1.0, 2.0, 4.0, 3.0, 9.0],
+                                     [[(2, 1), (0, 1), (2, 4)], [(1, 2), (2, 2), (1, 1)], [(0, 3), (1, 1)]],
+                                     [0, 1, 2]),
+    "unary_chain": lambda: _single([1, 2, 3, -1, 3], [0.5, 0.25, 1.0, 0.0, 2.0],
+                                   [[(0, 1)], [(1, 1)], [(0, 1), (1, 1)]], [0, 4]),
+}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", sorted(EDGE))
+def test_edge_cases(uf, ctx, case, prec):
+    prob = EDGE[case]()
+    plan = _plan(uf, ctx, prob)
+    for method in (UW, WN):
+        got = plan.distance(method, prec)
+        want = oracle.problem_condensed(prob, OMETHOD[method])
+        assert np.abs(got - want).max(initial=0.0) <= TOL[prec], (case, method)
+
+
+def test_one_sample_has_no_pairs(uf, ctx):
+    prob = _single([2, 2, -1], [1.0, 2.0, 0.0], [[(0, 1)]], [0, 1])
+    plan = _plan(uf, ctx, prob)
+    assert plan.distance(UW, "fp64").size == 0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_identical_samples_give_exact_zero(uf, ctx, prec):
+    base = config_problem(1, n=50, tips=400, p_nonzero=0.3, seed=5)
+    # append copies of samples 0 and 7
+    rows = [(base.indices[base.indptr[k]:base.indptr[k + 1]], base.counts[base.indptr[k]:base.indptr[k + 1]])
+            for k in list(range(base.n_samples)) + [0, 7]]
+    indptr = np.zeros(len(rows) + 1, np.int64)
+    indptr[1:] = np.cumsum([len(r[0]) for r in rows])
+    prob = Problem(**{**base.__dict__, "indptr": indptr, "indices": np.concatenate([r[0] for r in rows]),
+                      "counts": np.concatenate([r[1] for r in rows])})
+    plan = _plan(uf, ctx, prob)
+    n = prob.n_samples
+    for method in (UW, WN):
+        d = plan.distance(method, prec)
+        assert d[condensed_index(n, 0, n - 2)] == 0.0
+        assert d[condensed_index(n, 7, n - 1)] == 0.0
+        assert np.all(d >= 0) and np.all(d <= 1)
+
+
+def test_deterministic_runs(uf, ctx, problems):
+    plan = _plan(uf, ctx, problems["cfg2_shape_600"])
+    for prec in ("fp64", "fp32"):
+        a = plan.distance(WN, prec)
+        b = plan.distance(WN, prec)
+        np.testing.assert_array_equal(a, b)
+
+
+def test_f32_output_and_device_output(uf, ctx, problems):
+    import torch
+    prob = problems["cfg1_ragged_257"]
+    plan = _plan(uf, ctx, prob)
+    want = oracle.problem_condensed(prob, oracle.WEIGHTED_NORMALIZED)
+    got32 = plan.distance(WN, "fp64", out_dtype="f32")
+    assert got32.dtype == np.float32
+    assert np.abs(got32 - want).max() <= 1e-7
+    dev = torch.empty(want.size, dtype=torch.float64, device="cuda:0")
+    plan.distance(WN, "fp64", out=dev)
+    torch.cuda.synchronize()
+    assert np.abs(dev.cpu().numpy() - want).max() <= 1e-12
+
+
+def test_mfma_weighted_is_unsupported(uf, ctx, problems):
+    plan = _plan(uf, ctx, problems["tiny_a"])
+    with pytest.raises(uf.UniFracError) as ei:
+        plan.distance(WN, "mfma_bf16x2")
+    assert ei.value.status_name == "UF_E_UNSUPPORTED"
+
+
+def test_one_shot_distance(uf, ctx, problems):
+    prob = problems["tiny_b"]
+    got = uf.distance(ctx, prob, UW, "fp64")
+    want = oracle.problem_condensed(prob, oracle.UNWEIGHTED)
+    assert np.abs(got - want).max() <= 1e-12
+
+
+def _sampled_pairs(n, n_random, first, seed):
+    rng = make_rng(seed)
+    i = rng.integers(0, n, size=n_random)
+    j = rng.integers(0, n, size=n_random)
+    keep = i != j
+    i, j = np.minimum(i[keep], j[keep]), np.maximum(i[keep], j[keep])
+    fi, fj = np.triu_indices(first, k=1)
+    return np.concatenate([i, fi]), np.concatenate([j, fj])
+
+
+@pytest.fixture(scope="module")
+def cfg2():
+    return config_problem(2)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_workload2_full_size_sampled(uf, ctx, cfg2, prec):
+    """The benchmark workload (4,096 samples, 32,768-tip coalescent tree), default knobs:
+    every output checked for range, a seeded sample of pairs checked against the oracle."""
+    import torch
+    plan = _plan(uf, ctx, cfg2)
+    n = cfg2.n_samples
+    out = torch.empty(n * (n - 1) // 2, dtype=torch.float64, device="cuda:0")
+    plan.distance(WN, prec, out=out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    assert np.all(got >= 0) and np.all(got <= 1)
+    pi, pj = _sampled_pairs(n, 1500, 48, seed=11)
+    want = oracle.problem_pairs(cfg2, oracle.WEIGHTED_NORMALIZED, pi, pj)
+    err = _report(f"workload2 WN {prec} sampled", got[condensed_index(n, pi, pj)], want)
+    assert err.max() <= TOL[prec]
