@@ -103,7 +103,13 @@ typedef struct {
     int32_t den_mode;   /* striped path: 0 = numerator and denominator stripes (default);
                            1 = numerator stripes only, denominator from per-sample sums
                            (weighted normalized: sum_b L_b p_ib + sum_b L_b p_jb)            */
-    int32_t reserved;
+    int32_t variant;    /* striped path: 0 = fused kernel that transforms count rows while
+                           staging them and loops over every batch in one launch (default);
+                           1 = separate transform launch into an embedding buffer and one
+                           striped launch per batch                                          */
+    int32_t tile;       /* striped fused/queued kernels: per-lane tile shape, 0 or 1:
+                           FP64 4x8 | 2x16, FP32 4x16 | 8x8 samples x stripes (stripes
+                           doubled with den_mode 1)                                          */
 } uf_tuning;
 
 typedef struct {
@@ -184,6 +190,37 @@ typedef struct {
 uf_status uf_plan_set_profiling(uf_plan *plan, int32_t enable);
 /* Copies up to `cap` classes with at least one launch into `out`; *n_out = classes copied. */
 uf_status uf_plan_get_profile(uf_plan *plan, uf_kernel_stat *out, int32_t cap, int32_t *n_out);
+
+/* ---- Batches of independent jobs ------------------------------------------------------
+ * Many UniFrac problems of uneven size computed together (the batching of Section 3 taken
+ * one level up: many jobs per launch instead of many branches per launch).  Every job is
+ * validated and made resident at creation; a run is a fixed sequence of launches shared by
+ * all jobs (one gather per tree level for every job together, one persistent
+ * queue-driven striped launch per precision and one for the matrix-core jobs, largest job
+ * first), which uf_batch_capture records once into a HIP graph for replay. */
+typedef struct {
+    uf_tree tree;
+    uf_table table;
+    uf_method method;
+    uf_precision prec;      /* FP64 / FP32 striped, or MFMA_BF16X2 (unweighted only)     */
+    uf_dtype out_dtype;
+    void *out;              /* DEVICE pointer to n*(n-1)/2 elements of out_dtype; it must
+                               stay valid for the life of the batch (graphs replay it)   */
+} uf_job;
+typedef struct uf_batch uf_batch;
+/* tuning (may be NULL): emb_batch, den_mode and k_chunk apply to every job. */
+uf_status uf_batch_create(uf_context *ctx, const uf_job *jobs, int32_t n_jobs,
+                          const uf_tuning *tuning, void *stream, uf_batch **out);
+/* Runs every job (replaying the captured graph if there is one) and waits for it. */
+uf_status uf_batch_run(uf_batch *batch, void *stream);
+/* Records the batch's device work into a HIP graph (on a private stream); later runs
+ * launch the graph.  Nothing is allocated while capturing or replaying. */
+uf_status uf_batch_capture(uf_batch *batch);
+uf_status uf_batch_set_profiling(uf_batch *batch, int32_t enable);
+uf_status uf_batch_get_profile(uf_batch *batch, uf_kernel_stat *out, int32_t cap, int32_t *n_out);
+void uf_batch_destroy(uf_batch *batch);
+/* One-shot: create, run, destroy. */
+uf_status uf_distance_batch(uf_context *ctx, const uf_job *jobs, int32_t n_jobs, void *stream);
 
 /* One-shot convenience: plan_create + plan_distance + plan_destroy. */
 uf_status uf_distance(uf_context *ctx, const uf_tree *tree, const uf_table *table,

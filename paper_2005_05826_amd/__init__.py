@@ -4,6 +4,7 @@ The compute lives in libunifrac_mi.so (C ABI: include/unifrac_mi.h); this packag
 thin Python binding.  Importing it loads the library and fails if it has not been built.
 """
 from .binding import (  # noqa: F401
+    Batch,
     Context,
     EXPORTED,
     LIB_PATH,

@@ -39,7 +39,9 @@ EXPORTED = ["uf_status_string", "uf_last_error", "uf_validate", "uf_context_crea
             "uf_context_destroy", "uf_plan_create", "uf_plan_destroy", "uf_plan_query",
             "uf_plan_embedding_counts", "uf_plan_embedding_presence", "uf_plan_distance",
             "uf_plan_stripes", "uf_plan_trim", "uf_plan_set_profiling",
-            "uf_plan_get_profile", "uf_distance"]
+            "uf_plan_get_profile", "uf_batch_create", "uf_batch_run", "uf_batch_capture",
+            "uf_batch_set_profiling", "uf_batch_get_profile", "uf_batch_destroy",
+            "uf_distance_batch", "uf_distance"]
 
 
 class UfTree(ctypes.Structure):
@@ -53,11 +55,16 @@ class UfTable(ctypes.Structure):
 
 class UfTuning(ctypes.Structure):
     _fields_ = [("emb_batch", c_i32), ("k_chunk", c_i32), ("den_mode", c_i32),
-                ("reserved", c_i32)]
+                ("variant", c_i32), ("tile", c_i32)]
 
 
 class UfKernelStat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", c_i64), ("total_ms", ctypes.c_double)]
+
+
+class UfJob(ctypes.Structure):
+    _fields_ = [("tree", UfTree), ("table", UfTable), ("method", ctypes.c_int),
+                ("prec", ctypes.c_int), ("out_dtype", ctypes.c_int), ("out", c_p)]
 
 
 class UfPlanInfo(ctypes.Structure):
@@ -89,12 +96,23 @@ _lib.uf_plan_trim.argtypes = [c_p]
 _lib.uf_plan_set_profiling.argtypes = [c_p, c_i32]
 _lib.uf_plan_get_profile.argtypes = [c_p, ctypes.POINTER(UfKernelStat), c_i32,
                                      ctypes.POINTER(c_i32)]
+_lib.uf_batch_create.argtypes = [c_p, ctypes.POINTER(UfJob), c_i32, ctypes.POINTER(UfTuning), c_p,
+                                 ctypes.POINTER(c_p)]
+_lib.uf_batch_run.argtypes = [c_p, c_p]
+_lib.uf_batch_capture.argtypes = [c_p]
+_lib.uf_batch_set_profiling.argtypes = [c_p, c_i32]
+_lib.uf_batch_get_profile.argtypes = [c_p, ctypes.POINTER(UfKernelStat), c_i32, ctypes.POINTER(c_i32)]
+_lib.uf_batch_destroy.argtypes = [c_p]
+_lib.uf_batch_destroy.restype = None
+_lib.uf_distance_batch.argtypes = [c_p, ctypes.POINTER(UfJob), c_i32, c_p]
 _lib.uf_distance.argtypes = [c_p, ctypes.POINTER(UfTree), ctypes.POINTER(UfTable), ctypes.c_int,
                              ctypes.c_int, ctypes.c_int, c_p, c_i32, c_p]
 for _name in ("uf_validate", "uf_context_create", "uf_plan_create", "uf_plan_query",
               "uf_plan_embedding_counts", "uf_plan_embedding_presence", "uf_plan_distance",
               "uf_plan_stripes", "uf_plan_trim", "uf_plan_set_profiling",
-              "uf_plan_get_profile", "uf_distance"):
+              "uf_plan_get_profile", "uf_batch_create", "uf_batch_run", "uf_batch_capture",
+              "uf_batch_set_profiling", "uf_batch_get_profile", "uf_distance_batch",
+              "uf_distance"):
     getattr(_lib, _name).restype = ctypes.c_int
 
 
@@ -164,7 +182,8 @@ def _tuning(t):
     if isinstance(t, UfTuning):
         return ctypes.byref(t)
     return ctypes.byref(UfTuning(int(t.get("emb_batch", 0)), int(t.get("k_chunk", 0)),
-                                 int(t.get("den_mode", 0)), 0))
+                                 int(t.get("den_mode", 0)), int(t.get("variant", 0)),
+                                 int(t.get("tile", 0))))
 
 
 class Context:
@@ -301,3 +320,55 @@ def distance(ctx: Context, prob, method="unweighted", precision="fp64", out_dtyp
                                 METHODS[method], PRECISIONS[precision], DTYPES[out_dtype],
                                 _ptr(out), 0, None))
     return out
+
+
+class Batch:
+    """Many jobs computed together.  `jobs` is a list of dicts with keys problem, method,
+    precision, out (a contiguous device tensor of n*(n-1)/2 elements) and optionally
+    out_dtype ('f64' or 'f32'); the output tensors must outlive the batch."""
+
+    def __init__(self, ctx: Context, jobs, tuning=None, stream=None):
+        self.ctx = ctx
+        arr = (UfJob * max(1, len(jobs)))()
+        self._outs = []
+        for i, j in enumerate(jobs):
+            inp = _Inputs(*_problem_args(j["problem"]))
+            out = j["out"]
+            self._outs.append(out)
+            arr[i] = UfJob(inp.tree, inp.table, METHODS[j["method"]], PRECISIONS[j["precision"]],
+                           DTYPES[j.get("out_dtype", "f64")], c_p(out.data_ptr()))
+            j["_inputs"] = inp   # keep the host arrays alive until creation returns
+        h = c_p()
+        ctx._check(_lib.uf_batch_create(ctx.handle, arr, len(jobs), _tuning(tuning),
+                                        _stream_handle(stream), ctypes.byref(h)))
+        for j in jobs:
+            j.pop("_inputs", None)
+        self._h = h
+
+    def run(self, stream=None):
+        self.ctx._check(_lib.uf_batch_run(self._h, _stream_handle(stream)))
+
+    def capture(self):
+        self.ctx._check(_lib.uf_batch_capture(self._h))
+
+    def set_profiling(self, enable: bool = True):
+        self.ctx._check(_lib.uf_batch_set_profiling(self._h, 1 if enable else 0))
+
+    def profile(self) -> dict:
+        cap = 16
+        buf = (UfKernelStat * cap)()
+        n = c_i32(0)
+        self.ctx._check(_lib.uf_batch_get_profile(self._h, buf, cap, ctypes.byref(n)))
+        return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms))
+                for i in range(n.value)}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.uf_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

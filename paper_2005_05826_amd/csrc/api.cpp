@@ -14,151 +14,15 @@
 #include <map>
 #include <new>
 
-#include "uf_internal.h"
+#include "uf_runtime.h"
+
+namespace ufmi {
+thread_local std::string g_tls_err;
+}
 
 using namespace ufmi;
 
-namespace {
-
-thread_local std::string g_tls_err;
-
-struct DevMem {
-    void *p = nullptr;
-    size_t bytes = 0;
-    hipError_t ensure(size_t want)
-    {
-        if (want == 0) want = 256;
-        if (bytes >= want) return hipSuccess;
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        bytes = 0;
-        hipError_t e = hipMalloc(&p, want);
-        if (e == hipSuccess) bytes = want;
-        return e;
-    }
-    void release()
-    {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        bytes = 0;
-    }
-    template <typename T>
-    T *as() const { return static_cast<T *>(p); }
-};
-
-// Event-pair timing of launches, grouped by kernel class.
-struct Profiler {
-    bool on = false;
-    struct Pending {
-        std::string cls;
-        hipEvent_t a, b;
-    };
-    std::vector<hipEvent_t> pool;
-    std::vector<Pending> pending;
-    std::map<std::string, std::pair<int64_t, double>> totals;
-
-    hipEvent_t take()
-    {
-        if (!pool.empty()) {
-            hipEvent_t e = pool.back();
-            pool.pop_back();
-            return e;
-        }
-        hipEvent_t e = nullptr;
-        if (hipEventCreate(&e) != hipSuccess) return nullptr;
-        return e;
-    }
-    void collect()
-    {
-        for (Pending &p : pending) {
-            float ms = 0.f;
-            if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
-                auto &t = totals[p.cls];
-                t.first += 1;
-                t.second += ms;
-            }
-            pool.push_back(p.a);
-            pool.push_back(p.b);
-        }
-        pending.clear();
-    }
-    void release()
-    {
-        collect();
-        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
-        pool.clear();
-    }
-};
-
-}  // namespace
-
-struct uf_context {
-    int32_t device = 0;
-    std::string err;
-};
-
-struct uf_plan {
-    uf_context *ctx = nullptr;
-    HostPrep hp;
-    // resident inputs
-    DevMem indptr, entry_slot, entry_count, totals, child_ptr, child_slot, len_slot, slot_of_node;
-    // scratch, allocated on first use
-    DevMem counts, bits, emb, num, den, D, out_tmp, gather_tmp;
-    DevMem mfma_scratch[4];
-    Profiler prof;
-    int64_t cstride = 0;  // int32 elements per count row (multiple of 64)
-    int64_t bstride = 0;  // uint32 words per presence row (multiple of 4)
-};
-
-namespace {
-
-uf_status set_err(uf_context *ctx, uf_status code, const std::string &msg)
-{
-    if (ctx)
-        ctx->err = msg;
-    else
-        g_tls_err = msg;
-    return code;
-}
-
-uf_status hip_fail(uf_context *ctx, hipError_t e, const char *what)
-{
-    std::string msg = std::string(what) + ": " + hipGetErrorString(e);
-    return set_err(ctx, e == hipErrorOutOfMemory ? UF_E_OOM : UF_E_DEVICE, msg);
-}
-
-#define UF_TRY(expr, what)                                       \
-    do {                                                         \
-        hipError_t _e = (expr);                                  \
-        if (_e != hipSuccess) return hip_fail(ctx, _e, (what));  \
-    } while (0)
-
-template <typename T>
-hipError_t upload(DevMem &m, const std::vector<T> &v, hipStream_t st)
-{
-    hipError_t e = m.ensure(v.size() * sizeof(T));
-    if (e != hipSuccess || v.empty()) return e;
-    return hipMemcpyAsync(m.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st);
-}
-
-inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
-
-// Launch `fn` on `st`, bracketed by timing events when the plan's profiler is on.
-template <typename F>
-hipError_t timed(uf_plan *plan, const char *cls, hipStream_t st, F &&fn)
-{
-    Profiler &P = plan->prof;
-    if (!P.on) return fn();
-    hipEvent_t a = P.take(), b = P.take();
-    if (!a || !b) return fn();
-    hipError_t e = hipEventRecord(a, st);
-    if (e != hipSuccess) return e;
-    e = fn();
-    if (e != hipSuccess) return e;
-    e = hipEventRecord(b, st);
-    if (e == hipSuccess) P.pending.push_back({cls, a, b});
-    return e;
-}
+namespace ufmi {
 
 // (a) embedding propagation, count form.
 uf_status propagate_counts(uf_plan *plan, hipStream_t st)
@@ -210,8 +74,51 @@ uf_status propagate_bits(uf_plan *plan, hipStream_t st)
     return UF_OK;
 }
 
+uf_status plan_prepare(uf_context *ctx, const uf_tree *tree, const uf_table *table,
+                       hipStream_t st, uf_plan **out)
+{
+    *out = nullptr;
+    uf_plan *plan = new (std::nothrow) uf_plan;
+    if (!plan) return set_err(ctx, UF_E_OOM, "host allocation failed");
+    plan->ctx = ctx;
+    std::string err;
+    uf_status s = validate_and_prepare(tree, table, &plan->hp, &err);
+    if (s != UF_OK) {
+        delete plan;
+        return set_err(ctx, s, err);
+    }
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) {
+        delete plan;
+        return hip_fail(ctx, e, "hipSetDevice");
+    }
+    const HostPrep &hp = plan->hp;
+    plan->cstride = round_up(hp.n_samples, 64);
+    plan->bstride = round_up((hp.n_samples + 31) / 32, 4);
+    hipError_t r = hipSuccess;
+    if (r == hipSuccess) r = upload(plan->indptr, hp.indptr, st);
+    if (r == hipSuccess) r = upload(plan->entry_slot, hp.entry_slot, st);
+    if (r == hipSuccess) r = upload(plan->entry_count, hp.entry_count, st);
+    if (r == hipSuccess) r = upload(plan->totals, hp.totals, st);
+    if (r == hipSuccess) r = upload(plan->child_ptr, hp.child_ptr, st);
+    if (r == hipSuccess) r = upload(plan->child_slot, hp.child_slot, st);
+    if (r == hipSuccess) r = upload(plan->len_slot, hp.length_slot, st);
+    if (r == hipSuccess) r = upload(plan->slot_of_node, hp.slot_of_node, st);
+    if (r == hipSuccess) r = hipStreamSynchronize(st);
+    if (r != hipSuccess) {
+        uf_plan_destroy(plan);
+        return hip_fail(ctx, r, "uploading inputs");
+    }
+    *out = plan;
+    return UF_OK;
+}
+
+}  // namespace ufmi
+
+namespace {
+
 struct Knobs {
-    int32_t emb_batch, k_chunk, den_mode;
+    int32_t emb_batch, k_chunk, den_mode, variant, tile;
 };
 
 Knobs resolve_knobs(const uf_tuning *t, uf_precision prec, int32_t n_branches)
@@ -226,6 +133,8 @@ Knobs resolve_knobs(const uf_tuning *t, uf_precision prec, int32_t n_branches)
     k.emb_batch = std::max(k.emb_batch, 1);
     k.k_chunk = (t && t->k_chunk > 0) ? t->k_chunk : 4096;
     k.den_mode = (t ? t->den_mode : 0);
+    k.variant = (t ? t->variant : 0);
+    k.tile = (t ? t->tile : 0);
     return k;
 }
 
@@ -236,7 +145,7 @@ uf_status run_striped(uf_plan *plan, uf_method method, uf_precision prec, const 
     uf_context *ctx = plan->ctx;
     const HostPrep &hp = plan->hp;
     const bool fp64 = (prec == UF_PREC_FP64);
-    const StripeGeom g = stripe_geometry(hp.n_samples, fp64);
+    const StripeGeom g = stripe_geometry(hp.n_samples, fp64, kn.den_mode, kn.variant == 0 ? kn.tile : 0);
     *geom = g;
     const int32_t B = hp.n_nodes - 1;
     const size_t tsz = fp64 ? sizeof(double) : sizeof(float);
@@ -255,10 +164,28 @@ uf_status run_striped(uf_plan *plan, uf_method method, uf_precision prec, const 
     }
     uf_status s = propagate_counts(plan, st);
     if (s != UF_OK) return s;
+    // the stripe kernels add every batch into the state, so it starts at zero
+    UF_TRY(launch_fill_u32(num, 0u, state / 4, st), "clearing stripes");
+    if (den) UF_TRY(launch_fill_u32(den, 0u, state / 4, st), "clearing stripes");
     const int32_t E = kn.emb_batch;
-    UF_TRY(plan->emb.ensure((size_t)E * g.estride * tsz), "allocating embedding batch");
     const int32_t *C = plan->counts.as<int32_t>();
     const double *len = plan->len_slot.as<double>();
+    if (kn.variant == 0) {
+        UF_TRY(plan->inv_t.ensure((size_t)hp.n_samples * sizeof(double)), "allocating totals");
+        UF_TRY(launch_inv_totals(plan->totals.as<int32_t>(), hp.n_samples, plan->inv_t.as<double>(), st),
+               "reciprocal totals");
+        UF_TRY(timed(plan, "stripe", st, [&] {
+                   return launch_stripe_fused(fp64, method, kn.den_mode, kn.tile, C, plan->cstride,
+                                              plan->inv_t.as<double>(), len, B, E, num, den, g, st);
+               }), "striped accumulation");
+        if (kn.den_mode != 0)
+            UF_TRY(timed(plan, "rowdot", st, [&] {
+                       return launch_rowdot(method, C, plan->cstride, 0, B,
+                                            plan->totals.as<int32_t>(), len, g.n, D, true, st);
+                   }), "per-sample sums");
+        return UF_OK;
+    }
+    UF_TRY(plan->emb.ensure((size_t)E * g.estride * tsz), "allocating embedding batch");
     for (int32_t b0 = 0; b0 < B; b0 += E) {
         const int32_t eb = std::min(E, B - b0);
         UF_TRY(timed(plan, "transform", st, [&] {
@@ -399,41 +326,7 @@ uf_status uf_plan_create(uf_context *ctx, const uf_tree *tree, const uf_table *t
                          void *stream, uf_plan **out)
 {
     if (!ctx || !out) return set_err(ctx, UF_E_ARG, "ctx and out must not be NULL");
-    *out = nullptr;
-    uf_plan *plan = new (std::nothrow) uf_plan;
-    if (!plan) return set_err(ctx, UF_E_OOM, "host allocation failed");
-    plan->ctx = ctx;
-    std::string err;
-    uf_status s = validate_and_prepare(tree, table, &plan->hp, &err);
-    if (s != UF_OK) {
-        delete plan;
-        return set_err(ctx, s, err);
-    }
-    hipError_t e = hipSetDevice(ctx->device);
-    if (e != hipSuccess) {
-        delete plan;
-        return hip_fail(ctx, e, "hipSetDevice");
-    }
-    const HostPrep &hp = plan->hp;
-    plan->cstride = round_up(hp.n_samples, 64);
-    plan->bstride = round_up((hp.n_samples + 31) / 32, 4);
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    hipError_t r = hipSuccess;
-    if (r == hipSuccess) r = upload(plan->indptr, hp.indptr, st);
-    if (r == hipSuccess) r = upload(plan->entry_slot, hp.entry_slot, st);
-    if (r == hipSuccess) r = upload(plan->entry_count, hp.entry_count, st);
-    if (r == hipSuccess) r = upload(plan->totals, hp.totals, st);
-    if (r == hipSuccess) r = upload(plan->child_ptr, hp.child_ptr, st);
-    if (r == hipSuccess) r = upload(plan->child_slot, hp.child_slot, st);
-    if (r == hipSuccess) r = upload(plan->len_slot, hp.length_slot, st);
-    if (r == hipSuccess) r = upload(plan->slot_of_node, hp.slot_of_node, st);
-    if (r == hipSuccess) r = hipStreamSynchronize(st);
-    if (r != hipSuccess) {
-        uf_plan_destroy(plan);
-        return hip_fail(ctx, r, "uploading inputs");
-    }
-    *out = plan;
-    return UF_OK;
+    return plan_prepare(ctx, tree, table, static_cast<hipStream_t>(stream), out);
 }
 
 void uf_plan_destroy(uf_plan *plan)
@@ -443,7 +336,7 @@ void uf_plan_destroy(uf_plan *plan)
     for (DevMem *m : {&plan->indptr, &plan->entry_slot, &plan->entry_count, &plan->totals,
                       &plan->child_ptr, &plan->child_slot, &plan->len_slot, &plan->slot_of_node,
                       &plan->counts, &plan->bits, &plan->emb, &plan->num, &plan->den, &plan->D,
-                      &plan->out_tmp, &plan->gather_tmp})
+                      &plan->inv_t, &plan->out_tmp, &plan->gather_tmp})
         m->release();
     for (DevMem &m : plan->mfma_scratch) m.release();
     plan->prof.release();
@@ -455,7 +348,7 @@ uf_status uf_plan_trim(uf_plan *plan)
     if (!plan) return set_err(nullptr, UF_E_ARG, "plan must not be NULL");
     (void)hipSetDevice(plan->ctx->device);
     for (DevMem *m : {&plan->counts, &plan->bits, &plan->emb, &plan->num, &plan->den, &plan->D,
-                      &plan->out_tmp, &plan->gather_tmp})
+                      &plan->inv_t, &plan->out_tmp, &plan->gather_tmp})
         m->release();
     for (DevMem &m : plan->mfma_scratch) m.release();
     return UF_OK;
@@ -536,6 +429,8 @@ uf_status uf_plan_distance(uf_plan *plan, uf_method method, uf_precision prec,
     if (!out) return set_err(ctx, UF_E_ARG, "out must not be NULL");
     const Knobs kn = resolve_knobs(tuning, prec, hp.n_nodes - 1);
     if (kn.den_mode != 0 && kn.den_mode != 1) return set_err(ctx, UF_E_ARG, "den_mode must be 0 or 1");
+    if (kn.variant != 0 && kn.variant != 1) return set_err(ctx, UF_E_ARG, "variant must be 0 or 1");
+    if (kn.tile != 0 && kn.tile != 1) return set_err(ctx, UF_E_ARG, "tile must be 0 or 1");
     UF_TRY(hipSetDevice(ctx->device), "hipSetDevice");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const size_t esz = out_dtype == UF_F32 ? sizeof(float) : sizeof(double);

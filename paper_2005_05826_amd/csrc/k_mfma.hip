@@ -95,28 +95,29 @@ __device__ inline bf16x8 as_bf16x8(uint32_t a, uint32_t b, uint32_t c, uint32_t 
     return __builtin_bit_cast(bf16x8, v);
 }
 
-// Upper-triangular tiles of S = P diag(hi + lo) P^T.  Tile t covers rows tiles[t].x*GM ..
-// and columns tiles[t].y*GM .. (x <= y).  Work-group b takes tile (b % 8) * per + b / 8, so
-// the 8 XCDs (which receive work-groups round-robin) each sweep a contiguous run of tiles
-// that share A panels in their L2.  Writes S_ij (i < j) into the condensed array and S_ii
-// into T.
-__global__ __launch_bounds__(256, 1) void k_mfma_gemm(
-    const uint8_t *__restrict__ P, int64_t k_pad, int32_t n_kstep,
-    const uint16_t *__restrict__ hi, const uint16_t *__restrict__ lo, int32_t chunk_steps,
-    const int2 *__restrict__ tiles, int32_t n_tiles, int32_t n, double *__restrict__ S,
-    double *__restrict__ T)
-{
-    // two LDS stages: the next stage's global loads are in flight while this one computes
-    __shared__ __align__(16) uint8_t sA[2][GM * LDK];
-    __shared__ __align__(16) uint8_t sB[2][GM * LDK];
-    __shared__ __align__(16) uint16_t sh[2][GK];
-    __shared__ __align__(16) uint16_t sl[2][GK];
+// Two LDS stages: the next stage's global loads are in flight while this one computes.
+struct MfmaSmem {
+    __align__(16) uint8_t A[2][GM * LDK];
+    __align__(16) uint8_t B[2][GM * LDK];
+    __align__(16) uint16_t h[2][GK];
+    __align__(16) uint16_t l[2][GK];
+};
 
-    const int32_t per = (n_tiles + 7) / 8;
-    const int32_t t = (int32_t)(blockIdx.x % 8) * per + (int32_t)(blockIdx.x / 8);
-    if (t >= n_tiles) return;
-    const int2 tile = tiles[t];
-    const int32_t row0 = tile.x * GM, col0 = tile.y * GM;
+// One GM x GM tile of S = P diag(hi + lo) P^T (rows row0.., columns col0.., row0 <= col0):
+// writes S_ij (i < j) into the condensed array and S_ii into T.
+__device__ void mfma_tile(const MfmaArgs &a, int32_t row0, int32_t col0, MfmaSmem &sm)
+{
+    auto &sA = sm.A;
+    auto &sB = sm.B;
+    auto &sh = sm.h;
+    auto &sl = sm.l;
+    const uint8_t *__restrict__ P = a.P;
+    const uint16_t *__restrict__ hi = a.hi;
+    const uint16_t *__restrict__ lo = a.lo;
+    const int64_t k_pad = a.k_pad;
+    const int32_t n_kstep = a.n_kstep, chunk_steps = a.chunk_steps, n = a.n;
+    double *__restrict__ S = a.S;
+    double *__restrict__ T = a.T;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -246,6 +247,41 @@ __global__ __launch_bounds__(256, 1) void k_mfma_gemm(
             }
 }
 
+// Single job.  Work-group b takes tile (b % 8) * per + b / 8 of the upper-triangular list,
+// so the 8 XCDs (which receive work-groups round-robin) each sweep a contiguous run of
+// tiles that share A panels in their L2.
+__global__ __launch_bounds__(256, 1) void k_mfma_gemm(MfmaArgs a, const int2 *__restrict__ tiles,
+                                                     int32_t n_tiles)
+{
+    __shared__ MfmaSmem sm;
+    const int32_t per = (n_tiles + 7) / 8;
+    const int32_t t = (int32_t)(blockIdx.x % 8) * per + (int32_t)(blockIdx.x / 8);
+    if (t >= n_tiles) return;
+    const int2 tile = tiles[t];
+    mfma_tile(a, tile.x * GM, tile.y * GM, sm);
+}
+
+// Many jobs: work-groups take (job, tile) items from a global counter (items listed
+// largest job first), leaving at the first fetch past the end.  *counter is zero at launch.
+__global__ __launch_bounds__(256, 1) void k_mfma_queue(const MfmaArgs *__restrict__ jobs,
+                                                      const int2 *__restrict__ items,
+                                                      int32_t n_items, int32_t *__restrict__ counter)
+{
+    __shared__ MfmaSmem sm;
+    __shared__ int32_t s_item;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+        __syncthreads();
+        const int32_t it = s_item;
+        if (it >= n_items) break;
+        const int2 item = items[it];
+        const MfmaArgs a = jobs[item.x];
+        const int2 tile = a.tiles[item.y];
+        mfma_tile(a, tile.x * GM, tile.y * GM, sm);
+    }
+}
+
 // d_ij = (T_i + T_j - 2 S_ij) / (T_i + T_j - S_ij), 0 when the denominator is 0.
 // S may alias out (FP64 output): each element is read before it is written by one thread.
 template <typename OUT>
@@ -311,17 +347,40 @@ hipError_t launch_bits_to_bytes(const uint32_t *bits, int64_t bstride, const Mfm
     return hipGetLastError();
 }
 
+MfmaArgs make_mfma_args(const uint8_t *P, const uint16_t *hi, const uint16_t *lo, int32_t k_chunk,
+                        const int32_t *tiles_xy, const MfmaGeom &g, double *S, double *T)
+{
+    MfmaArgs a;
+    a.P = P;
+    a.k_pad = g.k_pad;
+    a.n_kstep = (int32_t)(g.k_pad / GK);
+    a.chunk_steps = k_chunk / GK < 1 ? 1 : k_chunk / GK;
+    a.hi = hi;
+    a.lo = lo;
+    a.n = g.n;
+    a.n_tiles = g.n_tiles;
+    a.S = S;
+    a.T = T;
+    a.tiles = reinterpret_cast<const int2 *>(tiles_xy);
+    return a;
+}
+
 hipError_t launch_mfma_gemm(const uint8_t *P, const uint16_t *hi, const uint16_t *lo,
                             int32_t k_chunk, const int32_t *tiles_xy, const MfmaGeom &g,
                             double *S, double *T, hipStream_t st)
 {
-    const int32_t n_kstep = (int32_t)(g.k_pad / GK);
-    int32_t chunk_steps = k_chunk / GK;
-    if (chunk_steps < 1) chunk_steps = 1;
+    const MfmaArgs a = make_mfma_args(P, hi, lo, k_chunk, tiles_xy, g, S, T);
     const int32_t per = (g.n_tiles + 7) / 8;
-    k_mfma_gemm<<<(unsigned)(8 * per), 256, 0, st>>>(P, g.k_pad, n_kstep, hi, lo, chunk_steps,
-                                                     reinterpret_cast<const int2 *>(tiles_xy),
-                                                     g.n_tiles, g.n, S, T);
+    k_mfma_gemm<<<(unsigned)(8 * per), 256, 0, st>>>(a, a.tiles, g.n_tiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_mfma_queue(const MfmaArgs *jobs, const int32_t *items_xy, int32_t n_items,
+                             int32_t *counter, int32_t n_groups, hipStream_t st)
+{
+    if (n_items <= 0) return hipSuccess;
+    k_mfma_queue<<<n_groups, 256, 0, st>>>(jobs, reinterpret_cast<const int2 *>(items_xy), n_items,
+                                           counter);
     return hipGetLastError();
 }
 

@@ -91,6 +91,53 @@ __global__ void k_gather_rows(const uint32_t *__restrict__ src, int64_t sstride,
 
 inline unsigned grid1(size_t n, size_t per) { return (unsigned)((n + per - 1) / per); }
 
+// Many jobs at once: one launch scatters the tips of every job, and one launch per height
+// level gathers that level of every job (tasks are (job, slot) pairs), so a batch of jobs
+// costs max-height launches rather than the sum of the heights.
+__global__ void k_scatter_batched(const PropJob *__restrict__ jobs, const int2 *__restrict__ tasks,
+                                  int32_t n_tasks)
+{
+    const int32_t t = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (t >= n_tasks) return;
+    const int2 task = tasks[t];
+    const PropJob &J = jobs[task.x];
+    const int32_t k = task.y;
+    const int lane = threadIdx.x & 63;
+    const int64_t e1 = J.indptr[k + 1];
+    if (J.mode == 0) {
+        int32_t *C = reinterpret_cast<int32_t *>(J.X);
+        for (int64_t e = J.indptr[k] + lane; e < e1; e += 64)
+            atomicAdd(C + (int64_t)J.entry_slot[e] * J.stride + k, J.entry_count[e]);
+    } else {
+        const uint32_t bit = 1u << (k & 31);
+        for (int64_t e = J.indptr[k] + lane; e < e1; e += 64)
+            if (J.entry_count[e] > 0) atomicOr(J.X + (int64_t)J.entry_slot[e] * J.stride + (k >> 5), bit);
+    }
+}
+
+__global__ void k_level_batched(const PropJob *__restrict__ jobs, const int2 *__restrict__ tasks,
+                                int32_t n_tasks)
+{
+    const int32_t c = blockIdx.x * kBlock + threadIdx.x;
+    for (int32_t r = blockIdx.y; r < n_tasks; r += gridDim.y) {
+        const int2 task = tasks[r];
+        const PropJob &J = jobs[task.x];
+        if (c >= (int32_t)(J.stride / 4)) continue;
+        const int32_t i = task.y - J.n_leaf;
+        const int32_t q0 = J.child_ptr[i], q1 = J.child_ptr[i + 1];
+        uint4 acc = make_uint4(0u, 0u, 0u, 0u);
+        for (int32_t q = q0; q < q1; ++q) {
+            const uint4 v = reinterpret_cast<const uint4 *>(J.X + (int64_t)J.child_slot[q] * J.stride)[c];
+            if (J.mode) {
+                acc.x |= v.x; acc.y |= v.y; acc.z |= v.z; acc.w |= v.w;
+            } else {
+                acc.x += v.x; acc.y += v.y; acc.z += v.z; acc.w += v.w;
+            }
+        }
+        reinterpret_cast<uint4 *>(J.X + (int64_t)task.y * J.stride)[c] = acc;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_fill_u32(void *p, uint32_t value, size_t n_words, hipStream_t st)
@@ -157,6 +204,28 @@ hipError_t launch_gather_rows_u32(const uint32_t *src, int64_t sstride, const in
     if (n_nodes <= 0 || width <= 0) return hipSuccess;
     dim3 grid(grid1(width, kBlock), (unsigned)(n_nodes < 65535 ? n_nodes : 65535));
     k_gather_rows<<<grid, kBlock, 0, st>>>(src, sstride, slot_of_node, n_nodes, width, out);
+    return hipGetLastError();
+}
+
+}  // namespace ufmi
+
+namespace ufmi {
+
+hipError_t launch_scatter_batched(const PropJob *jobs, const int32_t *tasks_xy, int32_t n_tasks,
+                                  hipStream_t st)
+{
+    if (n_tasks <= 0) return hipSuccess;
+    k_scatter_batched<<<grid1(n_tasks, kBlock / 64), kBlock, 0, st>>>(
+        jobs, reinterpret_cast<const int2 *>(tasks_xy), n_tasks);
+    return hipGetLastError();
+}
+
+hipError_t launch_level_batched(const PropJob *jobs, const int32_t *tasks_xy, int32_t n_tasks,
+                                int32_t max_vec, hipStream_t st)
+{
+    if (n_tasks <= 0) return hipSuccess;
+    dim3 grid(grid1(max_vec, kBlock), (unsigned)(n_tasks < 65535 ? n_tasks : 65535));
+    k_level_batched<<<grid, kBlock, 0, st>>>(jobs, reinterpret_cast<const int2 *>(tasks_xy), n_tasks);
     return hipGetLastError();
 }
 

@@ -20,16 +20,57 @@ namespace {
 
 constexpr int kBlock = 256;  // 4 waves: wave w owns stripes [w*TST, (w+1)*TST) of the tile
 
-template <typename T>
+// Per-lane micro-tile: TKT consecutive samples x TST consecutive stripes; EB branches per
+// LDS stage.  The tile is sized so that accumulators stay near 128 VGPRs (two waves per
+// SIMD) and the work-group covers enough stripes (4 * TST) to amortize the staging of its
+// windows (2 * TKW + TSW values per branch for TKW * TSW updates).
+template <typename T, int DEN, int TILE>
 struct StripeCfg;
-template <>
-struct StripeCfg<double> {
-    static constexpr int TKT = 4, TST = 8, EB = 16;
-};
-template <>
-struct StripeCfg<float> {
-    static constexpr int TKT = 8, TST = 4, EB = 16;
-};
+template <> struct StripeCfg<double, 0, 0> { static constexpr int TKT = 4, TST = 8, EB = 16; };
+template <> struct StripeCfg<double, 0, 1> { static constexpr int TKT = 2, TST = 16, EB = 16; };
+template <> struct StripeCfg<double, 1, 0> { static constexpr int TKT = 4, TST = 16, EB = 16; };
+template <> struct StripeCfg<double, 1, 1> { static constexpr int TKT = 2, TST = 32, EB = 16; };
+template <> struct StripeCfg<float, 0, 0> { static constexpr int TKT = 4, TST = 16, EB = 16; };
+template <> struct StripeCfg<float, 0, 1> { static constexpr int TKT = 8, TST = 8, EB = 16; };
+template <> struct StripeCfg<float, 1, 0> { static constexpr int TKT = 4, TST = 32, EB = 16; };
+template <> struct StripeCfg<float, 1, 1> { static constexpr int TKT = 8, TST = 16, EB = 16; };
+
+// Pins a register value at this point of the program: the conversions that follow cannot
+// be hoisted above it, which keeps the FP64 copies of a tile from being live all at once.
+template <typename T>
+__device__ inline T pin(T x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
+// Adds a lane's register tile (TST stripe rows of TKT consecutive samples) into the FP64
+// stripe state (cleared before the first batch), one row at a time.
+template <int TST, int TKT, int DEN, typename T>
+__device__ inline void add_tile(const T (&an)[TST][TKT], const T (&ad)[TST][TKT],
+                                double *__restrict__ num, double *__restrict__ den,
+                                int64_t off, int64_t sstride)
+{
+    static_assert(TKT % 2 == 0, "rows are written as double2");
+#pragma unroll
+    for (int s = 0; s < TST; ++s) {
+        double2 *pn = reinterpret_cast<double2 *>(num + off + s * sstride);
+        double2 *pd = reinterpret_cast<double2 *>(den + off + s * sstride);
+#pragma unroll
+        for (int r = 0; r < TKT; r += 2) {
+            double2 a = pn[r / 2];
+            a.x += (double)pin(an[s][r]);
+            a.y += (double)pin(an[s][r + 1]);
+            pn[r / 2] = a;
+            if (DEN == 0) {
+                double2 b = pd[r / 2];
+                b.x += (double)pin(ad[s][r]);
+                b.y += (double)pin(ad[s][r + 1]);
+                pd[r / 2] = b;
+            }
+        }
+    }
+}
 
 // emb[e][x] = f(C[slot0 + e][x mod n]) for x < n + S, else 0.
 // Weighted normalized: f = count / total (FP64 division, then rounded to T).
@@ -59,7 +100,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_stripe(
     const T *__restrict__ emb, int64_t estride, const double *__restrict__ len, int32_t E,
     double *__restrict__ num, double *__restrict__ den, int64_t sstride, int32_t first)
 {
-    constexpr int TKT = StripeCfg<T>::TKT, TST = StripeCfg<T>::TST, EB = StripeCfg<T>::EB;
+    constexpr int TKT = StripeCfg<T, DEN, 0>::TKT, TST = StripeCfg<T, DEN, 0>::TST, EB = StripeCfg<T, DEN, 0>::EB;
     constexpr int TKW = 64 * TKT, TSW = 4 * TST, VW = TKW + TSW;
     constexpr int NV = TKT + TST - 1;
     __shared__ T su[EB * TKW];
@@ -93,6 +134,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_stripe(
             sv[idx] = vbase[(int64_t)(e0 + e) * estride + x];
         }
         __syncthreads();
+#pragma unroll 1
         for (int e = 0; e < eb; ++e) {
             const T L = (T)len[e0 + e];
             T u[TKT], v[NV];
@@ -116,19 +158,186 @@ __global__ __launch_bounds__(kBlock, 2) void k_stripe(
         }
     }
 
+    add_tile<TST, TKT, DEN>(an, ad, num, den, (int64_t)(s0 + w * TST) * sstride + k0 + lane * TKT,
+                            sstride);
+}
+
+// Fused form of (a2) + (b): one work-group tile covers every batch of branches.  The
+// work-group stages the embedding windows straight from the int32 count rows (transforming
+// while staging: proportion = count * (1 / total) or presence = count > 0), so no embedding
+// buffer is written.  A thread stages fixed window positions for every branch, so the
+// sample index (with the wrap k + s + 1 - n) and the reciprocal total of each position are
+// computed once.  Batches of E branches accumulate in registers; between batches the tile
+// is added into the FP64 stripe state (num/den, cleared beforehand), the cross-batch
+// accumulator.
+template <typename T, int DEN, int TILE>
+struct StripeSmem {
+    static constexpr int TKT = StripeCfg<T, DEN, TILE>::TKT, TST = StripeCfg<T, DEN, TILE>::TST,
+                         EB = StripeCfg<T, DEN, TILE>::EB;
+    static constexpr int TKW = 64 * TKT, TSW = 4 * TST, VW = TKW + TSW;
+    T su[EB * TKW];
+    T sv[EB * VW];
+};
+
+template <typename T, int METHOD, int DEN, int TILE>
+__device__ void stripe_tile(const StripeArgs &a, int32_t k0, int32_t s0, StripeSmem<T, DEN, TILE> &sm)
+{
+    using SM = StripeSmem<T, DEN, TILE>;
+    constexpr int TKT = SM::TKT, TST = SM::TST, EB = SM::EB;
+    constexpr int TKW = SM::TKW, VW = SM::VW;
+    constexpr int NV = TKT + TST - 1;
+    constexpr int NU_T = (TKW + kBlock - 1) / kBlock;   // u positions per thread
+    constexpr int NV_T = (VW + kBlock - 1) / kBlock;    // v positions per thread
+    const int32_t *__restrict__ C = a.C;
+    const double *__restrict__ len = a.len;
+    const int64_t cstride = a.cstride, sstride = a.sstride;
+    const int32_t n = a.n, S = a.S, B = a.B, E = a.E;
+    T *su = sm.su, *sv = sm.sv;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = tid >> 6;
+
+    // staging positions: clamped sample index, validity, and scale (1/total or 1)
+    int32_t uk[NU_T], vk[NV_T];
+    T us[NU_T], vs[NV_T];
 #pragma unroll
-    for (int s = 0; s < TST; ++s) {
-        const int64_t off = (int64_t)(s0 + w * TST + s) * sstride + k0 + lane * TKT;
+    for (int q = 0; q < NU_T; ++q) {
+        const int32_t g = k0 + tid + q * kBlock;
+        const bool ok = g < n && tid + q * kBlock < TKW;
+        uk[q] = ok ? g : 0;
+        us[q] = ok ? (METHOD == UF_WEIGHTED_NORMALIZED ? (T)a.inv_t[g] : T(1)) : T(0);
+    }
 #pragma unroll
-        for (int r = 0; r < TKT; ++r) {
-            const double a = first ? 0.0 : num[off + r];
-            num[off + r] = a + (double)an[s][r];
-            if (DEN == 0) {
-                const double b = first ? 0.0 : den[off + r];
-                den[off + r] = b + (double)ad[s][r];
+    for (int q = 0; q < NV_T; ++q) {
+        const int32_t x = tid + q * kBlock;
+        const int32_t g = k0 + s0 + 1 + x;
+        int32_t k = -1;
+        if (x < VW) k = g < n ? g : (g < n + S ? g - n : -1);
+        vk[q] = k >= 0 ? k : 0;
+        vs[q] = k >= 0 ? (METHOD == UF_WEIGHTED_NORMALIZED ? (T)a.inv_t[k] : T(1)) : T(0);
+    }
+
+    for (int32_t b0 = 0; b0 < B; b0 += E) {
+        const int32_t b1 = (B - b0) < E ? B : b0 + E;
+        T an[TST][TKT], ad[TST][TKT];
+#pragma unroll
+        for (int s = 0; s < TST; ++s)
+#pragma unroll
+            for (int r = 0; r < TKT; ++r) {
+                an[s][r] = T(0);
+                ad[s][r] = T(0);
+            }
+        for (int32_t e0 = b0; e0 < b1; e0 += EB) {
+            const int eb = (b1 - e0) < EB ? (b1 - e0) : EB;
+            // issue every load of the stage before the first use (rows past the batch end
+            // re-read the last row and are never stored); padding positions read sample 0
+            // and are zeroed by their scale
+            int32_t cu[EB][NU_T], cv[EB][NV_T];
+#pragma unroll
+            for (int e = 0; e < EB; ++e) {
+                const int32_t *row = C + (int64_t)(e0 + (e < eb ? e : eb - 1)) * cstride;
+#pragma unroll
+                for (int q = 0; q < NU_T; ++q) cu[e][q] = row[uk[q]];
+#pragma unroll
+                for (int q = 0; q < NV_T; ++q) cv[e][q] = row[vk[q]];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int e = 0; e < EB; ++e) {
+                if (e < eb) {
+#pragma unroll
+                    for (int q = 0; q < NU_T; ++q) {
+                        const int32_t x = tid + q * kBlock;
+                        const int32_t c = cu[e][q];
+                        if (x < TKW)
+                            su[e * TKW + x] = METHOD == UF_WEIGHTED_NORMALIZED
+                                                  ? (T)c * us[q]
+                                                  : (c > 0 ? us[q] : T(0));
+                    }
+#pragma unroll
+                    for (int q = 0; q < NV_T; ++q) {
+                        const int32_t x = tid + q * kBlock;
+                        const int32_t c = cv[e][q];
+                        if (x < VW)
+                            sv[e * VW + x] = METHOD == UF_WEIGHTED_NORMALIZED
+                                                 ? (T)c * vs[q]
+                                                 : (c > 0 ? vs[q] : T(0));
+                    }
+                }
+            }
+            __syncthreads();
+#pragma unroll 1
+            for (int e = 0; e < eb; ++e) {
+                const T L = (T)len[e0 + e];
+                T u[TKT], v[NV];
+#pragma unroll
+                for (int r = 0; r < TKT; ++r) u[r] = su[e * TKW + lane * TKT + r];
+#pragma unroll
+                for (int c = 0; c < NV; ++c) v[c] = sv[e * VW + lane * TKT + w * TST + c];
+#pragma unroll
+                for (int s = 0; s < TST; ++s)
+#pragma unroll
+                    for (int r = 0; r < TKT; ++r) {
+                        const T x = v[r + s];
+                        an[s][r] = fma(fabs(u[r] - x), L, an[s][r]);
+                        if (DEN == 0) {
+                            if (METHOD == UF_WEIGHTED_NORMALIZED)
+                                ad[s][r] = fma(u[r] + x, L, ad[s][r]);
+                            else
+                                ad[s][r] = fma(fmax(u[r], x), L, ad[s][r]);
+                        }
+                    }
             }
         }
+        add_tile<TST, TKT, DEN>(an, ad, a.num, a.den,
+                                (int64_t)(s0 + w * TST) * sstride + k0 + lane * TKT, sstride);
     }
+}
+
+template <typename T, int METHOD, int DEN, int TILE>
+__global__ __launch_bounds__(kBlock, 2) void k_stripe_fused(StripeArgs a)
+{
+    using SM = StripeSmem<T, DEN, TILE>;
+    __shared__ SM sm;
+    stripe_tile<T, METHOD, DEN, TILE>(a, blockIdx.x * SM::TKW, blockIdx.y * SM::TSW, sm);
+}
+
+// Persistent form for many jobs: every work-group takes items (job, tile) from a global
+// counter until the list is exhausted.  Items are listed largest job first (cost of a tile
+// is proportional to the job's branch count), so the dynamic queue is a longest-processing-
+// time-first schedule over the machine.  The counter must be zero at launch; every
+// work-group leaves the loop at its first fetch past the end.
+template <typename T, int DEN, int TILE>
+__global__ __launch_bounds__(kBlock, 2) void k_stripe_queue(
+    const StripeArgs *__restrict__ jobs, const int2 *__restrict__ items, int32_t n_items,
+    int32_t *__restrict__ counter)
+{
+    using SM = StripeSmem<T, DEN, TILE>;
+    __shared__ SM sm;
+    __shared__ int32_t s_item;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+        __syncthreads();
+        const int32_t it = s_item;
+        if (it >= n_items) break;
+        const int2 item = items[it];
+        const StripeArgs a = jobs[item.x];
+        const int32_t kt = item.y % a.tiles_k, stile = item.y / a.tiles_k;
+        const int32_t k0 = kt * SM::TKW, s0 = stile * SM::TSW;
+        if (a.method == UF_WEIGHTED_NORMALIZED)
+            stripe_tile<T, UF_WEIGHTED_NORMALIZED, DEN, TILE>(a, k0, s0, sm);
+        else
+            stripe_tile<T, UF_UNWEIGHTED, DEN, TILE>(a, k0, s0, sm);
+    }
+}
+
+// 1 / total per sample (FP64), for the fused transform.
+__global__ void k_inv_totals(const int32_t *__restrict__ totals, int32_t n, double *__restrict__ inv_t)
+{
+    const int32_t k = blockIdx.x * kBlock + threadIdx.x;
+    if (k < n) inv_t[k] = 1.0 / (double)totals[k];
 }
 
 // D[k] (+)= sum over the batch of L_e * u_k,e in FP64, for the separable denominator.
@@ -213,13 +422,29 @@ inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
 }  // namespace
 
-StripeGeom stripe_geometry(int32_t n, bool fp64)
+template <typename T, int DEN, int TILE>
+static void tile_dims(StripeGeom *g)
+{
+    g->tkw = 64 * StripeCfg<T, DEN, TILE>::TKT;
+    g->tsw = 4 * StripeCfg<T, DEN, TILE>::TST;
+}
+
+StripeGeom stripe_geometry(int32_t n, bool fp64, int32_t den_mode, int32_t tile)
 {
     StripeGeom g;
     g.n = n;
     g.S = n / 2;
-    g.tkw = fp64 ? 64 * StripeCfg<double>::TKT : 64 * StripeCfg<float>::TKT;
-    g.tsw = fp64 ? 4 * StripeCfg<double>::TST : 4 * StripeCfg<float>::TST;
+    const int key = (fp64 ? 4 : 0) + (den_mode ? 2 : 0) + (tile ? 1 : 0);
+    switch (key) {
+    case 0: tile_dims<float, 0, 0>(&g); break;
+    case 1: tile_dims<float, 0, 1>(&g); break;
+    case 2: tile_dims<float, 1, 0>(&g); break;
+    case 3: tile_dims<float, 1, 1>(&g); break;
+    case 4: tile_dims<double, 0, 0>(&g); break;
+    case 5: tile_dims<double, 0, 1>(&g); break;
+    case 6: tile_dims<double, 1, 0>(&g); break;
+    default: tile_dims<double, 1, 1>(&g); break;
+    }
     g.sstride = round_up(n, g.tkw);
     g.spad = (int32_t)round_up(g.S > 0 ? g.S : 1, g.tsw);
     // largest embedding index read: (sstride - tkw) + (spad - tsw) + 1 + (tkw + tsw) - 1
@@ -254,6 +479,83 @@ hipError_t launch_stripe(bool fp64, int32_t method, int32_t den_mode, const void
     if (E <= 0) return hipSuccess;
     if (fp64) return stripe_dispatch<double>(method, den_mode, emb, estride, len, E, num, den, g, first, st);
     return stripe_dispatch<float>(method, den_mode, emb, estride, len, E, num, den, g, first, st);
+}
+
+hipError_t launch_inv_totals(const int32_t *totals, int32_t n, double *inv_t, hipStream_t st)
+{
+    k_inv_totals<<<grid1(n, kBlock), kBlock, 0, st>>>(totals, n, inv_t);
+    return hipGetLastError();
+}
+
+template <typename T, int TILE>
+static hipError_t fused_dispatch(const StripeArgs &a, int32_t den_mode, const StripeGeom &g,
+                                 hipStream_t st)
+{
+    dim3 grid((unsigned)(g.sstride / g.tkw), (unsigned)(g.spad / g.tsw));
+#define UF_FUSED(M, D) k_stripe_fused<T, M, D, TILE><<<grid, kBlock, 0, st>>>(a)
+    if (a.method == UF_WEIGHTED_NORMALIZED) {
+        if (den_mode == 0) UF_FUSED(UF_WEIGHTED_NORMALIZED, 0); else UF_FUSED(UF_WEIGHTED_NORMALIZED, 1);
+    } else {
+        if (den_mode == 0) UF_FUSED(UF_UNWEIGHTED, 0); else UF_FUSED(UF_UNWEIGHTED, 1);
+    }
+#undef UF_FUSED
+    return hipGetLastError();
+}
+
+hipError_t launch_stripe_fused(bool fp64, int32_t method, int32_t den_mode, int32_t tile,
+                               const int32_t *C, int64_t cstride, const double *inv_t,
+                               const double *len, int32_t B, int32_t E, double *num, double *den,
+                               const StripeGeom &g, hipStream_t st)
+{
+    if (B <= 0) return hipSuccess;
+    StripeArgs a = make_stripe_args(method, C, cstride, inv_t, len, B, E, num, den, g);
+    if (fp64) return tile ? fused_dispatch<double, 1>(a, den_mode, g, st) : fused_dispatch<double, 0>(a, den_mode, g, st);
+    return tile ? fused_dispatch<float, 1>(a, den_mode, g, st) : fused_dispatch<float, 0>(a, den_mode, g, st);
+}
+
+StripeArgs make_stripe_args(int32_t method, const int32_t *C, int64_t cstride, const double *inv_t,
+                            const double *len, int32_t B, int32_t E, double *num, double *den,
+                            const StripeGeom &g)
+{
+    StripeArgs a;
+    a.C = C;
+    a.cstride = cstride;
+    a.inv_t = inv_t;
+    a.len = len;
+    a.B = B;
+    a.E = E;
+    a.n = g.n;
+    a.S = g.S;
+    a.num = num;
+    a.den = den;
+    a.sstride = g.sstride;
+    a.method = method;
+    a.tiles_k = (int32_t)(g.sstride / g.tkw);
+    a.tiles_s = g.spad / g.tsw;
+    a.pad = 0;
+    return a;
+}
+
+hipError_t launch_stripe_queue(bool fp64, int32_t den_mode, int32_t tile, const StripeArgs *jobs,
+                               const int32_t *items_xy, int32_t n_items, int32_t *counter,
+                               int32_t n_groups, hipStream_t st)
+{
+    if (n_items <= 0) return hipSuccess;
+    const int2 *it = reinterpret_cast<const int2 *>(items_xy);
+    const int key = (fp64 ? 4 : 0) + (den_mode ? 2 : 0) + (tile ? 1 : 0);
+#define UF_QUEUE(T, D, TL) k_stripe_queue<T, D, TL><<<n_groups, kBlock, 0, st>>>(jobs, it, n_items, counter)
+    switch (key) {
+    case 0: UF_QUEUE(float, 0, 0); break;
+    case 1: UF_QUEUE(float, 0, 1); break;
+    case 2: UF_QUEUE(float, 1, 0); break;
+    case 3: UF_QUEUE(float, 1, 1); break;
+    case 4: UF_QUEUE(double, 0, 0); break;
+    case 5: UF_QUEUE(double, 0, 1); break;
+    case 6: UF_QUEUE(double, 1, 0); break;
+    default: UF_QUEUE(double, 1, 1); break;
+    }
+#undef UF_QUEUE
+    return hipGetLastError();
 }
 
 hipError_t launch_rowdot(int32_t method, const int32_t *C, int64_t cstride, int32_t slot0,

@@ -54,6 +54,20 @@ hipError_t launch_scatter_bits(const int64_t *indptr, const int32_t *entry_slot,
 hipError_t launch_level_or(uint32_t *B, int64_t bstride, int32_t slot_begin, int32_t n_rows,
                            int32_t n_leaf, const int32_t *child_ptr, const int32_t *child_slot,
                            hipStream_t st);
+// Batched propagation over many jobs: mode 0 = int32 counts, 1 = presence bits.
+struct PropJob {
+    uint32_t *X;              // counts (as uint32) or presence words, slot-major rows
+    int64_t stride;           // elements per row (multiple of 4)
+    const int32_t *child_ptr, *child_slot;
+    const int64_t *indptr;
+    const int32_t *entry_slot, *entry_count;
+    int32_t n_leaf, mode, n_samples, pad;
+};
+// tasks_xy: (job, sample) pairs for the scatter; (job, slot) pairs of one level for the gather.
+hipError_t launch_scatter_batched(const PropJob *jobs, const int32_t *tasks_xy, int32_t n_tasks,
+                                  hipStream_t st);
+hipError_t launch_level_batched(const PropJob *jobs, const int32_t *tasks_xy, int32_t n_tasks,
+                                int32_t max_vec, hipStream_t st);
 // out[v][0..width) = src[slot_of_node[v]][0..width), for node-ordered output.
 hipError_t launch_gather_rows_u32(const uint32_t *src, int64_t sstride, const int32_t *slot_of_node,
                                   int32_t n_nodes, int32_t width, uint32_t *out, hipStream_t st);
@@ -67,7 +81,7 @@ struct StripeGeom {
     int32_t spad;            // stripes rounded up to tsw
     int64_t estride;         // embedding row stride
 };
-StripeGeom stripe_geometry(int32_t n, bool fp64);
+StripeGeom stripe_geometry(int32_t n, bool fp64, int32_t den_mode, int32_t tile = 0);
 
 hipError_t launch_transform(bool fp64, int32_t method, const int32_t *C, int64_t cstride,
                             int32_t slot0, int32_t E, const int32_t *totals, int32_t n, int32_t S,
@@ -75,6 +89,31 @@ hipError_t launch_transform(bool fp64, int32_t method, const int32_t *C, int64_t
 hipError_t launch_stripe(bool fp64, int32_t method, int32_t den_mode, const void *emb,
                          int64_t estride, const double *len, int32_t E, double *num, double *den,
                          const StripeGeom &g, bool first, hipStream_t st);
+// Fused transform + striped accumulation over all B branches in one launch (batches of E
+// accumulate in registers; the stripe state, cleared beforehand, is the cross-batch
+// accumulator).  StripeArgs describes one job for the fused and queued kernels.
+struct StripeArgs {
+    const int32_t *C;        // counts [n_nodes][cstride], branch slots first
+    int64_t cstride;
+    const double *inv_t;     // 1 / total per sample
+    const double *len;       // branch length per slot
+    int32_t B, E, n, S;      // branches, batch depth, samples, stripes
+    double *num, *den;       // stripe state [spad][sstride]
+    int64_t sstride;
+    int32_t method, tiles_k, tiles_s, pad;
+};
+StripeArgs make_stripe_args(int32_t method, const int32_t *C, int64_t cstride, const double *inv_t,
+                            const double *len, int32_t B, int32_t E, double *num, double *den,
+                            const StripeGeom &g);
+// items_xy: (job index, tile index) pairs, tile = s_tile * tiles_k + k_tile; *counter == 0.
+hipError_t launch_stripe_queue(bool fp64, int32_t den_mode, int32_t tile, const StripeArgs *jobs,
+                               const int32_t *items_xy, int32_t n_items, int32_t *counter,
+                               int32_t n_groups, hipStream_t st);
+hipError_t launch_inv_totals(const int32_t *totals, int32_t n, double *inv_t, hipStream_t st);
+hipError_t launch_stripe_fused(bool fp64, int32_t method, int32_t den_mode, int32_t tile,
+                               const int32_t *C, int64_t cstride, const double *inv_t,
+                               const double *len, int32_t B, int32_t E, double *num, double *den,
+                               const StripeGeom &g, hipStream_t st);
 // Per-sample sums D_k = sum_b L_b u_kb over a batch (separable denominator).
 hipError_t launch_rowdot(int32_t method, const int32_t *C, int64_t cstride, int32_t slot0,
                          int32_t E, const int32_t *totals, const double *len, int32_t n,
@@ -103,5 +142,20 @@ hipError_t launch_mfma_gemm(const uint8_t *P, const uint16_t *hi, const uint16_t
                             double *S, double *T, hipStream_t st);
 hipError_t launch_mfma_normalize(const double *S, const double *T, int32_t n, int32_t out_f32,
                                  void *out, hipStream_t st);
+// One job of the matrix-core path, for the single-job and queued kernels.
+struct MfmaArgs {
+    const uint8_t *P;           // presence bytes [n_pad][k_pad]
+    int64_t k_pad;
+    int32_t n_kstep, chunk_steps;
+    const uint16_t *hi, *lo;    // bf16 splits [k_pad]
+    int32_t n, n_tiles;
+    double *S, *T;              // condensed shared lengths, per-sample totals
+    const int2 *tiles;          // (I, J) tile list of this job
+};
+MfmaArgs make_mfma_args(const uint8_t *P, const uint16_t *hi, const uint16_t *lo, int32_t k_chunk,
+                        const int32_t *tiles_xy, const MfmaGeom &g, double *S, double *T);
+// items_xy: (job index, tile index) pairs; *counter == 0 at launch.
+hipError_t launch_mfma_queue(const MfmaArgs *jobs, const int32_t *items_xy, int32_t n_items,
+                             int32_t *counter, int32_t n_groups, hipStream_t st);
 
 }  // namespace ufmi

@@ -1,0 +1,166 @@
+// Host runtime objects shared by the C ABI files: device buffers, event profiler, the
+// context and plan structures, and error helpers.
+#pragma once
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "uf_internal.h"
+
+namespace ufmi {
+
+extern thread_local std::string g_tls_err;
+
+// A device allocation that only grows.
+struct DevMem {
+    void *p = nullptr;
+    size_t bytes = 0;
+    hipError_t ensure(size_t want)
+    {
+        if (want == 0) want = 256;
+        if (bytes >= want) return hipSuccess;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+        hipError_t e = hipMalloc(&p, want);
+        if (e == hipSuccess) bytes = want;
+        return e;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <typename T>
+    T *as() const { return static_cast<T *>(p); }
+};
+
+// Event-pair timing of launches, grouped by kernel class.
+struct Profiler {
+    bool on = false;
+    struct Pending {
+        std::string cls;
+        hipEvent_t a, b;
+    };
+    std::vector<hipEvent_t> pool;
+    std::vector<Pending> pending;
+    std::map<std::string, std::pair<int64_t, double>> totals;
+
+    hipEvent_t take()
+    {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    void collect()
+    {
+        for (Pending &p : pending) {
+            float ms = 0.f;
+            if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+                auto &t = totals[p.cls];
+                t.first += 1;
+                t.second += ms;
+            }
+            pool.push_back(p.a);
+            pool.push_back(p.b);
+        }
+        pending.clear();
+    }
+    void release()
+    {
+        collect();
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+        pool.clear();
+    }
+};
+
+}  // namespace ufmi
+
+struct uf_context {
+    int32_t device = 0;
+    std::string err;
+};
+
+struct uf_plan {
+    uf_context *ctx = nullptr;
+    ufmi::HostPrep hp;
+    // resident inputs
+    ufmi::DevMem indptr, entry_slot, entry_count, totals, child_ptr, child_slot, len_slot,
+        slot_of_node;
+    // scratch, allocated on first use
+    ufmi::DevMem counts, bits, emb, num, den, D, inv_t, out_tmp, gather_tmp;
+    ufmi::DevMem mfma_scratch[4];
+    ufmi::Profiler prof;
+    int64_t cstride = 0;  // int32 elements per count row (multiple of 64)
+    int64_t bstride = 0;  // uint32 words per presence row (multiple of 4)
+};
+
+namespace ufmi {
+
+inline uf_status set_err(uf_context *ctx, uf_status code, const std::string &msg)
+{
+    if (ctx)
+        ctx->err = msg;
+    else
+        g_tls_err = msg;
+    return code;
+}
+
+inline uf_status hip_fail(uf_context *ctx, hipError_t e, const char *what)
+{
+    std::string msg = std::string(what) + ": " + hipGetErrorString(e);
+    return set_err(ctx, e == hipErrorOutOfMemory ? UF_E_OOM : UF_E_DEVICE, msg);
+}
+
+#define UF_TRY(expr, what)                                       \
+    do {                                                         \
+        hipError_t _e = (expr);                                  \
+        if (_e != hipSuccess) return hip_fail(ctx, _e, (what));  \
+    } while (0)
+
+template <typename T>
+hipError_t upload(DevMem &m, const std::vector<T> &v, hipStream_t st)
+{
+    hipError_t e = m.ensure(v.size() * sizeof(T));
+    if (e != hipSuccess || v.empty()) return e;
+    return hipMemcpyAsync(m.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st);
+}
+
+inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+// Launch `fn` on `st`, bracketed by timing events when the profiler is on.
+template <typename F>
+hipError_t timed(Profiler &P, const char *cls, hipStream_t st, F &&fn)
+{
+    if (!P.on) return fn();
+    hipEvent_t a = P.take(), b = P.take();
+    if (!a || !b) return fn();
+    hipError_t e = hipEventRecord(a, st);
+    if (e != hipSuccess) return e;
+    e = fn();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(b, st);
+    if (e == hipSuccess) P.pending.push_back({cls, a, b});
+    return e;
+}
+
+template <typename F>
+hipError_t timed(uf_plan *plan, const char *cls, hipStream_t st, F &&fn)
+{
+    return timed(plan->prof, cls, st, fn);
+}
+
+// Plan-level steps reused by the batch runner.
+uf_status propagate_counts(uf_plan *plan, hipStream_t st);
+uf_status propagate_bits(uf_plan *plan, hipStream_t st);
+uf_status plan_prepare(uf_context *ctx, const uf_tree *tree, const uf_table *table,
+                       hipStream_t st, uf_plan **out);
+
+}  // namespace ufmi

@@ -1,0 +1,125 @@
+"""GPU tests of batched execution (many uneven jobs, persistent queues, HIP graph replay)
+through the C ABI, against the FP64 oracle and against single-job plans."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from oracle import oracle
+from synth import batch_job_specs, build_job, config_problem
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5, "mfma_bf16x2": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def uf():
+    import paper_2005_05826_amd as uf
+    return uf
+
+
+@pytest.fixture(scope="module")
+def ctx(uf):
+    return uf.Context(0)
+
+
+def _jobs():
+    # uneven small jobs of the batched workload's kind, covering every path
+    specs = batch_job_specs(n_jobs=6, seed=4242, n_range=(2, 400), tips_range=(200, 3000))
+    kinds = [("weighted_normalized", "fp32"), ("unweighted", "mfma_bf16x2"),
+             ("weighted_normalized", "fp64"), ("unweighted", "fp32"),
+             ("unweighted", "mfma_bf16x2"), ("unweighted", "fp64")]
+    probs = []
+    for spec, (m, p) in zip(specs, kinds):
+        spec["p_nonzero"] = 0.2
+        probs.append((build_job(spec), m, p))
+    probs.append((config_problem(1, n=1, tips=50, p_nonzero=0.5, seed=3), "weighted_normalized", "fp32"))
+    return probs
+
+
+@pytest.fixture(scope="module")
+def jobs():
+    return _jobs()
+
+
+def _outs(jobs, dtype="f64"):
+    import torch
+    td = torch.float64 if dtype == "f64" else torch.float32
+    return [torch.full((max(1, p.n_samples * (p.n_samples - 1) // 2),), -1.0, dtype=td, device="cuda:0")
+            for p, _, _ in jobs]
+
+
+def _want(jobs):
+    return [oracle.problem_condensed(p, oracle.UNWEIGHTED if m == "unweighted" else oracle.WEIGHTED_NORMALIZED)
+            for p, m, _ in jobs]
+
+
+def _check(jobs, outs, want, tag):
+    import torch
+    torch.cuda.synchronize()
+    for (p, m, prec), o, w in zip(jobs, outs, want):
+        got = o.cpu().numpy()[: w.size].astype(np.float64)
+        err = np.abs(got - w).max(initial=0.0)
+        print(f"[{tag}] n={p.n_samples} {m} {prec} max_abs_err={err:.3e}", flush=True)
+        assert err <= TOL[prec], (tag, p.n_samples, m, prec, err)
+
+
+@pytest.mark.parametrize("den_mode", [0, 1])
+def test_batch_matches_oracle(uf, ctx, jobs, den_mode):
+    outs = _outs(jobs)
+    b = uf.Batch(ctx, [dict(problem=p, method=m, precision=pr, out=o) for (p, m, pr), o in zip(jobs, outs)],
+                 tuning=dict(den_mode=den_mode))
+    b.run()
+    _check(jobs, outs, _want(jobs), f"batch den_mode={den_mode}")
+    b.close()
+
+
+def test_batch_equals_single_plans_bitwise(uf, ctx, jobs):
+    outs = _outs(jobs)
+    b = uf.Batch(ctx, [dict(problem=p, method=m, precision=pr, out=o) for (p, m, pr), o in zip(jobs, outs)])
+    b.run()
+    for (p, m, pr), o in zip(jobs, outs):
+        if p.n_samples < 2:
+            continue
+        single = uf.Plan.from_problem(ctx, p).distance(m, pr)
+        np.testing.assert_array_equal(o.cpu().numpy(), single)
+    b.close()
+
+
+def test_graph_replay_matches_eager(uf, ctx, jobs):
+    import torch
+    outs = _outs(jobs, "f32")
+    b = uf.Batch(ctx, [dict(problem=p, method=m, precision=pr, out=o, out_dtype="f32")
+                       for (p, m, pr), o in zip(jobs, outs)])
+    b.run()
+    eager = [o.clone() for o in outs]
+    b.capture()
+    for rep in range(3):
+        for o in outs:
+            o.fill_(-7.0)
+        torch.cuda.synchronize()
+        b.run()
+        for o, e in zip(outs, eager):
+            assert torch.equal(o, e), f"replay {rep} differs from the eager run"
+        # unrelated eager work between replays
+        x = torch.randn(1 << 16, device="cuda:0")
+        (x * 2).sum().item()
+    _check(jobs, outs, _want(jobs), "graph f32 out")
+    b.close()
+
+
+def test_batch_errors(uf, ctx, jobs):
+    import torch
+    p, _, _ = jobs[0]
+    out = torch.empty(p.n_samples * (p.n_samples - 1) // 2, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(uf.UniFracError) as ei:
+        uf.Batch(ctx, [dict(problem=p, method="weighted_normalized", precision="mfma_bf16x2", out=out)])
+    assert ei.value.status_name == "UF_E_UNSUPPORTED"
+    bad = config_problem(1, n=5, tips=40, p_nonzero=0.5, seed=8)
+    bad.parent = bad.parent.copy()
+    bad.parent[0] = bad.parent.shape[0] + 5
+    with pytest.raises(uf.UniFracError) as ei:
+        uf.Batch(ctx, [dict(problem=p, method="unweighted", precision="fp64", out=out),
+                       dict(problem=bad, method="unweighted", precision="fp64", out=out)])
+    assert ei.value.status_name == "UF_E_TREE"

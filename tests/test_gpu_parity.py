@@ -260,3 +260,17 @@ def test_workload2_full_size_sampled(uf, ctx, cfg2, prec):
     want = oracle.problem_pairs(cfg2, oracle.WEIGHTED_NORMALIZED, pi, pj)
     err = _report(f"workload2 WN {prec} sampled", got[condensed_index(n, pi, pj)], want)
     assert err.max() <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("method", [UW, WN])
+@pytest.mark.parametrize("case", ["cfg1_ragged_257", "cfg2_shape_513"])
+def test_separate_transform_variant(uf, ctx, problems, case, method, prec):
+    """variant 1: transform into an embedding buffer, one striped launch per batch"""
+    prob = problems[case]
+    plan = _plan(uf, ctx, prob)
+    want = oracle.problem_condensed(prob, OMETHOD[method])
+    for E in (5, 128):
+        got = plan.distance(method, prec, tuning=dict(variant=1, emb_batch=E))
+        err = _report(f"variant1 E={E} {case} {method} {prec}", got, want)
+        assert err.max() <= TOL[prec]
