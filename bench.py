@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--tips", type=int, default=None, help="override the tip count")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle CPU time")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device-to-device copy 3 times (HBM counter scale)")
     return ap.parse_args()
 
 
@@ -65,6 +67,14 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": src.numel() * 4, "dispatches": 3}))
+        return
     import paper_2005_05826_amd as uf
     from synth import config_problem
 

@@ -191,6 +191,20 @@ uf_status uf_plan_set_profiling(uf_plan *plan, int32_t enable);
 /* Copies up to `cap` classes with at least one launch into `out`; *n_out = classes copied. */
 uf_status uf_plan_get_profile(uf_plan *plan, uf_kernel_stat *out, int32_t cap, int32_t *n_out);
 
+/* Autotuner for the grouping parameters (Section 3: tile and batch sizes decide the run
+ * time).  Times candidate settings of `prec` on this plan's resident inputs with HIP events
+ * (one warm-up, then `reps` calls each; reps <= 0 means 3): striped paths try both tile
+ * shapes with three embedding-batch depths each (FP32 depths stay <= 256 to bound the
+ * FP32 in-batch error), the matrix-core path tries k_chunk 4096, 2048, 1024.  den_mode is
+ * taken from `base` (NULL = 0).  A candidate whose output differs from the first
+ * candidate's by more than the path's tolerance (FP64 1e-12, else 1e-5) is rejected.  The
+ * winner goes to *best (and its milliseconds per call to *best_ms if non-NULL).  With a
+ * non-NULL cache_path the winner is appended to that text file under a key of device
+ * architecture, method, precision, den_mode and log2 size buckets, and a later call with
+ * the same key returns the cached entry without timing.  Uses the default stream. */
+uf_status uf_autotune(uf_plan *plan, uf_method method, uf_precision prec, const uf_tuning *base,
+                      int32_t reps, const char *cache_path, uf_tuning *best, double *best_ms);
+
 /* ---- Batches of independent jobs ------------------------------------------------------
  * Many UniFrac problems of uneven size computed together (the batching of Section 3 taken
  * one level up: many jobs per launch instead of many branches per launch).  Every job is

@@ -18,6 +18,13 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libunifrac_mi.so")
 
+try:
+    # Load torch's HIP runtime first when torch is present: the library then binds to that
+    # same runtime (identical soname), so device tensors and streams are valid in both.
+    import torch  # noqa: F401
+except ImportError:
+    pass
+
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with "
                       "`python -m paper_2005_05826_amd.build` (or __graft_entry__.build())")
@@ -39,7 +46,7 @@ EXPORTED = ["uf_status_string", "uf_last_error", "uf_validate", "uf_context_crea
             "uf_context_destroy", "uf_plan_create", "uf_plan_destroy", "uf_plan_query",
             "uf_plan_embedding_counts", "uf_plan_embedding_presence", "uf_plan_distance",
             "uf_plan_stripes", "uf_plan_trim", "uf_plan_set_profiling",
-            "uf_plan_get_profile", "uf_batch_create", "uf_batch_run", "uf_batch_capture",
+            "uf_plan_get_profile", "uf_autotune", "uf_batch_create", "uf_batch_run", "uf_batch_capture",
             "uf_batch_set_profiling", "uf_batch_get_profile", "uf_batch_destroy",
             "uf_distance_batch", "uf_distance"]
 
@@ -96,6 +103,8 @@ _lib.uf_plan_trim.argtypes = [c_p]
 _lib.uf_plan_set_profiling.argtypes = [c_p, c_i32]
 _lib.uf_plan_get_profile.argtypes = [c_p, ctypes.POINTER(UfKernelStat), c_i32,
                                      ctypes.POINTER(c_i32)]
+_lib.uf_autotune.argtypes = [c_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(UfTuning), c_i32,
+                             ctypes.c_char_p, ctypes.POINTER(UfTuning), ctypes.POINTER(ctypes.c_double)]
 _lib.uf_batch_create.argtypes = [c_p, ctypes.POINTER(UfJob), c_i32, ctypes.POINTER(UfTuning), c_p,
                                  ctypes.POINTER(c_p)]
 _lib.uf_batch_run.argtypes = [c_p, c_p]
@@ -110,7 +119,7 @@ _lib.uf_distance.argtypes = [c_p, ctypes.POINTER(UfTree), ctypes.POINTER(UfTable
 for _name in ("uf_validate", "uf_context_create", "uf_plan_create", "uf_plan_query",
               "uf_plan_embedding_counts", "uf_plan_embedding_presence", "uf_plan_distance",
               "uf_plan_stripes", "uf_plan_trim", "uf_plan_set_profiling",
-              "uf_plan_get_profile", "uf_batch_create", "uf_batch_run", "uf_batch_capture",
+              "uf_plan_get_profile", "uf_autotune", "uf_batch_create", "uf_batch_run", "uf_batch_capture",
               "uf_batch_set_profiling", "uf_batch_get_profile", "uf_distance_batch",
               "uf_distance"):
     getattr(_lib, _name).restype = ctypes.c_int
@@ -286,6 +295,16 @@ class Plan:
 
     def trim(self):
         self.ctx._check(_lib.uf_plan_trim(self._h))
+
+    def autotune(self, method="unweighted", precision="fp64", base=None, reps=3, cache_path=None):
+        """Fastest eligible knobs for this plan: (dict, milliseconds per call)."""
+        best = UfTuning()
+        ms = ctypes.c_double(0)
+        self.ctx._check(_lib.uf_autotune(self._h, METHODS[method], PRECISIONS[precision],
+                                         _tuning(base), int(reps),
+                                         None if cache_path is None else str(cache_path).encode(),
+                                         ctypes.byref(best), ctypes.byref(ms)))
+        return ({f: int(getattr(best, f)) for f, _ in UfTuning._fields_}, float(ms.value))
 
     def set_profiling(self, enable: bool = True):
         self.ctx._check(_lib.uf_plan_set_profiling(self._h, 1 if enable else 0))

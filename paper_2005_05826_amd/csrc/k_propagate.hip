@@ -138,7 +138,37 @@ __global__ void k_level_batched(const PropJob *__restrict__ jobs, const int2 *__
     }
 }
 
+// max |a - b| over n elements into *out (which the launcher clears first).  Non-negative
+// doubles order like their bit patterns, so an integer atomicMax combines work-groups.
+__global__ void k_max_abs_diff(const double *__restrict__ a, const double *__restrict__ b, int64_t n,
+                               unsigned long long *__restrict__ out)
+{
+    __shared__ double red[kBlock];
+    double m = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        const double d = fabs(a[i] - b[i]);
+        m = (d > m || d != d) ? (d != d ? INFINITY : d) : m;
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(out, (unsigned long long)__double_as_longlong(red[0]));
+}
+
 }  // namespace
+
+hipError_t launch_max_abs_diff(const double *a, const double *b, int64_t n, double *out, hipStream_t st)
+{
+    hipError_t e = launch_fill_u32(out, 0u, 2, st);
+    if (e != hipSuccess || n <= 0) return e;
+    size_t blocks = grid1((size_t)n, kBlock * 16);
+    if (blocks > 4096) blocks = 4096;
+    k_max_abs_diff<<<(unsigned)blocks, kBlock, 0, st>>>(a, b, n, reinterpret_cast<unsigned long long *>(out));
+    return hipGetLastError();
+}
 
 hipError_t launch_fill_u32(void *p, uint32_t value, size_t n_words, hipStream_t st)
 {

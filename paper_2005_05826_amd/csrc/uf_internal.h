@@ -39,6 +39,8 @@ uf_status validate_and_prepare(const uf_tree *tree, const uf_table *table, HostP
 
 // All launches are asynchronous on `st` and return the launch status.
 hipError_t launch_fill_u32(void *p, uint32_t value, size_t n_words, hipStream_t st);
+// *out = max_i |a[i] - b[i]| (NaN counts as infinity).
+hipError_t launch_max_abs_diff(const double *a, const double *b, int64_t n, double *out, hipStream_t st);
 
 // Embedding propagation (count form): C is [n_nodes][cstride] int32 in slot order.
 hipError_t launch_scatter_counts(const int64_t *indptr, const int32_t *entry_slot,

@@ -123,3 +123,19 @@ def test_batch_errors(uf, ctx, jobs):
         uf.Batch(ctx, [dict(problem=p, method="unweighted", precision="fp64", out=out),
                        dict(problem=bad, method="unweighted", precision="fp64", out=out)])
     assert ei.value.status_name == "UF_E_TREE"
+
+
+@pytest.mark.parametrize("method,prec", [("weighted_normalized", "fp32"), ("unweighted", "mfma_bf16x2"),
+                                         ("unweighted", "fp64")])
+def test_autotune_picks_valid_knobs_and_caches(uf, ctx, tmp_path, method, prec):
+    prob = config_problem(2, n=700, tips=4000, k=300, depth=1500, seed=77)
+    plan = uf.Plan.from_problem(ctx, prob)
+    cache = tmp_path / "tune.txt"
+    best, ms = plan.autotune(method, prec, reps=2, cache_path=cache)
+    assert ms > 0
+    got = plan.distance(method, prec, tuning=best)
+    want = oracle.problem_condensed(prob, oracle.UNWEIGHTED if method == "unweighted" else oracle.WEIGHTED_NORMALIZED)
+    assert np.abs(got - want).max() <= TOL[prec]
+    best2, ms2 = plan.autotune(method, prec, reps=2, cache_path=cache)   # served from the cache
+    assert best2 == best and ms2 == pytest.approx(ms, rel=1e-5)
+    assert len(cache.read_text().strip().splitlines()) == 1
