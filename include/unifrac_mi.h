@@ -55,8 +55,14 @@ typedef enum {
 /* UniFrac variant.  Unweighted: per pair, branch length seen in exactly one sample over
  * branch length seen in either.  Weighted normalized: per pair, sum over branches of
  * L * |p - q| over sum of L * (p + q), with p, q the fractions of each sample's reads below
- * the branch.  The root has no branch. */
-typedef enum { UF_UNWEIGHTED = 0, UF_WEIGHTED_NORMALIZED = 1 } uf_method;
+ * the branch.  Weighted unnormalized: the numerator sum of L * |p - q| alone (the variant
+ * of the Striped UniFrac work the paper builds on, reference [3]).  The root has no
+ * branch. */
+typedef enum {
+    UF_UNWEIGHTED = 0,
+    UF_WEIGHTED_NORMALIZED = 1,
+    UF_WEIGHTED_UNNORMALIZED = 2
+} uf_method;
 
 /* Arithmetic of the hot path (the fp64 / fp32 code paths of Section 4, plus a matrix-core
  * form of the unweighted variant):
@@ -163,11 +169,23 @@ uf_status uf_plan_embedding_presence(uf_plan *plan, uint32_t *out, int32_t out_o
 
 /* The full hot path on resident inputs: embedding propagation, transform, striped (or
  * matrix-core) accumulation, normalize/condense.  `out` receives n*(n-1)/2 values of
- * `out_dtype` in condensed order.  UF_PREC_MFMA_BF16X2 with UF_WEIGHTED_NORMALIZED returns
+ * `out_dtype` in condensed order.  UF_PREC_MFMA_BF16X2 with a weighted method returns
  * UF_E_UNSUPPORTED.  Device scratch is allocated on first use and kept by the plan. */
 uf_status uf_plan_distance(uf_plan *plan, uf_method method, uf_precision prec,
                            const uf_tuning *tuning, uf_dtype out_dtype, void *out,
                            int32_t out_on_device, void *stream);
+
+/* Stripe-range subproblem: the independent chunks the paper distributes over many chips
+ * (Section 1; Table 2 runs 128 and 4 chunks).  Computes only stripes [s_begin, s_end)
+ * (0 <= s_begin <= s_end <= n/2) and writes the distances of the pairs those stripes hold
+ * into `out`, a FULL condensed array of n*(n-1)/2 elements; all other entries are left
+ * as they were (host outputs are staged through the device to keep them).  Ranges that
+ * partition [0, n/2) fill the whole matrix with exactly the values of uf_plan_distance
+ * (same per-element arithmetic).  Striped precisions only; tuning->variant is ignored. */
+uf_status uf_plan_distance_stripes(uf_plan *plan, uf_method method, uf_precision prec,
+                                   const uf_tuning *tuning, int32_t s_begin, int32_t s_end,
+                                   uf_dtype out_dtype, void *out, int32_t out_on_device,
+                                   void *stream);
 
 /* Raw stripe accumulators of the striped path (for inspection): num and den, each
  * [n_stripes][n_samples] FP64 row-major on the host, where row s, column k holds the sums
@@ -204,6 +222,18 @@ uf_status uf_plan_get_profile(uf_plan *plan, uf_kernel_stat *out, int32_t cap, i
  * the same key returns the cached entry without timing.  Uses the default stream. */
 uf_status uf_autotune(uf_plan *plan, uf_method method, uf_precision prec, const uf_tuning *base,
                       int32_t reps, const char *cache_path, uf_tuning *best, double *best_ms);
+
+/* Mantel test between two condensed matrices (the paper's fp32-vs-fp64 check, Section 4:
+ * Mantel R^2 0.99999).  x, y: DEVICE arrays of n*(n-1)/2 FP64 values in condensed order
+ * (n >= 3).  *r_out = Pearson correlation over all pairs.  perms: DEVICE array of n_perm
+ * rows of n int32, each a permutation of 0..n-1 supplied by the caller (a row that is not
+ * a permutation gives UF_E_ARG); for each row the labels of y are permuted and the
+ * correlation recomputed; *p_out = (1 + #{|r_perm| >= |r|}) / (1 + n_perm) (two-sided;
+ * 1 when n_perm = 0).  r_perm_out (host, n_perm values) may be NULL.  Arithmetic in FP64
+ * with deterministic reductions.  Blocks until done; allocates its own scratch. */
+uf_status uf_mantel(uf_context *ctx, const double *x, const double *y, int32_t n,
+                    const int32_t *perms, int32_t n_perm, double *r_out, double *r_perm_out,
+                    double *p_out, void *stream);
 
 /* ---- Batches of independent jobs ------------------------------------------------------
  * Many UniFrac problems of uneven size computed together (the batching of Section 3 taken

@@ -125,3 +125,26 @@ def subtree_counts(parent, table_rows, feature_node=None):
     ch, root, below = _tips_below(parent)
     rows = _node_table(table_rows, feature_node, len(parent))
     return [[sum(r.get(t, 0) for t in below[v]) for v in range(len(parent))] for r in rows]
+
+
+def weighted_unnormalized(parent, length, table_rows, feature_node=None):
+    """Condensed exact weighted unnormalized UniFrac: sum_b L_b |A_b/A_T - B_b/B_T|."""
+    L = [Fraction(x) for x in length]
+    ch, root, below = _tips_below(parent)
+    rows = _node_table(table_rows, feature_node, len(parent))
+    totals = [sum(r.values()) for r in rows]
+    n = len(rows)
+    out = []
+    for i in range(n):
+        for j in range(i + 1, n):
+            A, B = rows[i], rows[j]
+            AT, BT = Fraction(totals[i]), Fraction(totals[j])
+            u = Fraction(0)
+            for v in range(len(parent)):
+                if v == root:
+                    continue
+                Ab = sum(A.get(t, 0) for t in below[v])
+                Bb = sum(B.get(t, 0) for t in below[v])
+                u += L[v] * abs(Fraction(Ab) / AT - Fraction(Bb) / BT)
+            out.append(u)
+    return out

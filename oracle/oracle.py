@@ -23,6 +23,7 @@ _lib = None
 
 UNWEIGHTED = 0
 WEIGHTED_NORMALIZED = 1
+WEIGHTED_UNNORMALIZED = 2
 
 
 def build(force: bool = True) -> str:

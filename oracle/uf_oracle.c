@@ -18,6 +18,8 @@
  *                          num += L_v * |p - q|
  *                          den += L_v * (p + q)
  *   d_ij = num / den   (0 when den == 0)
+ *   weighted unnormalized (the variant of the Striped UniFrac work the paper builds on,
+ *   its reference [3]): d_ij = num of the weighted normalized form, no division
  *
  * Counts come from walking every tip's reads up its ancestor chain (deliberately unlike a
  * level-by-level gather).  Both sums are Neumaier-compensated, branches are visited in
@@ -78,7 +80,8 @@ static inline void neumaier_add(double *sum, double *comp, double x)
 }
 
 /* Distances for the pairs (a[p], b[p]) of rows of `rows` (the [n_rows][n_nodes] walk-up
- * counts) with totals tot[row].  method 0 = unweighted, 1 = weighted normalized.
+ * counts) with totals tot[row].  method 0 = unweighted, 1 = weighted normalized,
+ * 2 = weighted unnormalized.
  * n_threads <= 0 uses the OpenMP default.  Returns an OR_* code. */
 int uf_oracle_pairs(int32_t n_nodes, const int32_t *parent, const double *length,
                     int32_t n_rows, const int64_t *rows, const int64_t *tot, int32_t method,
@@ -86,7 +89,7 @@ int uf_oracle_pairs(int32_t n_nodes, const int32_t *parent, const double *length
                     int32_t n_threads)
 {
     if (n_nodes < 1 || !parent || !length || !rows || !out || n_pairs < 0) return OR_E_ARG;
-    if (method != 0 && method != 1) return OR_E_ARG;
+    if (method < 0 || method > 2) return OR_E_ARG;
     for (int64_t p = 0; p < n_pairs; ++p)
         if (a[p] < 0 || a[p] >= n_rows || b[p] < 0 || b[p] >= n_rows) return OR_E_ARG;
 #ifdef _OPENMP
@@ -120,7 +123,10 @@ int uf_oracle_pairs(int32_t n_nodes, const int32_t *parent, const double *length
             }
         }
         double N = num + num_c, D = den + den_c;
-        out[p] = (D == 0.0) ? 0.0 : N / D;
+        if (method == 2)
+            out[p] = N;
+        else
+            out[p] = (D == 0.0) ? 0.0 : N / D;
     }
     return OR_OK;
 }

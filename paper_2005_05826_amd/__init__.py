@@ -15,6 +15,7 @@ from .binding import (  # noqa: F401
     UniFracError,
     distance,
     library,
+    mantel,
     validate,
     validate_problem,
 )

@@ -37,7 +37,7 @@ UF_OK = 0
 STATUS_NAMES = {0: "UF_OK", 1: "UF_E_ARG", 2: "UF_E_TREE", 3: "UF_E_TABLE",
                 4: "UF_E_EMPTY_SAMPLE", 5: "UF_E_DEVICE", 6: "UF_E_OOM",
                 7: "UF_E_UNSUPPORTED", 8: "UF_E_INTERNAL"}
-METHODS = {"unweighted": 0, "weighted_normalized": 1}
+METHODS = {"unweighted": 0, "weighted_normalized": 1, "weighted_unnormalized": 2}
 PRECISIONS = {"fp64": 0, "fp32": 1, "mfma_bf16x2": 2}
 DTYPES = {"f64": 0, "f32": 1}
 
@@ -45,10 +45,10 @@ DTYPES = {"f64": 0, "f32": 1}
 EXPORTED = ["uf_status_string", "uf_last_error", "uf_validate", "uf_context_create",
             "uf_context_destroy", "uf_plan_create", "uf_plan_destroy", "uf_plan_query",
             "uf_plan_embedding_counts", "uf_plan_embedding_presence", "uf_plan_distance",
-            "uf_plan_stripes", "uf_plan_trim", "uf_plan_set_profiling",
+            "uf_plan_distance_stripes", "uf_plan_stripes", "uf_plan_trim", "uf_plan_set_profiling",
             "uf_plan_get_profile", "uf_autotune", "uf_batch_create", "uf_batch_run", "uf_batch_capture",
             "uf_batch_set_profiling", "uf_batch_get_profile", "uf_batch_destroy",
-            "uf_distance_batch", "uf_distance"]
+            "uf_distance_batch", "uf_mantel", "uf_distance"]
 
 
 class UfTree(ctypes.Structure):
@@ -97,6 +97,8 @@ _lib.uf_plan_embedding_counts.argtypes = [c_p, c_p, c_i32, c_p]
 _lib.uf_plan_embedding_presence.argtypes = [c_p, c_p, c_i32, c_p]
 _lib.uf_plan_distance.argtypes = [c_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(UfTuning),
                                   ctypes.c_int, c_p, c_i32, c_p]
+_lib.uf_plan_distance_stripes.argtypes = [c_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(UfTuning),
+                                          c_i32, c_i32, ctypes.c_int, c_p, c_i32, c_p]
 _lib.uf_plan_stripes.argtypes = [c_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(UfTuning),
                                  c_p, c_p, c_p]
 _lib.uf_plan_trim.argtypes = [c_p]
@@ -114,11 +116,14 @@ _lib.uf_batch_get_profile.argtypes = [c_p, ctypes.POINTER(UfKernelStat), c_i32, 
 _lib.uf_batch_destroy.argtypes = [c_p]
 _lib.uf_batch_destroy.restype = None
 _lib.uf_distance_batch.argtypes = [c_p, ctypes.POINTER(UfJob), c_i32, c_p]
+_lib.uf_mantel.argtypes = [c_p, c_p, c_p, c_i32, c_p, c_i32, ctypes.POINTER(ctypes.c_double),
+                           c_p, ctypes.POINTER(ctypes.c_double), c_p]
+_lib.uf_mantel.restype = ctypes.c_int
 _lib.uf_distance.argtypes = [c_p, ctypes.POINTER(UfTree), ctypes.POINTER(UfTable), ctypes.c_int,
                              ctypes.c_int, ctypes.c_int, c_p, c_i32, c_p]
 for _name in ("uf_validate", "uf_context_create", "uf_plan_create", "uf_plan_query",
               "uf_plan_embedding_counts", "uf_plan_embedding_presence", "uf_plan_distance",
-              "uf_plan_stripes", "uf_plan_trim", "uf_plan_set_profiling",
+              "uf_plan_distance_stripes", "uf_plan_stripes", "uf_plan_trim", "uf_plan_set_profiling",
               "uf_plan_get_profile", "uf_autotune", "uf_batch_create", "uf_batch_run", "uf_batch_capture",
               "uf_batch_set_profiling", "uf_batch_get_profile", "uf_distance_batch",
               "uf_distance"):
@@ -284,6 +289,19 @@ class Plan:
                                               _stream_handle(stream)))
         return out
 
+    def distance_stripes(self, s_begin, s_end, out, method="unweighted", precision="fp64",
+                         out_dtype="f64", tuning=None, stream=None):
+        """Fill the pairs of stripes [s_begin, s_end) into `out` (full condensed array)."""
+        if isinstance(out, np.ndarray):
+            ptr, on_dev = _ptr(out), 0
+        else:
+            ptr, on_dev = c_p(out.data_ptr()), 1
+        self.ctx._check(_lib.uf_plan_distance_stripes(self._h, METHODS[method], PRECISIONS[precision],
+                                                      _tuning(tuning), int(s_begin), int(s_end),
+                                                      DTYPES[out_dtype], ptr, on_dev,
+                                                      _stream_handle(stream)))
+        return out
+
     def stripes(self, method="unweighted", precision="fp64", tuning=None, stream=None):
         S, n = self.info.n_stripes, self.info.n_samples
         num = np.empty((S, n), np.float64)
@@ -391,3 +409,16 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def mantel(ctx: Context, x, y, n: int, perms=None, stream=None):
+    """Mantel test of two condensed FP64 device tensors; perms: device int32 tensor
+    [n_perm][n] of permutations (or None).  Returns (r, p_value, r_perm numpy array)."""
+    n_perm = 0 if perms is None else int(perms.shape[0])
+    r = ctypes.c_double(0)
+    p = ctypes.c_double(0)
+    rp = np.empty(max(n_perm, 1), np.float64)
+    ctx._check(_lib.uf_mantel(ctx.handle, c_p(x.data_ptr()), c_p(y.data_ptr()), int(n),
+                              None if perms is None else c_p(perms.data_ptr()), n_perm,
+                              ctypes.byref(r), _ptr(rp), ctypes.byref(p), _stream_handle(stream)))
+    return float(r.value), float(p.value), rp[:n_perm]

@@ -139,17 +139,29 @@ Knobs resolve_knobs(const uf_tuning *t, uf_precision prec, int32_t n_branches)
 }
 
 // (a)-(b): fills plan->num / den (den_mode 0) or num / D (den_mode 1).
+// Stripes [s_begin, s_end) (-1, -1 = all): the state block covers the stripe tiles that
+// overlap the range and *s_base receives the stripe held by its first row.
 uf_status run_striped(uf_plan *plan, uf_method method, uf_precision prec, const Knobs &kn,
-                      StripeGeom *geom, hipStream_t st)
+                      StripeGeom *geom, hipStream_t st, int32_t s_begin = -1, int32_t s_end = -1,
+                      int32_t *s_base = nullptr)
 {
     uf_context *ctx = plan->ctx;
     const HostPrep &hp = plan->hp;
     const bool fp64 = (prec == UF_PREC_FP64);
+    // the unnormalized variant accumulates the weighted-normalized numerator only
+    const bool unnorm = (method == UF_WEIGHTED_UNNORMALIZED);
+    if (unnorm) method = UF_WEIGHTED_NORMALIZED;
     const StripeGeom g = stripe_geometry(hp.n_samples, fp64, kn.den_mode, kn.variant == 0 ? kn.tile : 0);
     *geom = g;
+    int32_t tile_s0 = 0, tile_s1 = g.spad / g.tsw;
+    if (s_begin >= 0) {
+        tile_s0 = s_begin / g.tsw;
+        tile_s1 = (s_end + g.tsw - 1) / g.tsw;
+    }
+    if (s_base) *s_base = tile_s0 * g.tsw;
     const int32_t B = hp.n_nodes - 1;
     const size_t tsz = fp64 ? sizeof(double) : sizeof(float);
-    const size_t state = (size_t)g.spad * g.sstride * sizeof(double);
+    const size_t state = (size_t)(tile_s1 - tile_s0) * g.tsw * g.sstride * sizeof(double);
     UF_TRY(plan->num.ensure(state), "allocating numerator stripes");
     if (kn.den_mode == 0) UF_TRY(plan->den.ensure(state), "allocating denominator stripes");
     UF_TRY(plan->D.ensure((size_t)hp.n_samples * sizeof(double)), "allocating per-sample sums");
@@ -176,9 +188,10 @@ uf_status run_striped(uf_plan *plan, uf_method method, uf_precision prec, const 
                "reciprocal totals");
         UF_TRY(timed(plan, "stripe", st, [&] {
                    return launch_stripe_fused(fp64, method, kn.den_mode, kn.tile, C, plan->cstride,
-                                              plan->inv_t.as<double>(), len, B, E, num, den, g, st);
+                                              plan->inv_t.as<double>(), len, B, E, num, den, g,
+                                              tile_s0, tile_s1, st);
                }), "striped accumulation");
-        if (kn.den_mode != 0)
+        if (kn.den_mode != 0 && !unnorm)
             UF_TRY(timed(plan, "rowdot", st, [&] {
                        return launch_rowdot(method, C, plan->cstride, 0, B,
                                             plan->totals.as<int32_t>(), len, g.n, D, true, st);
@@ -197,7 +210,7 @@ uf_status run_striped(uf_plan *plan, uf_method method, uf_precision prec, const 
                    return launch_stripe(fp64, method, kn.den_mode, plan->emb.p, g.estride,
                                         len + b0, eb, num, den, g, b0 == 0, st);
                }), "striped accumulation");
-        if (kn.den_mode != 0)
+        if (kn.den_mode != 0 && !unnorm)
             UF_TRY(timed(plan, "rowdot", st, [&] {
                        return launch_rowdot(method, C, plan->cstride, b0, eb,
                                             plan->totals.as<int32_t>(), len + b0, g.n, D,
@@ -209,7 +222,8 @@ uf_status run_striped(uf_plan *plan, uf_method method, uf_precision prec, const 
 
 uf_status check_enums(uf_context *ctx, uf_method method, uf_precision prec)
 {
-    if (method != UF_UNWEIGHTED && method != UF_WEIGHTED_NORMALIZED)
+    if (method != UF_UNWEIGHTED && method != UF_WEIGHTED_NORMALIZED &&
+        method != UF_WEIGHTED_UNNORMALIZED)
         return set_err(ctx, UF_E_ARG, "unknown method");
     if (prec != UF_PREC_FP64 && prec != UF_PREC_FP32 && prec != UF_PREC_MFMA_BF16X2)
         return set_err(ctx, UF_E_ARG, "unknown precision");
@@ -427,9 +441,10 @@ uf_status uf_plan_distance(uf_plan *plan, uf_method method, uf_precision prec,
     const int64_t n_pairs = (int64_t)hp.n_samples * (hp.n_samples - 1) / 2;
     if (n_pairs == 0) return UF_OK;
     if (!out) return set_err(ctx, UF_E_ARG, "out must not be NULL");
-    const Knobs kn = resolve_knobs(tuning, prec, hp.n_nodes - 1);
+    Knobs kn = resolve_knobs(tuning, prec, hp.n_nodes - 1);
     if (kn.den_mode != 0 && kn.den_mode != 1) return set_err(ctx, UF_E_ARG, "den_mode must be 0 or 1");
     if (kn.variant != 0 && kn.variant != 1) return set_err(ctx, UF_E_ARG, "variant must be 0 or 1");
+    if (method == UF_WEIGHTED_UNNORMALIZED) kn.den_mode = 1;   // no denominator at all
     if (kn.tile != 0 && kn.tile != 1) return set_err(ctx, UF_E_ARG, "tile must be 0 or 1");
     UF_TRY(hipSetDevice(ctx->device), "hipSetDevice");
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -453,6 +468,59 @@ uf_status uf_plan_distance(uf_plan *plan, uf_method method, uf_precision prec,
                                           g.sstride, g.n, g.S, out_dtype == UF_F32, dst, st);
                }), "condense");
     }
+    if (!out_on_device)
+        UF_TRY(hipMemcpyAsync(out, dst, (size_t)n_pairs * esz, hipMemcpyDeviceToHost, st),
+               "copying distances out");
+    UF_TRY(hipStreamSynchronize(st), "synchronizing");
+    if (plan->prof.on) plan->prof.collect();
+    return UF_OK;
+}
+
+uf_status uf_plan_distance_stripes(uf_plan *plan, uf_method method, uf_precision prec,
+                                   const uf_tuning *tuning, int32_t s_begin, int32_t s_end,
+                                   uf_dtype out_dtype, void *out, int32_t out_on_device,
+                                   void *stream)
+{
+    if (!plan) return set_err(nullptr, UF_E_ARG, "plan must not be NULL");
+    uf_context *ctx = plan->ctx;
+    uf_status s = check_enums(ctx, method, prec);
+    if (s != UF_OK) return s;
+    if (prec == UF_PREC_MFMA_BF16X2)
+        return set_err(ctx, UF_E_ARG, "stripe ranges exist for the striped precisions only");
+    if (out_dtype != UF_F64 && out_dtype != UF_F32) return set_err(ctx, UF_E_ARG, "unknown dtype");
+    const HostPrep &hp = plan->hp;
+    const int32_t S = hp.n_samples / 2;
+    if (s_begin < 0 || s_end > S || s_begin > s_end)
+        return set_err(ctx, UF_E_ARG, "stripe range must satisfy 0 <= s_begin <= s_end <= n/2");
+    if (s_begin == s_end) return UF_OK;
+    if (!out) return set_err(ctx, UF_E_ARG, "out must not be NULL");
+    Knobs kn = resolve_knobs(tuning, prec, hp.n_nodes - 1);
+    if (kn.den_mode != 0 && kn.den_mode != 1) return set_err(ctx, UF_E_ARG, "den_mode must be 0 or 1");
+    if (kn.tile != 0 && kn.tile != 1) return set_err(ctx, UF_E_ARG, "tile must be 0 or 1");
+    kn.variant = 0;
+    if (method == UF_WEIGHTED_UNNORMALIZED) kn.den_mode = 1;
+    UF_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t n_pairs = (int64_t)hp.n_samples * (hp.n_samples - 1) / 2;
+    const size_t esz = out_dtype == UF_F32 ? sizeof(float) : sizeof(double);
+    void *dst = out;
+    if (!out_on_device) {   // staging keeps the entries this range does not write
+        UF_TRY(plan->out_tmp.ensure((size_t)n_pairs * esz), "allocating output staging");
+        dst = plan->out_tmp.p;
+        UF_TRY(hipMemcpyAsync(dst, out, (size_t)n_pairs * esz, hipMemcpyHostToDevice, st),
+               "staging output");
+    }
+    StripeGeom g;
+    int32_t s_base = 0;
+    s = run_striped(plan, method, prec, kn, &g, st, s_begin, s_end, &s_base);
+    if (s != UF_OK) return s;
+    UF_TRY(timed(plan, "condense", st, [&] {
+               return launch_condense_range(method, plan->num.as<double>(),
+                                            kn.den_mode == 0 ? plan->den.as<double>() : nullptr,
+                                            kn.den_mode == 0 ? nullptr : plan->D.as<double>(),
+                                            g.sstride, g.n, g.S, s_base, s_begin, s_end,
+                                            out_dtype == UF_F32, dst, st);
+           }), "condense");
     if (!out_on_device)
         UF_TRY(hipMemcpyAsync(out, dst, (size_t)n_pairs * esz, hipMemcpyDeviceToHost, st),
                "copying distances out");
@@ -502,6 +570,8 @@ uf_status uf_plan_stripes(uf_plan *plan, uf_method method, uf_precision prec,
     const HostPrep &hp = plan->hp;
     Knobs kn = resolve_knobs(tuning, prec, hp.n_nodes - 1);
     if (kn.den_mode != 0) return set_err(ctx, UF_E_ARG, "stripes need den_mode 0");
+    if (method == UF_WEIGHTED_UNNORMALIZED)
+        return set_err(ctx, UF_E_ARG, "the unnormalized variant has no denominator stripes");
     if (hp.n_samples / 2 == 0) return UF_OK;
     UF_TRY(hipSetDevice(ctx->device), "hipSetDevice");
     hipStream_t st = static_cast<hipStream_t>(stream);

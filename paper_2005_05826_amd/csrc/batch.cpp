@@ -99,7 +99,7 @@ uf_status enqueue(uf_batch *b, hipStream_t st)
         uf_plan *p = b->plans[j];
         const uf_job &J = b->jobs[j];
         const StripeGeom g = stripe_geometry(p->hp.n_samples, J.prec == UF_PREC_FP64, b->den_mode, b->tile);
-        if (b->den_mode != 0)
+        if (b->den_mode != 0 && J.method != UF_WEIGHTED_UNNORMALIZED)
             UF_TRY(launch_rowdot(J.method, p->counts.as<int32_t>(), p->cstride, 0, p->hp.n_nodes - 1,
                                  p->totals.as<int32_t>(), p->len_slot.as<double>(), g.n,
                                  p->D.as<double>(), true, st), "per-sample sums");
@@ -231,7 +231,9 @@ uf_status build_tables(uf_batch *b, hipStream_t st)
             E = std::max(1, std::min(E, std::max(1, hp.n_nodes - 1)));
             const int32_t idx = (int32_t)sj.size();
             b->stripe_of_job[j] = idx;
-            sj.push_back(make_stripe_args(J.method, p->counts.as<int32_t>(), p->cstride,
+            // the unnormalized variant runs the weighted-normalized numerator
+            const int32_t km = J.method == UF_WEIGHTED_UNNORMALIZED ? UF_WEIGHTED_NORMALIZED : J.method;
+            sj.push_back(make_stripe_args(km, p->counts.as<int32_t>(), p->cstride,
                                           p->inv_t.as<double>(), p->len_slot.as<double>(),
                                           hp.n_nodes - 1, E, p->num.as<double>(),
                                           b->den_mode == 0 ? p->den.as<double>() : nullptr, g));
@@ -312,7 +314,8 @@ uf_status uf_batch_create(uf_context *ctx, const uf_job *jobs, int32_t n_jobs,
     *out = nullptr;
     for (int32_t j = 0; j < n_jobs; ++j) {
         const uf_job &J = jobs[j];
-        if (J.method != UF_UNWEIGHTED && J.method != UF_WEIGHTED_NORMALIZED)
+        if (J.method != UF_UNWEIGHTED && J.method != UF_WEIGHTED_NORMALIZED &&
+            J.method != UF_WEIGHTED_UNNORMALIZED)
             return set_err(ctx, UF_E_ARG, "job has an unknown method");
         if (J.prec != UF_PREC_FP64 && J.prec != UF_PREC_FP32 && J.prec != UF_PREC_MFMA_BF16X2)
             return set_err(ctx, UF_E_ARG, "job has an unknown precision");

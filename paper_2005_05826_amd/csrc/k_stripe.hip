@@ -291,7 +291,7 @@ __device__ void stripe_tile(const StripeArgs &a, int32_t k0, int32_t s0, StripeS
             }
         }
         add_tile<TST, TKT, DEN>(an, ad, a.num, a.den,
-                                (int64_t)(s0 + w * TST) * sstride + k0 + lane * TKT, sstride);
+                                (int64_t)(s0 - a.s_base + w * TST) * sstride + k0 + lane * TKT, sstride);
     }
 }
 
@@ -300,7 +300,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_stripe_fused(StripeArgs a)
 {
     using SM = StripeSmem<T, DEN, TILE>;
     __shared__ SM sm;
-    stripe_tile<T, METHOD, DEN, TILE>(a, blockIdx.x * SM::TKW, blockIdx.y * SM::TSW, sm);
+    stripe_tile<T, METHOD, DEN, TILE>(a, blockIdx.x * SM::TKW, a.s_base + blockIdx.y * SM::TSW, sm);
 }
 
 // Persistent form for many jobs: every work-group takes items (job, tile) from a global
@@ -325,7 +325,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_stripe_queue(
         const int2 item = items[it];
         const StripeArgs a = jobs[item.x];
         const int32_t kt = item.y % a.tiles_k, stile = item.y / a.tiles_k;
-        const int32_t k0 = kt * SM::TKW, s0 = stile * SM::TSW;
+        const int32_t k0 = kt * SM::TKW, s0 = a.s_base + stile * SM::TSW;
         if (a.method == UF_WEIGHTED_NORMALIZED)
             stripe_tile<T, UF_WEIGHTED_NORMALIZED, DEN, TILE>(a, k0, s0, sm);
         else
@@ -382,16 +382,53 @@ __global__ void k_condense(const double *__restrict__ num, const double *__restr
         }
         const int64_t at = (int64_t)s * sstride + k;
         const double a = num[at];
+        double d;
+        if (METHOD == UF_WEIGHTED_UNNORMALIZED) {
+            d = a;
+        } else {
+            double b;
+            if (D == nullptr)
+                b = den[at];
+            else if (METHOD == UF_WEIGHTED_NORMALIZED)
+                b = D[i] + D[j];
+            else
+                b = 0.5 * (D[i] + D[j] + a);
+            d = (b == 0.0) ? 0.0 : a / b;
+        }
+        out[row0 + j] = (OUT)d;
+    }
+}
+
+// Condense of a stripe range [s_begin, s_end) held in a state block whose first row is
+// stripe s_base: each (s, k) writes the pair (k, (k + s + 1) mod n) into the condensed
+// output (for even n the last stripe writes only k < n/2, the first copy of each pair).
+template <int METHOD, typename OUT>
+__global__ void k_condense_range(const double *__restrict__ num, const double *__restrict__ den,
+                                 const double *__restrict__ D, int64_t sstride, int32_t n, int32_t S,
+                                 int32_t s_base, int32_t s_begin, OUT *__restrict__ out)
+{
+    const int32_t s = s_begin + blockIdx.y;
+    const int32_t k = blockIdx.x * kBlock + threadIdx.x;
+    const int32_t kmax = (n % 2 == 0 && s == S - 1) ? n / 2 : n;
+    if (k >= kmax) return;
+    const int32_t j = (k + s + 1) % n;
+    const int32_t lo = k < j ? k : j, hi = k < j ? j : k;
+    const int64_t at = (int64_t)(s - s_base) * sstride + k;
+    const double a = num[at];
+    double d;
+    if (METHOD == UF_WEIGHTED_UNNORMALIZED) {
+        d = a;
+    } else {
         double b;
         if (D == nullptr)
             b = den[at];
         else if (METHOD == UF_WEIGHTED_NORMALIZED)
-            b = D[i] + D[j];
+            b = D[k] + D[j];
         else
-            b = 0.5 * (D[i] + D[j] + a);
-        const double d = (b == 0.0) ? 0.0 : a / b;
-        out[row0 + j] = (OUT)d;
+            b = 0.5 * (D[k] + D[j] + a);
+        d = (b == 0.0) ? 0.0 : a / b;
     }
+    out[(int64_t)n * lo - (int64_t)lo * (lo + 1) / 2 + (hi - lo - 1)] = (OUT)d;
 }
 
 inline unsigned grid1(int64_t n, int64_t per) { return (unsigned)((n + per - 1) / per); }
@@ -491,7 +528,7 @@ template <typename T, int TILE>
 static hipError_t fused_dispatch(const StripeArgs &a, int32_t den_mode, const StripeGeom &g,
                                  hipStream_t st)
 {
-    dim3 grid((unsigned)(g.sstride / g.tkw), (unsigned)(g.spad / g.tsw));
+    dim3 grid((unsigned)a.tiles_k, (unsigned)a.tiles_s);
 #define UF_FUSED(M, D) k_stripe_fused<T, M, D, TILE><<<grid, kBlock, 0, st>>>(a)
     if (a.method == UF_WEIGHTED_NORMALIZED) {
         if (den_mode == 0) UF_FUSED(UF_WEIGHTED_NORMALIZED, 0); else UF_FUSED(UF_WEIGHTED_NORMALIZED, 1);
@@ -505,10 +542,12 @@ static hipError_t fused_dispatch(const StripeArgs &a, int32_t den_mode, const St
 hipError_t launch_stripe_fused(bool fp64, int32_t method, int32_t den_mode, int32_t tile,
                                const int32_t *C, int64_t cstride, const double *inv_t,
                                const double *len, int32_t B, int32_t E, double *num, double *den,
-                               const StripeGeom &g, hipStream_t st)
+                               const StripeGeom &g, int32_t tile_s0, int32_t tile_s1, hipStream_t st)
 {
-    if (B <= 0) return hipSuccess;
+    if (B <= 0 || tile_s1 <= tile_s0) return hipSuccess;
     StripeArgs a = make_stripe_args(method, C, cstride, inv_t, len, B, E, num, den, g);
+    a.s_base = tile_s0 * g.tsw;
+    a.tiles_s = tile_s1 - tile_s0;
     if (fp64) return tile ? fused_dispatch<double, 1>(a, den_mode, g, st) : fused_dispatch<double, 0>(a, den_mode, g, st);
     return tile ? fused_dispatch<float, 1>(a, den_mode, g, st) : fused_dispatch<float, 0>(a, den_mode, g, st);
 }
@@ -532,7 +571,7 @@ StripeArgs make_stripe_args(int32_t method, const int32_t *C, int64_t cstride, c
     a.method = method;
     a.tiles_k = (int32_t)(g.sstride / g.tkw);
     a.tiles_s = g.spad / g.tsw;
-    a.pad = 0;
+    a.s_base = 0;
     return a;
 }
 
@@ -575,7 +614,12 @@ hipError_t launch_condense(int32_t method, const double *num, const double *den,
                            hipStream_t st)
 {
     if (n < 2) return hipSuccess;
-    if (method == UF_WEIGHTED_NORMALIZED) {
+    if (method == UF_WEIGHTED_UNNORMALIZED) {
+        if (out_f32)
+            k_condense<UF_WEIGHTED_UNNORMALIZED, float><<<n - 1, kBlock, 0, st>>>(num, den, D, sstride, n, S, (float *)out);
+        else
+            k_condense<UF_WEIGHTED_UNNORMALIZED, double><<<n - 1, kBlock, 0, st>>>(num, den, D, sstride, n, S, (double *)out);
+    } else if (method == UF_WEIGHTED_NORMALIZED) {
         if (out_f32)
             k_condense<UF_WEIGHTED_NORMALIZED, float><<<n - 1, kBlock, 0, st>>>(num, den, D, sstride, n, S, (float *)out);
         else
@@ -586,6 +630,29 @@ hipError_t launch_condense(int32_t method, const double *num, const double *den,
         else
             k_condense<UF_UNWEIGHTED, double><<<n - 1, kBlock, 0, st>>>(num, den, D, sstride, n, S, (double *)out);
     }
+    return hipGetLastError();
+}
+
+}  // namespace ufmi
+
+namespace ufmi {
+
+hipError_t launch_condense_range(int32_t method, const double *num, const double *den, const double *D,
+                                 int64_t sstride, int32_t n, int32_t S, int32_t s_base,
+                                 int32_t s_begin, int32_t s_end, int32_t out_f32, void *out,
+                                 hipStream_t st)
+{
+    if (s_end <= s_begin || n < 2) return hipSuccess;
+    dim3 grid(grid1(n, kBlock), (unsigned)(s_end - s_begin));
+#define UF_CR(M, O) k_condense_range<M, O><<<grid, kBlock, 0, st>>>(num, den, D, sstride, n, S, s_base, s_begin, (O *)out)
+    if (method == UF_WEIGHTED_UNNORMALIZED) {
+        if (out_f32) UF_CR(UF_WEIGHTED_UNNORMALIZED, float); else UF_CR(UF_WEIGHTED_UNNORMALIZED, double);
+    } else if (method == UF_WEIGHTED_NORMALIZED) {
+        if (out_f32) UF_CR(UF_WEIGHTED_NORMALIZED, float); else UF_CR(UF_WEIGHTED_NORMALIZED, double);
+    } else {
+        if (out_f32) UF_CR(UF_UNWEIGHTED, float); else UF_CR(UF_UNWEIGHTED, double);
+    }
+#undef UF_CR
     return hipGetLastError();
 }
 

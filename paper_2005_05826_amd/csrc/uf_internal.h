@@ -102,7 +102,7 @@ struct StripeArgs {
     int32_t B, E, n, S;      // branches, batch depth, samples, stripes
     double *num, *den;       // stripe state [spad][sstride]
     int64_t sstride;
-    int32_t method, tiles_k, tiles_s, pad;
+    int32_t method, tiles_k, tiles_s, s_base;   // s_base: stripe held by state row 0
 };
 StripeArgs make_stripe_args(int32_t method, const int32_t *C, int64_t cstride, const double *inv_t,
                             const double *len, int32_t B, int32_t E, double *num, double *den,
@@ -112,10 +112,17 @@ hipError_t launch_stripe_queue(bool fp64, int32_t den_mode, int32_t tile, const 
                                const int32_t *items_xy, int32_t n_items, int32_t *counter,
                                int32_t n_groups, hipStream_t st);
 hipError_t launch_inv_totals(const int32_t *totals, int32_t n, double *inv_t, hipStream_t st);
+// Covers stripe tiles [tile_s0, tile_s1); state row 0 holds stripe tile_s0 * tsw.
 hipError_t launch_stripe_fused(bool fp64, int32_t method, int32_t den_mode, int32_t tile,
                                const int32_t *C, int64_t cstride, const double *inv_t,
                                const double *len, int32_t B, int32_t E, double *num, double *den,
-                               const StripeGeom &g, hipStream_t st);
+                               const StripeGeom &g, int32_t tile_s0, int32_t tile_s1, hipStream_t st);
+// Writes the pairs of stripes [s_begin, s_end) into a full condensed output; the state
+// block's row 0 holds stripe s_base.
+hipError_t launch_condense_range(int32_t method, const double *num, const double *den, const double *D,
+                                 int64_t sstride, int32_t n, int32_t S, int32_t s_base,
+                                 int32_t s_begin, int32_t s_end, int32_t out_f32, void *out,
+                                 hipStream_t st);
 // Per-sample sums D_k = sum_b L_b u_kb over a batch (separable denominator).
 hipError_t launch_rowdot(int32_t method, const int32_t *C, int64_t cstride, int32_t slot0,
                          int32_t E, const int32_t *totals, const double *len, int32_t n,

@@ -21,4 +21,5 @@ from .generators import (  # noqa: F401
     batch_job_specs,
     CONFIGS,
     build_job,
+    permutations,
 )

@@ -342,3 +342,10 @@ def batch_job_specs(n_jobs: int = 64, seed: int | None = None, n_range=(200, 800
 
 def build_job(spec: dict) -> Problem:
     return _build(spec, make_rng(spec["seed"]))
+
+
+def permutations(n: int, n_perm: int, seed: int) -> np.ndarray:
+    """[n_perm][n] int32, each row a uniform random permutation of 0..n-1."""
+    rng = make_rng(seed)
+    return np.stack([rng.permutation(n) for _ in range(n_perm)]).astype(np.int32) if n_perm \
+        else np.zeros((0, n), np.int32)

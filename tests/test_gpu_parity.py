@@ -274,3 +274,60 @@ def test_separate_transform_variant(uf, ctx, problems, case, method, prec):
         got = plan.distance(method, prec, tuning=dict(variant=1, emb_batch=E))
         err = _report(f"variant1 E={E} {case} {method} {prec}", got, want)
         assert err.max() <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("den_mode", [0, 1])
+def test_stripe_ranges_partition_equals_full(uf, ctx, problems, prec, den_mode):
+    """Independent stripe-range chunks (uneven, not tile-aligned) fill the matrix with the
+    values of the full computation, bit for bit; host and device outputs."""
+    import torch
+    prob = problems["cfg2_shape_600"]
+    plan = _plan(uf, ctx, prob)
+    S = prob.n_samples // 2
+    cuts = [0, 5, 37, 40, 161, S]
+    for method in (UW, WN):
+        full = plan.distance(method, prec, tuning=dict(den_mode=den_mode))
+        host = np.full(full.size, -1.0)
+        dev = torch.full((full.size,), -1.0, dtype=torch.float64, device="cuda:0")
+        for a, b in zip(cuts[:-1], cuts[1:]):
+            plan.distance_stripes(a, b, host, method, prec, tuning=dict(den_mode=den_mode))
+            plan.distance_stripes(a, b, dev, method, prec, tuning=dict(den_mode=den_mode))
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(host, full)
+        np.testing.assert_array_equal(dev.cpu().numpy(), full)
+
+
+def test_stripe_range_leaves_other_pairs(uf, ctx, problems):
+    prob = problems["cfg1_ragged_257"]
+    plan = _plan(uf, ctx, prob)
+    out = np.full(prob.n_samples * (prob.n_samples - 1) // 2, -3.0)
+    plan.distance_stripes(10, 20, out, WN, "fp64")
+    n = prob.n_samples
+    i, j = oracle.condensed_pairs(n)
+    d = j - i
+    s = np.where(d <= n // 2, d - 1, n - d - 1)
+    inside = (s >= 10) & (s < 20)
+    assert np.all(out[~inside] == -3.0)
+    want = oracle.problem_pairs(prob, oracle.WEIGHTED_NORMALIZED, i[inside], j[inside])
+    assert np.abs(out[inside] - want).max() <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", ["cfg1_ragged_257", "cfg2_shape_600", "tiny_b"])
+def test_weighted_unnormalized(uf, ctx, problems, case, prec):
+    """Weighted unnormalized (numerator only) values are lengths, not fractions: the bar is
+    relative to max(1, |d|)."""
+    prob = problems[case]
+    plan = _plan(uf, ctx, prob)
+    want = oracle.problem_condensed(prob, oracle.WEIGHTED_UNNORMALIZED)
+    got = plan.distance("weighted_unnormalized", prec)
+    err = np.abs(got - want) / np.maximum(1.0, np.abs(want))
+    print(f"[wun {case} {prec}] max_rel_err={err.max():.3e}", flush=True)
+    assert err.max() <= TOL[prec]
+    if prec == "fp64":
+        host = np.full(got.size, -1.0)
+        S = prob.n_samples // 2
+        plan.distance_stripes(0, S // 3, host, "weighted_unnormalized", prec)
+        plan.distance_stripes(S // 3, S, host, "weighted_unnormalized", prec)
+        np.testing.assert_array_equal(host, got)

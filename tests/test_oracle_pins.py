@@ -17,7 +17,7 @@ from synth import Problem, config_problem, make_rng
 
 from helpers import euler_tour_counts, leaves_of, relabel, table_rows, tiny_problem
 
-UW, WN = oracle.UNWEIGHTED, oracle.WEIGHTED_NORMALIZED
+UW, WN, WU = oracle.UNWEIGHTED, oracle.WEIGHTED_NORMALIZED, oracle.WEIGHTED_UNNORMALIZED
 
 
 def _golden(golden_dir):
@@ -67,7 +67,8 @@ def test_worked_example_counts(golden_dir):
 def test_bruteforce_exact(seed):
     prob = tiny_problem(1000 + seed, max_nodes=14, max_samples=6)
     rows = table_rows(prob)
-    for method, fn in ((UW, exact.unweighted), (WN, exact.weighted_normalized)):
+    for method, fn in ((UW, exact.unweighted), (WN, exact.weighted_normalized),
+                       (WU, exact.weighted_unnormalized)):
         want = np.array([float(x) for x in fn(prob.parent, prob.length, rows, prob.feature_node)])
         got = oracle.problem_condensed(prob, method)
         # each product L*p rounds once (<= u relative), the compensated sums add < u, the
@@ -124,12 +125,15 @@ def test_star_tree_reduces_to_jaccard_and_braycurtis(unit):
     prop = dense / dense.sum(axis=1, keepdims=True)
     uw = oracle.problem_condensed(prob, UW)
     wn = oracle.problem_condensed(prob, WN)
+    wu = oracle.problem_condensed(prob, WU)
     k = 0
     for i in range(dense.shape[0]):
         for j in range(i + 1, dense.shape[0]):
             ww = None if unit else w
             assert abs(uw[k] - spd.jaccard(pres[i], pres[j], w=ww)) <= 1e-15
             assert abs(wn[k] - spd.braycurtis(prop[i], prop[j], w=ww)) <= 1e-15
+            # weighted unnormalized on a star tree: length-weighted L1 of proportions
+            assert abs(wu[k] - spd.cityblock(prop[i], prop[j], w=ww)) <= 1e-14
             k += 1
 
 
@@ -240,6 +244,7 @@ def test_zero_length_tree_gives_zero():
 # --------------------------------------------------------------------- planted mistakes
 
 MUTANTS = {
+    "unnormalized divides": ("            out[p] = N;\n", "            out[p] = (D == 0.0) ? 0.0 : N / D;\n"),
     "abs dropped": ("L * fabs(pi - pj)", "L * (pi - pj)"),
     "den drops q": ("L * (pi + pj)", "L * (pi)"),
     "xor as and": ("(x != y) ? L : 0.0", "(x && y) ? L : 0.0"),
@@ -286,3 +291,38 @@ def test_planted_mistakes_are_caught(name, tmp_path, golden_dir):
         assert caught, f"mutant '{name}' survived the pins"
     finally:
         oracle._lib = saved
+
+
+# ------------------------------------------------------------------------- Mantel statistic
+
+def test_mantel_pearson_matches_scipy():
+    from scipy.stats import pearsonr
+    from oracle import mantel as M
+    rng = make_rng(21)
+    for _ in range(5):
+        x = rng.random(300)
+        y = 0.3 * x + rng.random(300)
+        assert abs(M.pearson(x, y) - pearsonr(x, y)[0]) <= 1e-14
+
+
+def test_mantel_permutation_pins():
+    from itertools import permutations as all_perms
+    from oracle import mantel as M
+    n = 5
+    rng = make_rng(22)
+    x = rng.random(n * (n - 1) // 2)
+    y = x + 0.5 * rng.random(x.size)
+    ident = [np.arange(n)]
+    r, p, rp = M.mantel(x, y, n, ident)
+    assert rp[0] == pytest.approx(r, abs=1e-15) and p == 1.0
+    r1, _, _ = M.mantel(x, x, n, [])
+    assert r1 == pytest.approx(1.0, abs=1e-15)
+    # relabelling y by sigma and testing with sigma^-1 restores the original matrix
+    sigma = rng.permutation(n)
+    inv = np.argsort(sigma)
+    ys = M.relabel(y, n, sigma)
+    assert M.pearson(x, M.relabel(ys, n, inv)) == pytest.approx(r, abs=1e-15)
+    # full enumeration: the exact permutation distribution contains the observed value
+    perms = [np.array(q) for q in all_perms(range(n))]
+    _, p_all, rp_all = M.mantel(x, y, n, perms)
+    assert np.any(np.isclose(rp_all, r)) and 1 / 121 <= p_all <= 1
