@@ -1,18 +1,26 @@
 #!/usr/bin/env python3
-"""Benchmark of the UniFrac hot path on one MI355X.
+"""Benchmark of the UniFrac hot path on one MI355X.  Prints one JSON line.
 
-One step = one full distance matrix of the benchmark workload with inputs already resident
-in HBM: embedding propagation, embedding transform, striped accumulation and
+A step is one full distance matrix of the workload with the inputs already resident in HBM
+(the plan was created before the timed region): embedding propagation, embedding
+transform, accumulation (striped, or matrix-core for the unweighted form) and
 normalize/condense, ending with the condensed matrix in device memory.
 
-Default workload: 4,096 samples on a 32,768-tip random coalescent tree (65,534 branches),
-~800 features per sample with NegBin(10, 0.3) counts rarefied to 5,000, weighted normalized
-UniFrac.  The headline value is the FP32 path; the FP64 path is timed on the same inputs
-for the FP32-vs-FP64 comparison.  Max and mean absolute error of both against the FP64 CPU
-oracle on a seeded sample of pairs are reported, and the same oracle run is timed on the
-host cores as the CPU baseline.
+Workloads (--workload):
+  striped (default)  4,096 samples, 32,768-tip random coalescent tree (65,534 branches),
+                     ~800 features per sample, NegBin(10, 0.3) counts rarefied to 5,000;
+                     weighted normalized.  Headline: the FP32 path; the FP64 path is timed on
+                     the same inputs for the FP32-vs-FP64 comparison.
+  mfma               25,000 samples, 300,000-tip random binary tree, 1,500 Zipf(1.1)
+                     presences per sample; unweighted on bf16 matrix cores (hi+lo split).
+                     --compare fp64 also times the FP64 striped form (about 20 s a step).
+  batch              64 jobs (samples uniform in 200..8,000, tips uniform in 1,000..64,000,
+                     workload-1 distributions), each run weighted normalized (FP32 striped)
+                     and unweighted (matrix core): 128 jobs in one batch, replayed as a
+                     captured HIP graph.
 
-Prints one JSON line.
+The oracle (FP64 CPU) is timed on the host cores on a seeded sample of pairs as the CPU
+baseline, and the same sample gives the max and mean absolute error of every GPU result.
 """
 from __future__ import annotations
 
@@ -28,8 +36,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+METRIC = "sample-pair·branch updates/s + full-matrix wall time, FP32/MFMA vs FP64 plain"
 # VALU issue rate of one MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (lane-ops/s).
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+MFMA_BF16_PEAK_TFLOPS = 2500.0
 HBM_PEAK_GBS = 8000.0
 # Algorithmic VALU operations per pair-branch update of the striped kernel:
 #   num += L*|u - v|  (sub, fma with |.|)   den += L*(u + v)  (add, fma)
@@ -41,13 +51,17 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--method", default="weighted_normalized")
-    ap.add_argument("--precision", default="fp32")
-    ap.add_argument("--compare", default="fp64", help="second precision timed for comparison ('' = none)")
+    ap.add_argument("--workload", default="striped", choices=["striped", "mfma", "batch"])
+    ap.add_argument("--method", default=None)
+    ap.add_argument("--precision", default=None)
+    ap.add_argument("--compare", default=None, help="second precision timed for comparison ('' = none)")
     ap.add_argument("--emb-batch", type=int, default=0)
     ap.add_argument("--den-mode", type=int, default=0)
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--k-chunk", type=int, default=0)
     ap.add_argument("--n", type=int, default=None, help="override the sample count")
     ap.add_argument("--tips", type=int, default=None, help="override the tip count")
+    ap.add_argument("--jobs", type=int, default=64, help="batch workload: number of jobs")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle CPU time")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -59,13 +73,259 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def sample_pairs(rng, n, m):
+    i = rng.integers(0, n, size=m)
+    j = rng.integers(0, n, size=m)
+    keep = i != j
+    return np.minimum(i[keep], j[keep]), np.maximum(i[keep], j[keep])
+
+
+def cond_index(n, i, j):
+    return n * i - i * (i + 1) // 2 + (j - i - 1)
+
+
+def oracle_sample(prob, method, seconds, seed, subset=None):
+    """Time the oracle on a seeded pair sample sized for about `seconds` of CPU work.
+    With `subset` the pairs are drawn among that many random samples (bounds the walk-up
+    memory on very large workloads).  Returns (cpu_baseline dict, pi, pj, values)."""
+    from oracle import oracle
+    om = {"unweighted": oracle.UNWEIGHTED, "weighted_normalized": oracle.WEIGHTED_NORMALIZED,
+          "weighted_unnormalized": oracle.WEIGHTED_UNNORMALIZED}[method]
+    n = prob.n_samples
+    B = prob.n_nodes - 1
+    rng = np.random.Generator(np.random.Philox(seed))
+    pool = np.sort(rng.choice(n, size=subset, replace=False)) if subset and subset < n else None
+
+    def draw(m):
+        if pool is None:
+            return sample_pairs(rng, n, m)
+        a, b = sample_pairs(rng, pool.size, m)
+        return pool[a], pool[b]
+
+    pi, pj = draw(64)
+    t = time.perf_counter()
+    oracle.problem_pairs(prob, om, pi, pj)
+    per_pair = (time.perf_counter() - t) / max(1, pi.size)
+    m = int(min(max(seconds / max(per_pair, 1e-9), 200), 2_000_000))
+    pi, pj = draw(m)
+    threads = oracle.max_threads()
+    log(f"oracle: {pi.size} sampled pairs on {threads} threads")
+    t = time.perf_counter()
+    want = oracle.problem_pairs(prob, om, pi, pj)
+    cpu_s = time.perf_counter() - t
+    where = f" among {subset} random samples" if pool is not None else ""
+    cpu = {"value": round(pi.size * B / cpu_s, 1), "unit": "pair-branch updates/s",
+           "cores": threads, "kind": "oracle",
+           "sample": f"{pi.size} seeded random pairs{where} ({method}, all {B} branches each), "
+                     f"{cpu_s:.1f} s including walk-up counts of the touched samples",
+           "seconds": round(cpu_s, 2)}
+    return cpu, pi, pj, want
+
+
+def errors(out, n, pi, pj, want):
+    import torch
+    idx = torch.from_numpy(cond_index(n, pi, pj)).to(out.device)
+    got = out[idx].double().cpu().numpy()
+    e = np.abs(got - want)
+    return {"max_abs": float(e.max()), "mean_abs": float(e.mean()), "pairs": int(pi.size)}
+
+
+def timed_runs(plan, method, prec, tuning, out, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        plan.distance(method, prec, out=out, tuning=tuning, stream=stream)
+    plan.set_profiling(True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        plan.distance(method, prec, out=out, tuning=tuning, stream=stream)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / steps
+    prof = plan.profile()
+    plan.set_profiling(False)
+    return dt, prof
+
+
+def base_record(args, value, dt, dtype, config):
+    return {"metric": METRIC, "value": round(value, 1), "unit": "pair-branch updates/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(dt * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config,
+            "full_matrix_wall_ms": round(dt * 1e3, 3)}
+
+
+def bench_striped(args):
+    import torch
+    import paper_2005_05826_amd as uf
+    from synth import config_problem
+    method = args.method or "weighted_normalized"
+    prec = args.precision or "fp32"
+    compare = "fp64" if args.compare is None else args.compare
+    over = {k: v for k, v in (("n", args.n), ("tips", args.tips)) if v}
+    t0 = time.time()
+    prob = config_problem(2, **over)
+    log(f"generated in {time.time() - t0:.1f}s: n={prob.n_samples} nodes={prob.n_nodes} nnz={prob.indices.size}")
+    n, B = prob.n_samples, prob.n_nodes - 1
+    n_pairs = n * (n - 1) // 2
+    updates = n_pairs * B
+    ctx = uf.Context(0)
+    stream = torch.cuda.current_stream()
+    plan = uf.Plan.from_problem(ctx, prob, stream=stream)
+    tuning = dict(emb_batch=args.emb_batch, den_mode=args.den_mode, tile=args.tile)
+    out = torch.empty(n_pairs, dtype=torch.float64, device="cuda:0")
+    log(f"timing {prec}: {args.warmup} warmup + {args.steps} steps")
+    dt, prof = timed_runs(plan, method, prec, tuning, out, args.steps, args.warmup, stream)
+    log(f"{prec}: {dt * 1e3:.2f} ms/step; kernels {prof}")
+    out2 = None
+    if compare:
+        out2 = torch.empty_like(out)
+        steps2 = max(1, args.steps // 2)
+        dt2, prof2 = timed_runs(plan, method, compare, tuning, out2, steps2, 1, stream)
+        log(f"{compare}: {dt2 * 1e3:.2f} ms/step; kernels {prof2}")
+
+    launches, total_ms = prof.get("stripe", (0, 0.0))
+    roofline = None
+    if launches:
+        ops = OPS_PER_UPDATE[args.den_mode] * updates
+        achieved = ops / (total_ms / args.steps * 1e-3) / 1e12
+        roofline = {"kernel": "k_stripe_fused", "bound": "alu", "achieved": round(achieved, 3),
+                    "peak": round(VALU_PEAK_TOPS, 2), "unit": "Tops/s",
+                    "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+                    "launches_per_step": launches // args.steps,
+                    "avg_launch_ms": round(total_ms / launches, 4),
+                    "ops_per_update": OPS_PER_UPDATE[args.den_mode]}
+    res = base_record(args, updates / dt, dt, "f32" if prec == "fp32" else "f64",
+                      {"workload": f"{method.replace('_', '-')} striped UniFrac, {n} samples, "
+                                   f"coalescent tree with {(prob.n_nodes + 1) // 2} tips ({B} branches)",
+                       "n_samples": n, "branches": B, "levels": plan.info.n_levels,
+                       "nnz": int(plan.info.nnz), "method": method, "precision": prec,
+                       "emb_batch": args.emb_batch or "default", "den_mode": args.den_mode,
+                       "tile": args.tile})
+    res["kernels_ms_per_step"] = {k: round(v[1] / args.steps, 3) for k, v in prof.items()}
+    res["roofline"] = roofline
+    if compare:
+        res["compare"] = {"precision": compare, "ms_per_step": round(dt2 * 1e3, 3),
+                          "value": round(updates / dt2, 1),
+                          "kernels_ms_per_step": {k: round(v[1] / steps2, 3) for k, v in prof2.items()},
+                          "speedup_of_headline": round(dt2 / dt, 3)}
+    if not args.no_cpu:
+        cpu, pi, pj, want = oracle_sample(prob, method, args.cpu_seconds, 20050526 + 99)
+        res["cpu_baseline"] = cpu
+        res["error_vs_oracle"] = {prec: errors(out, n, pi, pj, want)}
+        if compare:
+            res["error_vs_oracle"][compare] = errors(out2, n, pi, pj, want)
+    if compare and n >= 3:
+        r, _, _ = uf.mantel(ctx, out, out2, n)
+        res["mantel_r2_vs_compare"] = round(r * r, 12)
+    return res
+
+
+def bench_mfma(args):
+    import torch
+    import paper_2005_05826_amd as uf
+    from synth import config_problem
+    compare = "" if args.compare is None else args.compare
+    over = {k: v for k, v in (("n", args.n), ("tips", args.tips)) if v}
+    t0 = time.time()
+    prob = config_problem(3, **over)
+    log(f"generated in {time.time() - t0:.1f}s: n={prob.n_samples} nodes={prob.n_nodes}")
+    n, B = prob.n_samples, prob.n_nodes - 1
+    n_pairs = n * (n - 1) // 2
+    updates = n_pairs * B
+    ctx = uf.Context(0)
+    stream = torch.cuda.current_stream()
+    plan = uf.Plan.from_problem(ctx, prob, stream=stream)
+    tuning = dict(k_chunk=args.k_chunk)
+    out = torch.empty(n_pairs, dtype=torch.float64, device="cuda:0")
+    dt, prof = timed_runs(plan, "unweighted", "mfma_bf16x2", tuning, out, args.steps, args.warmup, stream)
+    log(f"mfma: {dt * 1e3:.2f} ms/step; kernels {prof}")
+    launches, total_ms = prof.get("mfma", (0, 0.0))
+    k_pad = (B + 63) // 64 * 64
+    flops = 4.0 * k_pad * n * (n + 1) / 2          # hi and lo, 2 flops each, upper triangle
+    achieved = flops / (total_ms / args.steps * 1e-3) / 1e12 if launches else 0.0
+    res = base_record(args, updates / dt, dt, "bf16",
+                      {"workload": f"unweighted UniFrac on bf16 matrix cores, {n} samples, random "
+                                   f"binary tree with {(prob.n_nodes + 1) // 2} tips ({B} branches)",
+                       "n_samples": n, "branches": B, "method": "unweighted",
+                       "precision": "mfma_bf16x2", "k_chunk": args.k_chunk or 4096})
+    res["kernels_ms_per_step"] = {k: round(v[1] / args.steps, 3) for k, v in prof.items()}
+    res["roofline"] = {"kernel": "k_mfma_gemm", "bound": "mfma", "achieved": round(achieved, 2),
+                       "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                       "frac": round(achieved / MFMA_BF16_PEAK_TFLOPS, 4), "traffic": None,
+                       "avg_launch_ms": round(total_ms / max(1, launches), 3)}
+    if compare:
+        out2 = torch.empty_like(out)
+        dt2, prof2 = timed_runs(plan, "unweighted", compare, {}, out2, 1, 0, stream)
+        res["compare"] = {"precision": compare, "ms_per_step": round(dt2 * 1e3, 3),
+                          "value": round(updates / dt2, 1), "speedup_of_headline": round(dt2 / dt, 3)}
+    if not args.no_cpu:
+        cpu, pi, pj, want = oracle_sample(prob, "unweighted", args.cpu_seconds, 20050526 + 98, subset=400)
+        res["cpu_baseline"] = cpu
+        res["error_vs_oracle"] = {"mfma_bf16x2": errors(out, n, pi, pj, want)}
+        if compare:
+            res["error_vs_oracle"][compare] = errors(out2, n, pi, pj, want)
+    return res
+
+
+def bench_batch(args):
+    import torch
+    import paper_2005_05826_amd as uf
+    from synth import batch_job_specs, build_job
+    t0 = time.time()
+    specs = batch_job_specs(n_jobs=args.jobs)
+    probs = [build_job(s) for s in specs]
+    log(f"generated {len(probs)} jobs in {time.time() - t0:.1f}s")
+    ctx = uf.Context(0)
+    jobs, outs = [], []
+    for p in probs:
+        m = p.n_samples * (p.n_samples - 1) // 2
+        for method, prec in (("weighted_normalized", "fp32"), ("unweighted", "mfma_bf16x2")):
+            o = torch.empty(max(1, m), dtype=torch.float64, device="cuda:0")
+            outs.append(o)
+            jobs.append(dict(problem=p, method=method, precision=prec, out=o))
+    b = uf.Batch(ctx, jobs, tuning=dict(emb_batch=args.emb_batch, tile=args.tile))
+    for _ in range(max(1, args.warmup)):
+        b.run()
+    t = time.perf_counter()
+    b.run()
+    eager = time.perf_counter() - t
+    b.capture()
+    b.set_profiling(True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        b.run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / args.steps
+    prof = b.profile()
+    updates = sum(p.n_samples * (p.n_samples - 1) // 2 * (p.n_nodes - 1) for p in probs) * 2
+    res = base_record(args, updates / dt, dt, "f32+bf16",
+                      {"workload": f"{len(probs)} uneven jobs x (weighted normalized FP32 striped + "
+                                   f"unweighted bf16 matrix core) in one captured HIP graph",
+                       "jobs": len(jobs), "samples_range": [min(p.n_samples for p in probs),
+                                                            max(p.n_samples for p in probs)],
+                       "tips_range": [min((p.n_nodes + 1) // 2 for p in probs),
+                                      max((p.n_nodes + 1) // 2 for p in probs)]})
+    res["eager_run_ms"] = round(eager * 1e3, 3)
+    res["kernels_ms_per_step"] = {k: round(v[1] / args.steps, 3) for k, v in prof.items()}
+    if not args.no_cpu:
+        # error sample on the largest job, both methods
+        big = int(np.argmax([p.n_samples * p.n_nodes for p in probs]))
+        p = probs[big]
+        cpu, pi, pj, want = oracle_sample(p, "weighted_normalized", args.cpu_seconds / 2, 20050526 + 97)
+        res["cpu_baseline"] = cpu
+        res["error_vs_oracle"] = {"wn_fp32_largest_job": errors(outs[2 * big], p.n_samples, pi, pj, want)}
+        _, pi, pj, want = oracle_sample(p, "unweighted", args.cpu_seconds / 4, 20050526 + 96)
+        res["error_vs_oracle"]["uw_mfma_largest_job"] = errors(outs[2 * big + 1], p.n_samples, pi, pj, want)
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
-
     import torch
     if args.copy_calibration:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")   # 1 GiB
@@ -75,136 +335,7 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": src.numel() * 4, "dispatches": 3}))
         return
-    import paper_2005_05826_amd as uf
-    from synth import config_problem
-
-    over = {}
-    if args.n:
-        over["n"] = args.n
-    if args.tips:
-        over["tips"] = args.tips
-    t0 = time.time()
-    prob = config_problem(2, **over)
-    log(f"generated workload in {time.time() - t0:.1f}s: n={prob.n_samples} nodes={prob.n_nodes} "
-        f"nnz={prob.indices.size}")
-    n = prob.n_samples
-    n_pairs = n * (n - 1) // 2
-    B = prob.n_nodes - 1
-    updates = n_pairs * B
-
-    ctx = uf.Context(0)
-    stream = torch.cuda.current_stream()
-    plan = uf.Plan.from_problem(ctx, prob, stream=stream)
-    info = plan.info
-    tuning = dict(emb_batch=args.emb_batch, den_mode=args.den_mode)
-
-    def run(prec, steps, warmup, profile):
-        out = torch.empty(n_pairs, dtype=torch.float64, device="cuda:0")
-        for _ in range(warmup):
-            plan.distance(args.method, prec, out=out, tuning=tuning, stream=stream)
-        plan.set_profiling(profile)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(steps):
-            plan.distance(args.method, prec, out=out, tuning=tuning, stream=stream)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t) / steps
-        prof = plan.profile() if profile else {}
-        plan.set_profiling(False)
-        return dt, out, prof
-
-    log(f"timing {args.precision}: {args.warmup} warmup + {args.steps} steps")
-    dt, out, prof = run(args.precision, args.steps, args.warmup, True)
-    log(f"{args.precision}: {dt * 1e3:.2f} ms/step; kernels {prof}")
-    cmp = None
-    if args.compare:
-        log(f"timing {args.compare}")
-        dt2, out2, prof2 = run(args.compare, max(1, args.steps // 2), 1, True)
-        log(f"{args.compare}: {dt2 * 1e3:.2f} ms/step; kernels {prof2}")
-        cmp = (dt2, out2, prof2)
-
-    # roofline of the dominant kernel (the striped accumulation)
-    launches, total_ms = prof.get("stripe", (0, 0.0))
-    ops_per_step = OPS_PER_UPDATE[args.den_mode] * updates
-    stripe_ms_per_step = total_ms / args.steps
-    roofline = None
-    if launches:
-        achieved = ops_per_step / (stripe_ms_per_step * 1e-3) / 1e12
-        roofline = {"kernel": "k_stripe", "bound": "alu", "achieved": round(achieved, 3),
-                    "peak": round(VALU_PEAK_TOPS, 2), "unit": "Tops/s",
-                    "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
-                    "launches_per_step": launches // args.steps,
-                    "avg_launch_ms": round(total_ms / launches, 4),
-                    "ops_per_update": OPS_PER_UPDATE[args.den_mode]}
-
-    # oracle: CPU baseline and error sample (same seeded pairs for both precisions)
-    err = {}
-    cpu = None
-    if not args.no_cpu:
-        from oracle import oracle
-        rng = np.random.Generator(np.random.Philox(20050526 + 99))
-        omethod = oracle.WEIGHTED_NORMALIZED if args.method == "weighted_normalized" else oracle.UNWEIGHTED
-
-        def sample(m):
-            i = rng.integers(0, n, size=m)
-            j = rng.integers(0, n, size=m)
-            keep = i != j
-            return np.minimum(i[keep], j[keep]), np.maximum(i[keep], j[keep])
-
-        pi, pj = sample(256)
-        t = time.perf_counter()
-        oracle.problem_pairs(prob, omethod, pi, pj)
-        per_pair = (time.perf_counter() - t) / max(1, pi.size)
-        m = int(min(max(args.cpu_seconds / max(per_pair, 1e-9), 500), 2_000_000))
-        pi, pj = sample(m)
-        threads = oracle.max_threads()
-        log(f"oracle: {pi.size} sampled pairs on {threads} threads")
-        t = time.perf_counter()
-        want = oracle.problem_pairs(prob, omethod, pi, pj)
-        cpu_s = time.perf_counter() - t
-        cpu = {"value": round(pi.size * B / cpu_s, 1), "unit": "pair-branch updates/s",
-               "cores": threads, "kind": "oracle",
-               "sample": f"{pi.size} seeded random pairs of the workload (all {B} branches each), "
-                         f"{cpu_s:.1f} s incl. walk-up counts of the touched samples",
-               "seconds": round(cpu_s, 2)}
-        idx = n * pi - pi * (pi + 1) // 2 + (pj - pi - 1)
-        for prec, o in [(args.precision, out)] + ([(args.compare, cmp[1])] if cmp else []):
-            got = o.cpu().numpy()[idx]
-            e = np.abs(got - want)
-            err[prec] = {"max_abs": float(e.max()), "mean_abs": float(e.mean()), "pairs": int(pi.size)}
-
-    value = updates / dt
-    res = {
-        "metric": "sample-pair·branch updates/s + full-matrix wall time, FP32/MFMA vs FP64 plain",
-        "value": round(value, 1),
-        "unit": "pair-branch updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(dt * 1e3, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32" if args.precision == "fp32" else "f64",
-        "data": "synthetic",
-        "config": {"workload": f"weighted-normalized striped UniFrac, {n} samples, coalescent "
-                               f"tree with {(prob.n_nodes + 1) // 2} tips ({B} branches)",
-                   "n_samples": n, "branches": B, "levels": info.n_levels, "nnz": int(info.nnz),
-                   "method": args.method, "precision": args.precision,
-                   "emb_batch": args.emb_batch or "default", "den_mode": args.den_mode},
-        "full_matrix_wall_ms": round(dt * 1e3, 3),
-        "kernels_ms_per_step": {k: round(v[1] / args.steps, 3) for k, v in prof.items()},
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-        "error_vs_oracle": err,
-    }
-    if cmp:
-        dt2 = cmp[0]
-        res["compare"] = {"precision": args.compare, "ms_per_step": round(dt2 * 1e3, 3),
-                          "value": round(updates / dt2, 1),
-                          "kernels_ms_per_step": {k: round(v[1] / max(1, args.steps // 2), 3)
-                                                  for k, v in cmp[2].items()},
-                          "speedup_of_headline": round(dt2 / dt, 3)}
+    res = {"striped": bench_striped, "mfma": bench_mfma, "batch": bench_batch}[args.workload](args)
     print(json.dumps(res), flush=True)
 
 

@@ -33,8 +33,9 @@ def _jobs():
     probs = []
     for spec, (m, p) in zip(specs, kinds):
         spec["p_nonzero"] = 0.2
+        spec["depth"] = 200      # small trees: keep the rarefaction depth reachable
         probs.append((build_job(spec), m, p))
-    probs.append((config_problem(1, n=1, tips=50, p_nonzero=0.5, seed=3), "weighted_normalized", "fp32"))
+    probs.append((config_problem(1, n=1, tips=50, p_nonzero=0.5, depth=200, seed=3), "weighted_normalized", "fp32"))
     return probs
 
 
@@ -116,7 +117,7 @@ def test_batch_errors(uf, ctx, jobs):
     with pytest.raises(uf.UniFracError) as ei:
         uf.Batch(ctx, [dict(problem=p, method="weighted_normalized", precision="mfma_bf16x2", out=out)])
     assert ei.value.status_name == "UF_E_UNSUPPORTED"
-    bad = config_problem(1, n=5, tips=40, p_nonzero=0.5, seed=8)
+    bad = config_problem(1, n=5, tips=40, p_nonzero=0.5, depth=200, seed=8)
     bad.parent = bad.parent.copy()
     bad.parent[0] = bad.parent.shape[0] + 5
     with pytest.raises(uf.UniFracError) as ei:
