@@ -283,7 +283,21 @@ def bench_batch(args):
             o = torch.empty(max(1, m), dtype=torch.float64, device="cuda:0")
             outs.append(o)
             jobs.append(dict(problem=p, method=method, precision=prec, out=o))
-    b = uf.Batch(ctx, jobs, tuning=dict(emb_batch=args.emb_batch, tile=args.tile))
+    # knobs: the autotuner times tile shape x batch depth (and the MFMA chunk) on the
+    # largest job, unless they are given on the command line
+    tuning = dict(emb_batch=args.emb_batch, tile=args.tile, k_chunk=args.k_chunk)
+    tuned = {}
+    if not args.emb_batch:
+        big = int(np.argmax([p.n_samples * p.n_nodes for p in probs]))
+        tplan = uf.Plan.from_problem(ctx, probs[big])
+        best, ms = tplan.autotune("weighted_normalized", "fp32", reps=1)
+        bestm, msm = tplan.autotune("unweighted", "mfma_bf16x2", reps=1)
+        tuning.update(emb_batch=best["emb_batch"], tile=best["tile"], k_chunk=bestm["k_chunk"])
+        tuned = {"striped": best, "striped_ms": round(ms, 3), "mfma": bestm, "mfma_ms": round(msm, 3),
+                 "on_job": {"n_samples": probs[big].n_samples, "branches": probs[big].n_nodes - 1}}
+        tplan.close()
+        log(f"autotuned: {tuned}")
+    b = uf.Batch(ctx, jobs, tuning=tuning)
     for _ in range(max(1, args.warmup)):
         b.run()
     t = time.perf_counter()
@@ -307,6 +321,7 @@ def bench_batch(args):
                        "tips_range": [min((p.n_nodes + 1) // 2 for p in probs),
                                       max((p.n_nodes + 1) // 2 for p in probs)]})
     res["eager_run_ms"] = round(eager * 1e3, 3)
+    res["tuning"] = {"used": tuning, "autotune": tuned}
     res["kernels_ms_per_step"] = {k: round(v[1] / args.steps, 3) for k, v in prof.items()}
     if not args.no_cpu:
         # error sample on the largest job, both methods

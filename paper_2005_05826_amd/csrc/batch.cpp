@@ -39,6 +39,7 @@ struct uf_batch {
     DevMem counters;                      // [0] FP64 queue, [1] FP32 queue, [2] MFMA queue
     // graph
     hipStream_t cap_stream = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     Profiler prof;
@@ -366,7 +367,15 @@ uf_status uf_batch_run(uf_batch *b, void *stream)
     UF_TRY(hipSetDevice(ctx->device), "hipSetDevice");
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (b->exec) {
-        UF_TRY(timed(b->prof, "graph", st, [&] { return hipGraphLaunch(b->exec, st); }), "graph launch");
+        // the graph runs on the batch's own stream, ordered after the caller's stream work
+        // and before anything the caller enqueues next
+        hipStream_t gs = b->cap_stream;
+        UF_TRY(hipEventRecord(b->ev_in, st), "recording order event");
+        UF_TRY(hipStreamWaitEvent(gs, b->ev_in, 0), "ordering graph launch");
+        UF_TRY(timed(b->prof, "graph", gs, [&] { return hipGraphLaunch(b->exec, gs); }), "graph launch");
+        UF_TRY(hipEventRecord(b->ev_out, gs), "recording completion event");
+        UF_TRY(hipStreamWaitEvent(st, b->ev_out, 0), "ordering caller stream");
+        UF_TRY(hipStreamSynchronize(gs), "synchronizing");
     } else {
         uf_status s = enqueue(b, st);
         if (s != UF_OK) return s;
@@ -384,6 +393,8 @@ uf_status uf_batch_capture(uf_batch *b)
     destroy_graph(b);
     if (!b->cap_stream)
         UF_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking), "creating capture stream");
+    if (!b->ev_in) UF_TRY(hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming), "creating event");
+    if (!b->ev_out) UF_TRY(hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming), "creating event");
     const bool prof_on = b->prof.on;
     b->prof.on = false;   // no timing events inside the graph
     UF_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
@@ -437,6 +448,8 @@ void uf_batch_destroy(uf_batch *b)
     (void)hipSetDevice(b->ctx->device);
     destroy_graph(b);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+    if (b->ev_out) (void)hipEventDestroy(b->ev_out);
     for (uf_plan *p : b->plans) uf_plan_destroy(p);
     for (DevMem *m : {&b->prop_jobs, &b->scatter_tasks, &b->level_tasks, &b->stripe_jobs[0],
                       &b->stripe_jobs[1], &b->stripe_items[0], &b->stripe_items[1], &b->mfma_jobs,

@@ -102,6 +102,10 @@ def test_graph_replay_matches_eager(uf, ctx, jobs):
         torch.cuda.synchronize()
         b.run()
         for o, e in zip(outs, eager):
+            if not torch.equal(o, e):
+                bad = (o != e)
+                print(f"replay {rep}: {int(bad.sum())} of {o.numel()} differ; "
+                      f"{int((o[bad] == -7.0).sum())} still hold the fill value", flush=True)
             assert torch.equal(o, e), f"replay {rep} differs from the eager run"
         # unrelated eager work between replays
         x = torch.randn(1 << 16, device="cuda:0")
