@@ -116,6 +116,9 @@ typedef struct {
     int32_t tile;       /* striped fused/queued kernels: per-lane tile shape, 0 or 1:
                            FP64 4x8 | 2x16, FP32 4x16 | 8x8 samples x stripes (stripes
                            doubled with den_mode 1)                                          */
+    int32_t count_width; /* striped path: bytes per embedding count; 0 = 2 when every sample
+                           total fits in 16 bits (halves count memory and traffic), else 4;
+                           4 = int32; 2 = uint16 (UF_E_ARG if a total exceeds 65535)         */
 } uf_tuning;
 
 typedef struct {
@@ -161,6 +164,11 @@ uf_status uf_plan_query(const uf_plan *plan, uf_plan_info *info);
  * as int32 in node-id order, [n_nodes][n_samples] row-major. */
 uf_status uf_plan_embedding_counts(uf_plan *plan, int32_t *out, int32_t out_on_device,
                                    void *stream);
+
+/* The same through the 16-bit count rows (every sample total must be <= 65535, else
+ * UF_E_ARG); the output is int32 like uf_plan_embedding_counts. */
+uf_status uf_plan_embedding_counts16(uf_plan *plan, int32_t *out, int32_t out_on_device,
+                                     void *stream);
 
 /* Presence bits of the same embedding: bit (k % 32) of out[v][k / 32] is set iff sample k
  * has a read at or below node v; [n_nodes][ceil(n_samples / 32)] uint32, node-id order. */

@@ -44,8 +44,8 @@ DTYPES = {"f64": 0, "f32": 1}
 # every entry point declared in include/unifrac_mi.h
 EXPORTED = ["uf_status_string", "uf_last_error", "uf_validate", "uf_context_create",
             "uf_context_destroy", "uf_plan_create", "uf_plan_destroy", "uf_plan_query",
-            "uf_plan_embedding_counts", "uf_plan_embedding_presence", "uf_plan_distance",
-            "uf_plan_distance_stripes", "uf_plan_stripes", "uf_plan_trim", "uf_plan_set_profiling",
+            "uf_plan_embedding_counts", "uf_plan_embedding_counts16",
+            "uf_plan_embedding_presence", "uf_plan_distance", "uf_plan_distance_stripes", "uf_plan_stripes", "uf_plan_trim", "uf_plan_set_profiling",
             "uf_plan_get_profile", "uf_autotune", "uf_batch_create", "uf_batch_run", "uf_batch_capture",
             "uf_batch_set_profiling", "uf_batch_get_profile", "uf_batch_destroy",
             "uf_distance_batch", "uf_mantel", "uf_distance"]
@@ -62,7 +62,7 @@ class UfTable(ctypes.Structure):
 
 class UfTuning(ctypes.Structure):
     _fields_ = [("emb_batch", c_i32), ("k_chunk", c_i32), ("den_mode", c_i32),
-                ("variant", c_i32), ("tile", c_i32)]
+                ("variant", c_i32), ("tile", c_i32), ("count_width", c_i32)]
 
 
 class UfKernelStat(ctypes.Structure):
@@ -95,6 +95,7 @@ _lib.uf_plan_destroy.restype = None
 _lib.uf_plan_query.argtypes = [c_p, ctypes.POINTER(UfPlanInfo)]
 _lib.uf_plan_embedding_counts.argtypes = [c_p, c_p, c_i32, c_p]
 _lib.uf_plan_embedding_presence.argtypes = [c_p, c_p, c_i32, c_p]
+_lib.uf_plan_embedding_counts16.argtypes = [c_p, c_p, c_i32, c_p]
 _lib.uf_plan_distance.argtypes = [c_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(UfTuning),
                                   ctypes.c_int, c_p, c_i32, c_p]
 _lib.uf_plan_distance_stripes.argtypes = [c_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(UfTuning),
@@ -122,8 +123,8 @@ _lib.uf_mantel.restype = ctypes.c_int
 _lib.uf_distance.argtypes = [c_p, ctypes.POINTER(UfTree), ctypes.POINTER(UfTable), ctypes.c_int,
                              ctypes.c_int, ctypes.c_int, c_p, c_i32, c_p]
 for _name in ("uf_validate", "uf_context_create", "uf_plan_create", "uf_plan_query",
-              "uf_plan_embedding_counts", "uf_plan_embedding_presence", "uf_plan_distance",
-              "uf_plan_distance_stripes", "uf_plan_stripes", "uf_plan_trim", "uf_plan_set_profiling",
+              "uf_plan_embedding_counts", "uf_plan_embedding_counts16",
+              "uf_plan_embedding_presence", "uf_plan_distance", "uf_plan_distance_stripes", "uf_plan_stripes", "uf_plan_trim", "uf_plan_set_profiling",
               "uf_plan_get_profile", "uf_autotune", "uf_batch_create", "uf_batch_run", "uf_batch_capture",
               "uf_batch_set_profiling", "uf_batch_get_profile", "uf_distance_batch",
               "uf_distance"):
@@ -197,7 +198,7 @@ def _tuning(t):
         return ctypes.byref(t)
     return ctypes.byref(UfTuning(int(t.get("emb_batch", 0)), int(t.get("k_chunk", 0)),
                                  int(t.get("den_mode", 0)), int(t.get("variant", 0)),
-                                 int(t.get("tile", 0))))
+                                 int(t.get("tile", 0)), int(t.get("count_width", 0))))
 
 
 class Context:
@@ -254,6 +255,11 @@ class Plan:
     def embedding_counts(self, stream=None) -> np.ndarray:
         out = np.empty((self.info.n_nodes, self.info.n_samples), np.int32)
         self.ctx._check(_lib.uf_plan_embedding_counts(self._h, _ptr(out), 0, _stream_handle(stream)))
+        return out
+
+    def embedding_counts16(self, stream=None) -> np.ndarray:
+        out = np.empty((self.info.n_nodes, self.info.n_samples), np.int32)
+        self.ctx._check(_lib.uf_plan_embedding_counts16(self._h, _ptr(out), 0, _stream_handle(stream)))
         return out
 
     def embedding_presence(self, stream=None) -> np.ndarray:

@@ -24,23 +24,35 @@ using namespace ufmi;
 
 namespace ufmi {
 
-// (a) embedding propagation, count form.
-uf_status propagate_counts(uf_plan *plan, hipStream_t st)
+int32_t resolve_count_width(const HostPrep &hp, int32_t requested)
+{
+    int32_t max_total = 0;
+    for (int32_t t : hp.totals) max_total = std::max(max_total, t);
+    if (requested == 4) return 4;
+    if (requested == 2) return max_total <= 65535 ? 2 : -1;
+    return max_total <= 65535 ? 2 : 4;
+}
+
+// (a) embedding propagation, count form (int32 or packed uint16 rows).
+uf_status propagate_counts(uf_plan *plan, hipStream_t st, int32_t cw)
 {
     uf_context *ctx = plan->ctx;
     const HostPrep &hp = plan->hp;
-    UF_TRY(plan->counts.ensure((size_t)hp.n_nodes * plan->cstride * sizeof(int32_t)),
-           "allocating embedding counts");
-    int32_t *C = plan->counts.as<int32_t>();
-    UF_TRY(launch_fill_u32(C, 0u, (size_t)hp.n_leaf * plan->cstride, st), "clearing tip rows");
+    cw = resolve_count_width(hp, cw);
+    if (cw < 0) return set_err(ctx, UF_E_ARG, "16-bit counts need every sample total <= 65535");
+    plan->cw = cw;
+    const int64_t words = plan->cstride * cw / 4;   // uint32 words per row
+    UF_TRY(plan->counts.ensure((size_t)hp.n_nodes * words * 4), "allocating embedding counts");
+    void *C = plan->counts.p;
+    UF_TRY(launch_fill_u32(C, 0u, (size_t)hp.n_leaf * words, st), "clearing tip rows");
     UF_TRY(timed(plan, "propagate", st, [&] {
                hipError_t r = launch_scatter_counts(plan->indptr.as<int64_t>(),
                                                     plan->entry_slot.as<int32_t>(),
-                                                    plan->entry_count.as<int32_t>(), C,
+                                                    plan->entry_count.as<int32_t>(), C, cw,
                                                     plan->cstride, hp.n_samples, st);
                for (int32_t h = 1; h < hp.n_levels && r == hipSuccess; ++h) {
                    const int32_t b = hp.level_ptr[h], e = hp.level_ptr[h + 1];
-                   r = launch_level_sum(C, plan->cstride, b, e - b, hp.n_leaf,
+                   r = launch_level_sum(C, words, b, e - b, hp.n_leaf,
                                         plan->child_ptr.as<int32_t>(),
                                         plan->child_slot.as<int32_t>(), st);
                }
@@ -118,7 +130,7 @@ uf_status plan_prepare(uf_context *ctx, const uf_tree *tree, const uf_table *tab
 namespace {
 
 struct Knobs {
-    int32_t emb_batch, k_chunk, den_mode, variant, tile;
+    int32_t emb_batch, k_chunk, den_mode, variant, tile, count_width;
 };
 
 Knobs resolve_knobs(const uf_tuning *t, uf_precision prec, int32_t n_branches)
@@ -135,6 +147,7 @@ Knobs resolve_knobs(const uf_tuning *t, uf_precision prec, int32_t n_branches)
     k.den_mode = (t ? t->den_mode : 0);
     k.variant = (t ? t->variant : 0);
     k.tile = (t ? t->tile : 0);
+    k.count_width = (t ? t->count_width : 0);
     return k;
 }
 
@@ -174,26 +187,27 @@ uf_status run_striped(uf_plan *plan, uf_method method, uf_precision prec, const 
         UF_TRY(launch_fill_u32(D, 0u, (size_t)hp.n_samples * 2, st), "clearing sums");
         return UF_OK;
     }
-    uf_status s = propagate_counts(plan, st);
+    uf_status s = propagate_counts(plan, st, kn.count_width);
     if (s != UF_OK) return s;
+    const int32_t cw = plan->cw;
     // the stripe kernels add every batch into the state, so it starts at zero
     UF_TRY(launch_fill_u32(num, 0u, state / 4, st), "clearing stripes");
     if (den) UF_TRY(launch_fill_u32(den, 0u, state / 4, st), "clearing stripes");
     const int32_t E = kn.emb_batch;
-    const int32_t *C = plan->counts.as<int32_t>();
+    const void *C = plan->counts.p;
     const double *len = plan->len_slot.as<double>();
     if (kn.variant == 0) {
         UF_TRY(plan->inv_t.ensure((size_t)hp.n_samples * sizeof(double)), "allocating totals");
         UF_TRY(launch_inv_totals(plan->totals.as<int32_t>(), hp.n_samples, plan->inv_t.as<double>(), st),
                "reciprocal totals");
         UF_TRY(timed(plan, "stripe", st, [&] {
-                   return launch_stripe_fused(fp64, method, kn.den_mode, kn.tile, C, plan->cstride,
+                   return launch_stripe_fused(fp64, method, kn.den_mode, kn.tile, C, cw, plan->cstride,
                                               plan->inv_t.as<double>(), len, B, E, num, den, g,
                                               tile_s0, tile_s1, st);
                }), "striped accumulation");
         if (kn.den_mode != 0 && !unnorm)
             UF_TRY(timed(plan, "rowdot", st, [&] {
-                       return launch_rowdot(method, C, plan->cstride, 0, B,
+                       return launch_rowdot(method, C, cw, plan->cstride, 0, B,
                                             plan->totals.as<int32_t>(), len, g.n, D, true, st);
                    }), "per-sample sums");
         return UF_OK;
@@ -202,7 +216,7 @@ uf_status run_striped(uf_plan *plan, uf_method method, uf_precision prec, const 
     for (int32_t b0 = 0; b0 < B; b0 += E) {
         const int32_t eb = std::min(E, B - b0);
         UF_TRY(timed(plan, "transform", st, [&] {
-                   return launch_transform(fp64, method, C, plan->cstride, b0, eb,
+                   return launch_transform(fp64, method, C, cw, plan->cstride, b0, eb,
                                            plan->totals.as<int32_t>(), g.n, g.S, plan->emb.p,
                                            g.estride, st);
                }), "embedding transform");
@@ -212,7 +226,7 @@ uf_status run_striped(uf_plan *plan, uf_method method, uf_precision prec, const 
                }), "striped accumulation");
         if (kn.den_mode != 0 && !unnorm)
             UF_TRY(timed(plan, "rowdot", st, [&] {
-                       return launch_rowdot(method, C, plan->cstride, b0, eb,
+                       return launch_rowdot(method, C, cw, plan->cstride, b0, eb,
                                             plan->totals.as<int32_t>(), len + b0, g.n, D,
                                             b0 == 0, st);
                    }), "per-sample sums");
@@ -410,9 +424,33 @@ uf_status uf_plan_embedding_counts(uf_plan *plan, int32_t *out, int32_t out_on_d
     uf_context *ctx = plan->ctx;
     UF_TRY(hipSetDevice(ctx->device), "hipSetDevice");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    uf_status s = propagate_counts(plan, st);
+    uf_status s = propagate_counts(plan, st, 4);
     if (s != UF_OK) return s;
     return emit_rows(plan, plan->counts.p, plan->cstride, plan->hp.n_samples, out, out_on_device, st);
+}
+
+uf_status uf_plan_embedding_counts16(uf_plan *plan, int32_t *out, int32_t out_on_device, void *stream)
+{
+    if (!plan || !out) return set_err(plan ? plan->ctx : nullptr, UF_E_ARG, "NULL argument");
+    uf_context *ctx = plan->ctx;
+    UF_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    uf_status s = propagate_counts(plan, st, 2);
+    if (s != UF_OK) return s;
+    const HostPrep &hp = plan->hp;
+    const size_t bytes = (size_t)hp.n_nodes * hp.n_samples * sizeof(int32_t);
+    void *dst = out;
+    if (!out_on_device) {
+        UF_TRY(plan->gather_tmp.ensure(bytes), "allocating output staging");
+        dst = plan->gather_tmp.p;
+    }
+    UF_TRY(launch_gather_rows_u16(plan->counts.as<uint16_t>(), plan->cstride,
+                                  plan->slot_of_node.as<int32_t>(), hp.n_nodes, hp.n_samples,
+                                  static_cast<int32_t *>(dst), st), "gathering rows");
+    if (!out_on_device)
+        UF_TRY(hipMemcpyAsync(out, dst, bytes, hipMemcpyDeviceToHost, st), "copying rows out");
+    UF_TRY(hipStreamSynchronize(st), "synchronizing");
+    return UF_OK;
 }
 
 uf_status uf_plan_embedding_presence(uf_plan *plan, uint32_t *out, int32_t out_on_device,

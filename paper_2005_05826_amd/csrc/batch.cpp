@@ -22,7 +22,7 @@ struct uf_batch {
     uf_context *ctx = nullptr;
     std::vector<uf_plan *> plans;
     std::vector<uf_job> jobs;
-    int32_t emb_batch = 0, den_mode = 0, k_chunk = 4096, tile = 0;
+    int32_t emb_batch = 0, den_mode = 0, k_chunk = 4096, tile = 0, count_width = 0;
     int32_t n_groups = 512;
     // propagation tables
     DevMem prop_jobs, scatter_tasks, level_tasks;
@@ -58,7 +58,8 @@ uf_status enqueue(uf_batch *b, hipStream_t st)
     for (int32_t j = 0; j < nj; ++j) {
         uf_plan *p = b->plans[j];
         if (is_striped(b->jobs[j]))
-            UF_TRY(launch_fill_u32(p->counts.p, 0u, (size_t)p->hp.n_leaf * p->cstride, st), "clearing tips");
+            UF_TRY(launch_fill_u32(p->counts.p, 0u, (size_t)p->hp.n_leaf * p->cstride * p->cw / 4, st),
+                   "clearing tips");
         else
             UF_TRY(launch_fill_u32(p->bits.p, 0u, (size_t)p->hp.n_leaf * p->bstride, st), "clearing tips");
     }
@@ -101,7 +102,7 @@ uf_status enqueue(uf_batch *b, hipStream_t st)
         const uf_job &J = b->jobs[j];
         const StripeGeom g = stripe_geometry(p->hp.n_samples, J.prec == UF_PREC_FP64, b->den_mode, b->tile);
         if (b->den_mode != 0 && J.method != UF_WEIGHTED_UNNORMALIZED)
-            UF_TRY(launch_rowdot(J.method, p->counts.as<int32_t>(), p->cstride, 0, p->hp.n_nodes - 1,
+            UF_TRY(launch_rowdot(J.method, p->counts.p, p->cw, p->cstride, 0, p->hp.n_nodes - 1,
                                  p->totals.as<int32_t>(), p->len_slot.as<double>(), g.n,
                                  p->D.as<double>(), true, st), "per-sample sums");
         UF_TRY(timed(b->prof, "condense", st, [&] {
@@ -166,20 +167,22 @@ uf_status build_tables(uf_batch *b, hipStream_t st)
         uf_plan *p = b->plans[j];
         const HostPrep &hp = p->hp;
         const bool striped = is_striped(b->jobs[j]);
-        if (striped)
-            UF_TRY(p->counts.ensure((size_t)hp.n_nodes * p->cstride * sizeof(int32_t)), "allocating counts");
-        else
+        if (striped) {
+            p->cw = resolve_count_width(hp, b->count_width);
+            if (p->cw < 0) return set_err(ctx, UF_E_ARG, "16-bit counts need every sample total <= 65535");
+            UF_TRY(p->counts.ensure((size_t)hp.n_nodes * p->cstride * p->cw), "allocating counts");
+        } else
             UF_TRY(p->bits.ensure((size_t)hp.n_nodes * p->bstride * sizeof(uint32_t)), "allocating bits");
         PropJob &J = pj[j];
         J.X = striped ? p->counts.as<uint32_t>() : p->bits.as<uint32_t>();
-        J.stride = striped ? p->cstride : p->bstride;
+        J.stride = striped ? p->cstride * p->cw / 4 : p->bstride;
         J.child_ptr = p->child_ptr.as<int32_t>();
         J.child_slot = p->child_slot.as<int32_t>();
         J.indptr = p->indptr.as<int64_t>();
         J.entry_slot = p->entry_slot.as<int32_t>();
         J.entry_count = p->entry_count.as<int32_t>();
         J.n_leaf = hp.n_leaf;
-        J.mode = striped ? 0 : 1;
+        J.mode = striped ? (p->cw == 2 ? 2 : 0) : 1;
         J.n_samples = hp.n_samples;
         J.pad = 0;
         for (int32_t k = 0; k < hp.n_samples; ++k) {
@@ -234,7 +237,7 @@ uf_status build_tables(uf_batch *b, hipStream_t st)
             b->stripe_of_job[j] = idx;
             // the unnormalized variant runs the weighted-normalized numerator
             const int32_t km = J.method == UF_WEIGHTED_UNNORMALIZED ? UF_WEIGHTED_NORMALIZED : J.method;
-            sj.push_back(make_stripe_args(km, p->counts.as<int32_t>(), p->cstride,
+            sj.push_back(make_stripe_args(km, p->counts.p, p->cw, p->cstride,
                                           p->inv_t.as<double>(), p->len_slot.as<double>(),
                                           hp.n_nodes - 1, E, p->num.as<double>(),
                                           b->den_mode == 0 ? p->den.as<double>() : nullptr, g));
@@ -333,6 +336,7 @@ uf_status uf_batch_create(uf_context *ctx, const uf_job *jobs, int32_t n_jobs,
         b->emb_batch = tuning->emb_batch;
         b->den_mode = tuning->den_mode;
         b->tile = tuning->tile;
+        b->count_width = tuning->count_width;
         if (tuning->k_chunk > 0) b->k_chunk = tuning->k_chunk;
     }
     if ((b->den_mode != 0 && b->den_mode != 1) || (b->tile != 0 && b->tile != 1)) {

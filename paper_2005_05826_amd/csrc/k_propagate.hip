@@ -24,17 +24,23 @@ __global__ void k_fill_u32(uint32_t *__restrict__ p, uint32_t value, size_t n)
 
 // One wave per sample; its lanes stride over the sample's CSR entries.  Duplicate
 // features in a row land on the same element, hence the (exact, integer) atomic add.
+template <int CW>
 __global__ void k_scatter_counts(const int64_t *__restrict__ indptr,
                                  const int32_t *__restrict__ entry_slot,
                                  const int32_t *__restrict__ entry_count,
-                                 int32_t *__restrict__ C, int64_t cstride, int32_t n_samples)
+                                 void *__restrict__ C, int64_t cstride, int32_t n_samples)
 {
     const int32_t k = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     if (k >= n_samples) return;
     const int lane = threadIdx.x & 63;
     const int64_t e1 = indptr[k + 1];
-    for (int64_t e = indptr[k] + lane; e < e1; e += 64)
-        atomicAdd(C + (int64_t)entry_slot[e] * cstride + k, entry_count[e]);
+    for (int64_t e = indptr[k] + lane; e < e1; e += 64) {
+        const int64_t at = (int64_t)entry_slot[e] * cstride + k;
+        if (CW == 4)
+            atomicAdd(static_cast<int32_t *>(C) + at, entry_count[e]);
+        else   // add into the half of the 32-bit word that holds element `at`
+            atomicAdd(static_cast<uint32_t *>(C) + (at >> 1), (uint32_t)entry_count[e] << (16 * (at & 1)));
+    }
 }
 
 __global__ void k_scatter_bits(const int64_t *__restrict__ indptr,
@@ -79,6 +85,16 @@ __global__ void k_level(uint32_t *__restrict__ X, int64_t stride, int32_t n_vec,
     }
 }
 
+__global__ void k_gather_rows_u16(const uint16_t *__restrict__ src, int64_t sstride,
+                                  const int32_t *__restrict__ slot_of_node, int32_t n_nodes,
+                                  int32_t width, int32_t *__restrict__ out)
+{
+    const int32_t x = blockIdx.x * kBlock + threadIdx.x;
+    if (x >= width) return;
+    for (int32_t v = blockIdx.y; v < n_nodes; v += gridDim.y)
+        out[(int64_t)v * width + x] = (int32_t)src[(int64_t)slot_of_node[v] * sstride + x];
+}
+
 __global__ void k_gather_rows(const uint32_t *__restrict__ src, int64_t sstride,
                               const int32_t *__restrict__ slot_of_node, int32_t n_nodes,
                               int32_t width, uint32_t *__restrict__ out)
@@ -108,6 +124,11 @@ __global__ void k_scatter_batched(const PropJob *__restrict__ jobs, const int2 *
         int32_t *C = reinterpret_cast<int32_t *>(J.X);
         for (int64_t e = J.indptr[k] + lane; e < e1; e += 64)
             atomicAdd(C + (int64_t)J.entry_slot[e] * J.stride + k, J.entry_count[e]);
+    } else if (J.mode == 2) {   // uint16 counts, 2 * stride elements per row
+        for (int64_t e = J.indptr[k] + lane; e < e1; e += 64) {
+            const int64_t at = (int64_t)J.entry_slot[e] * (2 * J.stride) + k;
+            atomicAdd(J.X + (at >> 1), (uint32_t)J.entry_count[e] << (16 * (at & 1)));
+        }
     } else {
         const uint32_t bit = 1u << (k & 31);
         for (int64_t e = J.indptr[k] + lane; e < e1; e += 64)
@@ -128,7 +149,7 @@ __global__ void k_level_batched(const PropJob *__restrict__ jobs, const int2 *__
         uint4 acc = make_uint4(0u, 0u, 0u, 0u);
         for (int32_t q = q0; q < q1; ++q) {
             const uint4 v = reinterpret_cast<const uint4 *>(J.X + (int64_t)J.child_slot[q] * J.stride)[c];
-            if (J.mode) {
+            if (J.mode == 1) {
                 acc.x |= v.x; acc.y |= v.y; acc.z |= v.z; acc.w |= v.w;
             } else {
                 acc.x += v.x; acc.y += v.y; acc.z += v.z; acc.w += v.w;
@@ -180,11 +201,24 @@ hipError_t launch_fill_u32(void *p, uint32_t value, size_t n_words, hipStream_t 
 }
 
 hipError_t launch_scatter_counts(const int64_t *indptr, const int32_t *entry_slot,
-                                 const int32_t *entry_count, int32_t *C, int64_t cstride,
+                                 const int32_t *entry_count, void *C, int32_t cw, int64_t cstride,
                                  int32_t n_samples, hipStream_t st)
 {
-    k_scatter_counts<<<grid1(n_samples, kBlock / 64), kBlock, 0, st>>>(
-        indptr, entry_slot, entry_count, C, cstride, n_samples);
+    if (cw == 2)
+        k_scatter_counts<2><<<grid1(n_samples, kBlock / 64), kBlock, 0, st>>>(
+            indptr, entry_slot, entry_count, C, cstride, n_samples);
+    else
+        k_scatter_counts<4><<<grid1(n_samples, kBlock / 64), kBlock, 0, st>>>(
+            indptr, entry_slot, entry_count, C, cstride, n_samples);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_rows_u16(const uint16_t *src, int64_t sstride, const int32_t *slot_of_node,
+                                  int32_t n_nodes, int32_t width, int32_t *out, hipStream_t st)
+{
+    if (n_nodes <= 0 || width <= 0) return hipSuccess;
+    dim3 grid(grid1(width, kBlock), (unsigned)(n_nodes < 65535 ? n_nodes : 65535));
+    k_gather_rows_u16<<<grid, kBlock, 0, st>>>(src, sstride, slot_of_node, n_nodes, width, out);
     return hipGetLastError();
 }
 
@@ -213,11 +247,11 @@ static hipError_t launch_level(bool is_or, uint32_t *X, int64_t stride, int32_t 
     return hipGetLastError();
 }
 
-hipError_t launch_level_sum(int32_t *C, int64_t cstride, int32_t slot_begin, int32_t n_rows,
+hipError_t launch_level_sum(void *C, int64_t stride_words, int32_t slot_begin, int32_t n_rows,
                             int32_t n_leaf, const int32_t *child_ptr, const int32_t *child_slot,
                             hipStream_t st)
 {
-    return launch_level(false, reinterpret_cast<uint32_t *>(C), cstride, slot_begin, n_rows,
+    return launch_level(false, static_cast<uint32_t *>(C), stride_words, slot_begin, n_rows,
                         n_leaf, child_ptr, child_slot, st);
 }
 

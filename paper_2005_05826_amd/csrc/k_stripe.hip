@@ -75,8 +75,8 @@ __device__ inline void add_tile(const T (&an)[TST][TKT], const T (&ad)[TST][TKT]
 // emb[e][x] = f(C[slot0 + e][x mod n]) for x < n + S, else 0.
 // Weighted normalized: f = count / total (FP64 division, then rounded to T).
 // Unweighted: f = 1 if count > 0 else 0.
-template <typename T, int METHOD>
-__global__ void k_transform(const int32_t *__restrict__ C, int64_t cstride, int32_t slot0,
+template <typename T, int METHOD, typename CT>
+__global__ void k_transform(const CT *__restrict__ C, int64_t cstride, int32_t slot0,
                             const int32_t *__restrict__ totals, int32_t n, int32_t S,
                             T *__restrict__ emb, int64_t estride)
 {
@@ -86,7 +86,7 @@ __global__ void k_transform(const int32_t *__restrict__ C, int64_t cstride, int3
     T val = T(0);
     if (x < (int64_t)n + S) {
         const int32_t k = x < n ? (int32_t)x : (int32_t)(x - n);
-        const int32_t c = C[(int64_t)(slot0 + e) * cstride + k];
+        const int32_t c = (int32_t)C[(int64_t)(slot0 + e) * cstride + k];
         if (METHOD == UF_WEIGHTED_NORMALIZED)
             val = (T)((double)c / (double)totals[k]);
         else
@@ -179,7 +179,7 @@ struct StripeSmem {
     T sv[EB * VW];
 };
 
-template <typename T, int METHOD, int DEN, int TILE>
+template <typename T, int METHOD, int DEN, int TILE, typename CT>
 __device__ void stripe_tile(const StripeArgs &a, int32_t k0, int32_t s0, StripeSmem<T, DEN, TILE> &sm)
 {
     using SM = StripeSmem<T, DEN, TILE>;
@@ -188,7 +188,7 @@ __device__ void stripe_tile(const StripeArgs &a, int32_t k0, int32_t s0, StripeS
     constexpr int NV = TKT + TST - 1;
     constexpr int NU_T = (TKW + kBlock - 1) / kBlock;   // u positions per thread
     constexpr int NV_T = (VW + kBlock - 1) / kBlock;    // v positions per thread
-    const int32_t *__restrict__ C = a.C;
+    const CT *__restrict__ C = static_cast<const CT *>(a.C);
     const double *__restrict__ len = a.len;
     const int64_t cstride = a.cstride, sstride = a.sstride;
     const int32_t n = a.n, S = a.S, B = a.B, E = a.E;
@@ -236,11 +236,11 @@ __device__ void stripe_tile(const StripeArgs &a, int32_t k0, int32_t s0, StripeS
             int32_t cu[EB][NU_T], cv[EB][NV_T];
 #pragma unroll
             for (int e = 0; e < EB; ++e) {
-                const int32_t *row = C + (int64_t)(e0 + (e < eb ? e : eb - 1)) * cstride;
+                const CT *row = C + (int64_t)(e0 + (e < eb ? e : eb - 1)) * cstride;
 #pragma unroll
-                for (int q = 0; q < NU_T; ++q) cu[e][q] = row[uk[q]];
+                for (int q = 0; q < NU_T; ++q) cu[e][q] = (int32_t)row[uk[q]];
 #pragma unroll
-                for (int q = 0; q < NV_T; ++q) cv[e][q] = row[vk[q]];
+                for (int q = 0; q < NV_T; ++q) cv[e][q] = (int32_t)row[vk[q]];
             }
             __syncthreads();
 #pragma unroll
@@ -295,12 +295,12 @@ __device__ void stripe_tile(const StripeArgs &a, int32_t k0, int32_t s0, StripeS
     }
 }
 
-template <typename T, int METHOD, int DEN, int TILE>
+template <typename T, int METHOD, int DEN, int TILE, typename CT>
 __global__ __launch_bounds__(kBlock, 2) void k_stripe_fused(StripeArgs a)
 {
     using SM = StripeSmem<T, DEN, TILE>;
     __shared__ SM sm;
-    stripe_tile<T, METHOD, DEN, TILE>(a, blockIdx.x * SM::TKW, a.s_base + blockIdx.y * SM::TSW, sm);
+    stripe_tile<T, METHOD, DEN, TILE, CT>(a, blockIdx.x * SM::TKW, a.s_base + blockIdx.y * SM::TSW, sm);
 }
 
 // Persistent form for many jobs: every work-group takes items (job, tile) from a global
@@ -326,10 +326,17 @@ __global__ __launch_bounds__(kBlock, 2) void k_stripe_queue(
         const StripeArgs a = jobs[item.x];
         const int32_t kt = item.y % a.tiles_k, stile = item.y / a.tiles_k;
         const int32_t k0 = kt * SM::TKW, s0 = a.s_base + stile * SM::TSW;
-        if (a.method == UF_WEIGHTED_NORMALIZED)
-            stripe_tile<T, UF_WEIGHTED_NORMALIZED, DEN, TILE>(a, k0, s0, sm);
-        else
-            stripe_tile<T, UF_UNWEIGHTED, DEN, TILE>(a, k0, s0, sm);
+        if (a.cw == 2) {
+            if (a.method == UF_WEIGHTED_NORMALIZED)
+                stripe_tile<T, UF_WEIGHTED_NORMALIZED, DEN, TILE, uint16_t>(a, k0, s0, sm);
+            else
+                stripe_tile<T, UF_UNWEIGHTED, DEN, TILE, uint16_t>(a, k0, s0, sm);
+        } else {
+            if (a.method == UF_WEIGHTED_NORMALIZED)
+                stripe_tile<T, UF_WEIGHTED_NORMALIZED, DEN, TILE, int32_t>(a, k0, s0, sm);
+            else
+                stripe_tile<T, UF_UNWEIGHTED, DEN, TILE, int32_t>(a, k0, s0, sm);
+        }
     }
 }
 
@@ -341,8 +348,8 @@ __global__ void k_inv_totals(const int32_t *__restrict__ totals, int32_t n, doub
 }
 
 // D[k] (+)= sum over the batch of L_e * u_k,e in FP64, for the separable denominator.
-template <int METHOD>
-__global__ void k_rowdot(const int32_t *__restrict__ C, int64_t cstride, int32_t slot0,
+template <int METHOD, typename CT>
+__global__ void k_rowdot(const CT *__restrict__ C, int64_t cstride, int32_t slot0,
                          int32_t E, const int32_t *__restrict__ totals,
                          const double *__restrict__ len, int32_t n, double *__restrict__ D,
                          int32_t first)
@@ -352,7 +359,7 @@ __global__ void k_rowdot(const int32_t *__restrict__ C, int64_t cstride, int32_t
     const double t = (double)totals[k];
     double acc = first ? 0.0 : D[k];
     for (int32_t e = 0; e < E; ++e) {
-        const int32_t c = C[(int64_t)(slot0 + e) * cstride + k];
+        const int32_t c = (int32_t)C[(int64_t)(slot0 + e) * cstride + k];
         const double u = METHOD == UF_WEIGHTED_NORMALIZED ? (double)c / t : (c > 0 ? 1.0 : 0.0);
         acc = fma(len[e], u, acc);
     }
@@ -489,24 +496,36 @@ StripeGeom stripe_geometry(int32_t n, bool fp64, int32_t den_mode, int32_t tile)
     return g;
 }
 
-hipError_t launch_transform(bool fp64, int32_t method, const int32_t *C, int64_t cstride,
+template <typename CT>
+static hipError_t transform_dispatch(bool fp64, int32_t method, const CT *C, int64_t cstride,
+                                     int32_t slot0, int32_t E, const int32_t *totals, int32_t n,
+                                     int32_t S, void *emb, int64_t estride, hipStream_t st)
+{
+    dim3 grid(grid1(estride, kBlock), (unsigned)E);
+    if (fp64) {
+        if (method == UF_WEIGHTED_NORMALIZED)
+            k_transform<double, UF_WEIGHTED_NORMALIZED, CT><<<grid, kBlock, 0, st>>>(C, cstride, slot0, totals, n, S, (double *)emb, estride);
+        else
+            k_transform<double, UF_UNWEIGHTED, CT><<<grid, kBlock, 0, st>>>(C, cstride, slot0, totals, n, S, (double *)emb, estride);
+    } else {
+        if (method == UF_WEIGHTED_NORMALIZED)
+            k_transform<float, UF_WEIGHTED_NORMALIZED, CT><<<grid, kBlock, 0, st>>>(C, cstride, slot0, totals, n, S, (float *)emb, estride);
+        else
+            k_transform<float, UF_UNWEIGHTED, CT><<<grid, kBlock, 0, st>>>(C, cstride, slot0, totals, n, S, (float *)emb, estride);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_transform(bool fp64, int32_t method, const void *C, int32_t cw, int64_t cstride,
                             int32_t slot0, int32_t E, const int32_t *totals, int32_t n, int32_t S,
                             void *emb, int64_t estride, hipStream_t st)
 {
     if (E <= 0) return hipSuccess;
-    dim3 grid(grid1(estride, kBlock), (unsigned)E);
-    if (fp64) {
-        if (method == UF_WEIGHTED_NORMALIZED)
-            k_transform<double, UF_WEIGHTED_NORMALIZED><<<grid, kBlock, 0, st>>>(C, cstride, slot0, totals, n, S, (double *)emb, estride);
-        else
-            k_transform<double, UF_UNWEIGHTED><<<grid, kBlock, 0, st>>>(C, cstride, slot0, totals, n, S, (double *)emb, estride);
-    } else {
-        if (method == UF_WEIGHTED_NORMALIZED)
-            k_transform<float, UF_WEIGHTED_NORMALIZED><<<grid, kBlock, 0, st>>>(C, cstride, slot0, totals, n, S, (float *)emb, estride);
-        else
-            k_transform<float, UF_UNWEIGHTED><<<grid, kBlock, 0, st>>>(C, cstride, slot0, totals, n, S, (float *)emb, estride);
-    }
-    return hipGetLastError();
+    if (cw == 2)
+        return transform_dispatch(fp64, method, static_cast<const uint16_t *>(C), cstride, slot0, E,
+                                  totals, n, S, emb, estride, st);
+    return transform_dispatch(fp64, method, static_cast<const int32_t *>(C), cstride, slot0, E,
+                              totals, n, S, emb, estride, st);
 }
 
 hipError_t launch_stripe(bool fp64, int32_t method, int32_t den_mode, const void *emb,
@@ -524,12 +543,12 @@ hipError_t launch_inv_totals(const int32_t *totals, int32_t n, double *inv_t, hi
     return hipGetLastError();
 }
 
-template <typename T, int TILE>
+template <typename T, int TILE, typename CT>
 static hipError_t fused_dispatch(const StripeArgs &a, int32_t den_mode, const StripeGeom &g,
                                  hipStream_t st)
 {
     dim3 grid((unsigned)a.tiles_k, (unsigned)a.tiles_s);
-#define UF_FUSED(M, D) k_stripe_fused<T, M, D, TILE><<<grid, kBlock, 0, st>>>(a)
+#define UF_FUSED(M, D) k_stripe_fused<T, M, D, TILE, CT><<<grid, kBlock, 0, st>>>(a)
     if (a.method == UF_WEIGHTED_NORMALIZED) {
         if (den_mode == 0) UF_FUSED(UF_WEIGHTED_NORMALIZED, 0); else UF_FUSED(UF_WEIGHTED_NORMALIZED, 1);
     } else {
@@ -540,24 +559,35 @@ static hipError_t fused_dispatch(const StripeArgs &a, int32_t den_mode, const St
 }
 
 hipError_t launch_stripe_fused(bool fp64, int32_t method, int32_t den_mode, int32_t tile,
-                               const int32_t *C, int64_t cstride, const double *inv_t,
+                               const void *C, int32_t cw, int64_t cstride, const double *inv_t,
                                const double *len, int32_t B, int32_t E, double *num, double *den,
                                const StripeGeom &g, int32_t tile_s0, int32_t tile_s1, hipStream_t st)
 {
     if (B <= 0 || tile_s1 <= tile_s0) return hipSuccess;
-    StripeArgs a = make_stripe_args(method, C, cstride, inv_t, len, B, E, num, den, g);
+    StripeArgs a = make_stripe_args(method, C, cw, cstride, inv_t, len, B, E, num, den, g);
     a.s_base = tile_s0 * g.tsw;
     a.tiles_s = tile_s1 - tile_s0;
-    if (fp64) return tile ? fused_dispatch<double, 1>(a, den_mode, g, st) : fused_dispatch<double, 0>(a, den_mode, g, st);
-    return tile ? fused_dispatch<float, 1>(a, den_mode, g, st) : fused_dispatch<float, 0>(a, den_mode, g, st);
+    const int key = (fp64 ? 4 : 0) + (tile ? 2 : 0) + (cw == 2 ? 1 : 0);
+    switch (key) {
+    case 0: return fused_dispatch<float, 0, int32_t>(a, den_mode, g, st);
+    case 1: return fused_dispatch<float, 0, uint16_t>(a, den_mode, g, st);
+    case 2: return fused_dispatch<float, 1, int32_t>(a, den_mode, g, st);
+    case 3: return fused_dispatch<float, 1, uint16_t>(a, den_mode, g, st);
+    case 4: return fused_dispatch<double, 0, int32_t>(a, den_mode, g, st);
+    case 5: return fused_dispatch<double, 0, uint16_t>(a, den_mode, g, st);
+    case 6: return fused_dispatch<double, 1, int32_t>(a, den_mode, g, st);
+    default: return fused_dispatch<double, 1, uint16_t>(a, den_mode, g, st);
+    }
 }
 
-StripeArgs make_stripe_args(int32_t method, const int32_t *C, int64_t cstride, const double *inv_t,
-                            const double *len, int32_t B, int32_t E, double *num, double *den,
-                            const StripeGeom &g)
+StripeArgs make_stripe_args(int32_t method, const void *C, int32_t cw, int64_t cstride,
+                            const double *inv_t, const double *len, int32_t B, int32_t E,
+                            double *num, double *den, const StripeGeom &g)
 {
     StripeArgs a;
     a.C = C;
+    a.cw = cw;
+    a.pad = 0;
     a.cstride = cstride;
     a.inv_t = inv_t;
     a.len = len;
@@ -597,15 +627,18 @@ hipError_t launch_stripe_queue(bool fp64, int32_t den_mode, int32_t tile, const 
     return hipGetLastError();
 }
 
-hipError_t launch_rowdot(int32_t method, const int32_t *C, int64_t cstride, int32_t slot0,
+hipError_t launch_rowdot(int32_t method, const void *C, int32_t cw, int64_t cstride, int32_t slot0,
                          int32_t E, const int32_t *totals, const double *len, int32_t n,
                          double *D, bool first, hipStream_t st)
 {
     const int f = first ? 1 : 0;
-    if (method == UF_WEIGHTED_NORMALIZED)
-        k_rowdot<UF_WEIGHTED_NORMALIZED><<<grid1(n, kBlock), kBlock, 0, st>>>(C, cstride, slot0, E, totals, len, n, D, f);
-    else
-        k_rowdot<UF_UNWEIGHTED><<<grid1(n, kBlock), kBlock, 0, st>>>(C, cstride, slot0, E, totals, len, n, D, f);
+#define UF_RD(M, CT) k_rowdot<M, CT><<<grid1(n, kBlock), kBlock, 0, st>>>(static_cast<const CT *>(C), cstride, slot0, E, totals, len, n, D, f)
+    if (method == UF_WEIGHTED_NORMALIZED) {
+        if (cw == 2) UF_RD(UF_WEIGHTED_NORMALIZED, uint16_t); else UF_RD(UF_WEIGHTED_NORMALIZED, int32_t);
+    } else {
+        if (cw == 2) UF_RD(UF_UNWEIGHTED, uint16_t); else UF_RD(UF_UNWEIGHTED, int32_t);
+    }
+#undef UF_RD
     return hipGetLastError();
 }
 

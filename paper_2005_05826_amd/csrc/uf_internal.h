@@ -43,12 +43,18 @@ hipError_t launch_fill_u32(void *p, uint32_t value, size_t n_words, hipStream_t 
 hipError_t launch_max_abs_diff(const double *a, const double *b, int64_t n, double *out, hipStream_t st);
 
 // Embedding propagation (count form): C is [n_nodes][cstride] int32 in slot order.
+// C: [n_nodes][cstride] counts of cw bytes (4 = int32, 2 = uint16 packed two per word;
+// uint16 needs every sample total <= 65535, so packed halves never carry into each other).
 hipError_t launch_scatter_counts(const int64_t *indptr, const int32_t *entry_slot,
-                                 const int32_t *entry_count, int32_t *C, int64_t cstride,
+                                 const int32_t *entry_count, void *C, int32_t cw, int64_t cstride,
                                  int32_t n_samples, hipStream_t st);
-hipError_t launch_level_sum(int32_t *C, int64_t cstride, int32_t slot_begin, int32_t n_rows,
+// stride_words: uint32 words per row (the gather adds whole words, i.e. both packed halves)
+hipError_t launch_level_sum(void *C, int64_t stride_words, int32_t slot_begin, int32_t n_rows,
                             int32_t n_leaf, const int32_t *child_ptr, const int32_t *child_slot,
                             hipStream_t st);
+// out[v][0..width) = (int32) src16[slot_of_node[v]][0..width)
+hipError_t launch_gather_rows_u16(const uint16_t *src, int64_t sstride, const int32_t *slot_of_node,
+                                  int32_t n_nodes, int32_t width, int32_t *out, hipStream_t st);
 // Presence form: B is [n_nodes][bstride] uint32, bit k%32 of word k/32.
 hipError_t launch_scatter_bits(const int64_t *indptr, const int32_t *entry_slot,
                                const int32_t *entry_count, uint32_t *B, int64_t bstride,
@@ -56,10 +62,11 @@ hipError_t launch_scatter_bits(const int64_t *indptr, const int32_t *entry_slot,
 hipError_t launch_level_or(uint32_t *B, int64_t bstride, int32_t slot_begin, int32_t n_rows,
                            int32_t n_leaf, const int32_t *child_ptr, const int32_t *child_slot,
                            hipStream_t st);
-// Batched propagation over many jobs: mode 0 = int32 counts, 1 = presence bits.
+// Batched propagation over many jobs: mode 0 = int32 counts, 1 = presence bits,
+// 2 = uint16 counts packed two per word.
 struct PropJob {
-    uint32_t *X;              // counts (as uint32) or presence words, slot-major rows
-    int64_t stride;           // elements per row (multiple of 4)
+    uint32_t *X;              // counts or presence words, slot-major rows
+    int64_t stride;           // uint32 words per row (multiple of 4)
     const int32_t *child_ptr, *child_slot;
     const int64_t *indptr;
     const int32_t *entry_slot, *entry_count;
@@ -85,7 +92,8 @@ struct StripeGeom {
 };
 StripeGeom stripe_geometry(int32_t n, bool fp64, int32_t den_mode, int32_t tile = 0);
 
-hipError_t launch_transform(bool fp64, int32_t method, const int32_t *C, int64_t cstride,
+// Count rows are int32 (cw = 4) or uint16 (cw = 2, when every sample total fits in 16 bits).
+hipError_t launch_transform(bool fp64, int32_t method, const void *C, int32_t cw, int64_t cstride,
                             int32_t slot0, int32_t E, const int32_t *totals, int32_t n, int32_t S,
                             void *emb, int64_t estride, hipStream_t st);
 hipError_t launch_stripe(bool fp64, int32_t method, int32_t den_mode, const void *emb,
@@ -95,7 +103,8 @@ hipError_t launch_stripe(bool fp64, int32_t method, int32_t den_mode, const void
 // accumulate in registers; the stripe state, cleared beforehand, is the cross-batch
 // accumulator).  StripeArgs describes one job for the fused and queued kernels.
 struct StripeArgs {
-    const int32_t *C;        // counts [n_nodes][cstride], branch slots first
+    const void *C;           // counts [n_nodes][cstride], branch slots first
+    int32_t cw, pad;         // bytes per count: 4 (int32) or 2 (uint16)
     int64_t cstride;
     const double *inv_t;     // 1 / total per sample
     const double *len;       // branch length per slot
@@ -104,9 +113,9 @@ struct StripeArgs {
     int64_t sstride;
     int32_t method, tiles_k, tiles_s, s_base;   // s_base: stripe held by state row 0
 };
-StripeArgs make_stripe_args(int32_t method, const int32_t *C, int64_t cstride, const double *inv_t,
-                            const double *len, int32_t B, int32_t E, double *num, double *den,
-                            const StripeGeom &g);
+StripeArgs make_stripe_args(int32_t method, const void *C, int32_t cw, int64_t cstride,
+                            const double *inv_t, const double *len, int32_t B, int32_t E,
+                            double *num, double *den, const StripeGeom &g);
 // items_xy: (job index, tile index) pairs, tile = s_tile * tiles_k + k_tile; *counter == 0.
 hipError_t launch_stripe_queue(bool fp64, int32_t den_mode, int32_t tile, const StripeArgs *jobs,
                                const int32_t *items_xy, int32_t n_items, int32_t *counter,
@@ -114,7 +123,7 @@ hipError_t launch_stripe_queue(bool fp64, int32_t den_mode, int32_t tile, const 
 hipError_t launch_inv_totals(const int32_t *totals, int32_t n, double *inv_t, hipStream_t st);
 // Covers stripe tiles [tile_s0, tile_s1); state row 0 holds stripe tile_s0 * tsw.
 hipError_t launch_stripe_fused(bool fp64, int32_t method, int32_t den_mode, int32_t tile,
-                               const int32_t *C, int64_t cstride, const double *inv_t,
+                               const void *C, int32_t cw, int64_t cstride, const double *inv_t,
                                const double *len, int32_t B, int32_t E, double *num, double *den,
                                const StripeGeom &g, int32_t tile_s0, int32_t tile_s1, hipStream_t st);
 // Writes the pairs of stripes [s_begin, s_end) into a full condensed output; the state
@@ -124,7 +133,7 @@ hipError_t launch_condense_range(int32_t method, const double *num, const double
                                  int32_t s_begin, int32_t s_end, int32_t out_f32, void *out,
                                  hipStream_t st);
 // Per-sample sums D_k = sum_b L_b u_kb over a batch (separable denominator).
-hipError_t launch_rowdot(int32_t method, const int32_t *C, int64_t cstride, int32_t slot0,
+hipError_t launch_rowdot(int32_t method, const void *C, int32_t cw, int64_t cstride, int32_t slot0,
                          int32_t E, const int32_t *totals, const double *len, int32_t n,
                          double *D, bool first, hipStream_t st);
 hipError_t launch_condense(int32_t method, const double *num, const double *den, const double *D,

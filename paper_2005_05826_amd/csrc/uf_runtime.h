@@ -98,7 +98,8 @@ struct uf_plan {
     ufmi::DevMem counts, bits, emb, num, den, D, inv_t, out_tmp, gather_tmp;
     ufmi::DevMem mfma_scratch[4];
     ufmi::Profiler prof;
-    int64_t cstride = 0;  // int32 elements per count row (multiple of 64)
+    int64_t cstride = 0;  // count elements per row (multiple of 64)
+    int32_t cw = 4;       // bytes per count of the last propagation: 4 (int32) or 2 (uint16)
     int64_t bstride = 0;  // uint32 words per presence row (multiple of 4)
 };
 
@@ -158,7 +159,9 @@ hipError_t timed(uf_plan *plan, const char *cls, hipStream_t st, F &&fn)
 }
 
 // Plan-level steps reused by the batch runner.
-uf_status propagate_counts(uf_plan *plan, hipStream_t st);
+// cw: 4 = int32 counts, 2 = uint16 (needs every total <= 65535), 0 = uint16 when it fits
+uf_status propagate_counts(uf_plan *plan, hipStream_t st, int32_t cw = 0);
+int32_t resolve_count_width(const HostPrep &hp, int32_t requested);
 uf_status propagate_bits(uf_plan *plan, hipStream_t st);
 uf_status plan_prepare(uf_context *ctx, const uf_tree *tree, const uf_table *table,
                        hipStream_t st, uf_plan **out);

@@ -331,3 +331,29 @@ def test_weighted_unnormalized(uf, ctx, problems, case, prec):
         plan.distance_stripes(0, S // 3, host, "weighted_unnormalized", prec)
         plan.distance_stripes(S // 3, S, host, "weighted_unnormalized", prec)
         np.testing.assert_array_equal(host, got)
+
+
+@pytest.mark.parametrize("case", ["cfg1_ragged_257", "cfg2_shape_513", "tiny_b"])
+def test_count_width_16_and_32_agree(uf, ctx, problems, case):
+    """uint16 count rows (packed two per word) and int32 rows give the same counts and the
+    same distances bit for bit."""
+    prob = problems[case]
+    plan = _plan(uf, ctx, prob)
+    want = oracle.problem_counts(prob).T
+    np.testing.assert_array_equal(plan.embedding_counts16().astype(np.int64), want)
+    for method in (UW, WN):
+        for prec in ("fp64", "fp32"):
+            a = plan.distance(method, prec, tuning=dict(count_width=2))
+            b = plan.distance(method, prec, tuning=dict(count_width=4))
+            np.testing.assert_array_equal(a, b)
+
+
+def test_count_width_16_rejects_large_totals(uf, ctx):
+    big = _single([2, 2, -1], [1.0, 2.0, 0.0], [[(0, 70000)], [(1, 5)], [(0, 2), (1, 2)]], [0, 1])
+    plan = _plan(uf, ctx, big)
+    with pytest.raises(uf.UniFracError) as ei:
+        plan.distance(WN, "fp64", tuning=dict(count_width=2))
+    assert ei.value.status_name == "UF_E_ARG"
+    got = plan.distance(WN, "fp64")          # auto picks int32 rows here
+    want = oracle.problem_condensed(big, oracle.WEIGHTED_NORMALIZED)
+    assert np.abs(got - want).max() <= 1e-12
