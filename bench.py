@@ -51,7 +51,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="striped", choices=["striped", "mfma", "batch"])
+    ap.add_argument("--workload", default="striped",
+                    choices=["striped", "mfma", "batch", "large-wn", "large-uw"])
+    ap.add_argument("--share", type=int, default=8,
+                    help="large-wn: compute 1/share of the stripes (one GPU's share)")
     ap.add_argument("--method", default=None)
     ap.add_argument("--precision", default=None)
     ap.add_argument("--compare", default=None, help="second precision timed for comparison ('' = none)")
@@ -335,6 +338,86 @@ def bench_batch(args):
     return res
 
 
+def bench_large(args, part):
+    """Workload 5 (113,000 samples, 500,000-tip random binary tree, ~1,000 features per
+    sample, NegBin(8, 0.3) rarefied to 2,000).  large-uw: the full unweighted matrix on the
+    matrix cores (presence bytes 113 GB, FP64 shared lengths in the output).  large-wn: one
+    GPU's share of an N-way split of the weighted normalized FP32 striped computation, a
+    contiguous stripe range of 1/share of the stripes, with 16-bit count rows (226 GB);
+    the condensed output (FP32, 25.5 GB) stays resident."""
+    import torch
+    import paper_2005_05826_amd as uf
+    from synth import config_problem
+    over = {k: v for k, v in (("n", args.n), ("tips", args.tips)) if v}
+    t0 = time.time()
+    prob = config_problem(5, **over)
+    log(f"generated in {time.time() - t0:.1f}s: n={prob.n_samples} nodes={prob.n_nodes} nnz={prob.indices.size}")
+    n, B = prob.n_samples, prob.n_nodes - 1
+    n_pairs = n * (n - 1) // 2
+    ctx = uf.Context(0)
+    stream = torch.cuda.current_stream()
+    plan = uf.Plan.from_problem(ctx, prob, stream=stream)
+    S = n // 2
+    if part == "uw":
+        out = torch.empty(n_pairs, dtype=torch.float64, device="cuda:0")
+        dt, prof = timed_runs(plan, "unweighted", "mfma_bf16x2", dict(k_chunk=args.k_chunk), out,
+                              args.steps, args.warmup, stream)
+        launches, total_ms = prof.get("mfma", (0, 0.0))
+        k_pad = (B + 63) // 64 * 64
+        flops = 4.0 * k_pad * n * (n + 1) / 2
+        achieved = flops / (total_ms / args.steps * 1e-3) / 1e12 if launches else 0.0
+        res = base_record(args, n_pairs * B / dt, dt, "bf16",
+                          {"workload": f"unweighted UniFrac on bf16 matrix cores, {n} samples, random "
+                                       f"binary tree with {(prob.n_nodes + 1) // 2} tips ({B} branches)",
+                           "n_samples": n, "branches": B, "precision": "mfma_bf16x2"})
+        res["roofline"] = {"kernel": "k_mfma_gemm", "bound": "mfma", "achieved": round(achieved, 2),
+                           "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                           "frac": round(achieved / MFMA_BF16_PEAK_TFLOPS, 4), "traffic": None}
+        method = "unweighted"
+    else:
+        s0, s1 = 0, (S + args.share - 1) // args.share
+        out = torch.empty(n_pairs, dtype=torch.float32, device="cuda:0")
+        tuning = dict(emb_batch=args.emb_batch, tile=args.tile, count_width=2)
+        for _ in range(args.warmup):
+            plan.distance_stripes(s0, s1, out, "weighted_normalized", "fp32", out_dtype="f32",
+                                  tuning=tuning, stream=stream)
+        plan.set_profiling(True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            plan.distance_stripes(s0, s1, out, "weighted_normalized", "fp32", out_dtype="f32",
+                                  tuning=tuning, stream=stream)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / args.steps
+        prof = plan.profile()
+        plan.set_profiling(False)
+        updates = (s1 - s0) * n * B
+        launches, total_ms = prof.get("stripe", (0, 0.0))
+        achieved = 4 * updates / (total_ms / args.steps * 1e-3) / 1e12 if launches else 0.0
+        res = base_record(args, updates / dt, dt, "f32",
+                          {"workload": f"weighted-normalized FP32 striped UniFrac, {n} samples, random "
+                                       f"binary tree with {(prob.n_nodes + 1) // 2} tips ({B} branches), "
+                                       f"stripes [{s0}, {s1}) = 1/{args.share} of {S}",
+                           "n_samples": n, "branches": B, "stripes": [s0, s1],
+                           "precision": "fp32", "count_width": 2})
+        res["roofline"] = {"kernel": "k_stripe_fused", "bound": "alu", "achieved": round(achieved, 3),
+                           "peak": round(VALU_PEAK_TOPS, 2), "unit": "Tops/s",
+                           "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None}
+        method = "weighted_normalized"
+    res["kernels_ms_per_step"] = {k: round(v[1] / args.steps, 3) for k, v in prof.items()}
+    if not args.no_cpu:
+        cpu, pi, pj, want = oracle_sample(prob, method, args.cpu_seconds, 20050526 + 95, subset=300)
+        res["cpu_baseline"] = cpu
+        if part == "wn":   # only pairs held by the computed stripes
+            d = pj - pi
+            st = np.where(d <= S, d - 1, n - d - 1)
+            keep = (st >= s0) & (st < s1)
+            pi, pj, want = pi[keep], pj[keep], want[keep]
+        if pi.size:
+            res["error_vs_oracle"] = {method: errors(out, n, pi, pj, want)}
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -350,7 +433,10 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": src.numel() * 4, "dispatches": 3}))
         return
-    res = {"striped": bench_striped, "mfma": bench_mfma, "batch": bench_batch}[args.workload](args)
+    if args.workload.startswith("large"):
+        res = bench_large(args, args.workload.split("-")[1])
+    else:
+        res = {"striped": bench_striped, "mfma": bench_mfma, "batch": bench_batch}[args.workload](args)
     print(json.dumps(res), flush=True)
 
 
