@@ -205,14 +205,21 @@ uf_status run_striped(uf_plan *plan, uf_method method, uf_precision prec, const 
                                               plan->inv_t.as<double>(), len, B, E, num, den, g,
                                               tile_s0, tile_s1, st);
                }), "striped accumulation");
-        if (kn.den_mode != 0 && !unnorm)
+        if (kn.den_mode != 0 && !unnorm) {
+            UF_TRY(plan->rowdot_part.ensure(rowdot_scratch_elems(g.n, B) * sizeof(double)),
+                   "allocating per-sample sum scratch");
             UF_TRY(timed(plan, "rowdot", st, [&] {
                        return launch_rowdot(method, C, cw, plan->cstride, 0, B,
-                                            plan->totals.as<int32_t>(), len, g.n, D, true, st);
+                                            plan->totals.as<int32_t>(), len, g.n, D, true,
+                                            plan->rowdot_part.as<double>(), st);
                    }), "per-sample sums");
+        }
         return UF_OK;
     }
     UF_TRY(plan->emb.ensure((size_t)E * g.estride * tsz), "allocating embedding batch");
+    if (kn.den_mode != 0 && !unnorm)
+        UF_TRY(plan->rowdot_part.ensure(rowdot_scratch_elems(g.n, E) * sizeof(double)),
+               "allocating per-sample sum scratch");
     for (int32_t b0 = 0; b0 < B; b0 += E) {
         const int32_t eb = std::min(E, B - b0);
         UF_TRY(timed(plan, "transform", st, [&] {
@@ -228,7 +235,7 @@ uf_status run_striped(uf_plan *plan, uf_method method, uf_precision prec, const 
             UF_TRY(timed(plan, "rowdot", st, [&] {
                        return launch_rowdot(method, C, cw, plan->cstride, b0, eb,
                                             plan->totals.as<int32_t>(), len + b0, g.n, D,
-                                            b0 == 0, st);
+                                            b0 == 0, plan->rowdot_part.as<double>(), st);
                    }), "per-sample sums");
     }
     return UF_OK;
@@ -364,7 +371,7 @@ void uf_plan_destroy(uf_plan *plan)
     for (DevMem *m : {&plan->indptr, &plan->entry_slot, &plan->entry_count, &plan->totals,
                       &plan->child_ptr, &plan->child_slot, &plan->len_slot, &plan->slot_of_node,
                       &plan->counts, &plan->bits, &plan->emb, &plan->num, &plan->den, &plan->D,
-                      &plan->inv_t, &plan->out_tmp, &plan->gather_tmp})
+                      &plan->inv_t, &plan->out_tmp, &plan->gather_tmp, &plan->rowdot_part})
         m->release();
     for (DevMem &m : plan->mfma_scratch) m.release();
     plan->prof.release();
@@ -376,7 +383,7 @@ uf_status uf_plan_trim(uf_plan *plan)
     if (!plan) return set_err(nullptr, UF_E_ARG, "plan must not be NULL");
     (void)hipSetDevice(plan->ctx->device);
     for (DevMem *m : {&plan->counts, &plan->bits, &plan->emb, &plan->num, &plan->den, &plan->D,
-                      &plan->inv_t, &plan->out_tmp, &plan->gather_tmp})
+                      &plan->inv_t, &plan->out_tmp, &plan->gather_tmp, &plan->rowdot_part})
         m->release();
     for (DevMem &m : plan->mfma_scratch) m.release();
     return UF_OK;

@@ -29,14 +29,15 @@ struct uf_batch {
     std::vector<int32_t> level_ptr;       // per height level, range of level_tasks
     std::vector<int32_t> level_max_vec;   // widest row (uint4 columns) of each level
     int32_t n_scatter = 0;
-    // striped tables per precision: [0] FP64, [1] FP32
-    DevMem stripe_jobs[2], stripe_items[2];
-    int32_t n_stripe_items[2] = {0, 0};
-    std::vector<int32_t> stripe_of_job;   // index into the precision's job table, -1 if none
+    // striped tables, one queue per (precision, method, count width):
+    // q = 4 * (FP32) + 2 * (weighted) + (16-bit counts)
+    static constexpr int kQueues = 8;
+    DevMem stripe_jobs[kQueues], stripe_items[kQueues];
+    int32_t n_stripe_items[kQueues] = {};
     // matrix-core tables
     DevMem mfma_jobs, mfma_items, mfma_tiles;
     int32_t n_mfma_items = 0;
-    DevMem counters;                      // [0] FP64 queue, [1] FP32 queue, [2] MFMA queue
+    DevMem counters;                      // [0, kQueues) striped queues, [kQueues] MFMA queue
     // graph
     hipStream_t cap_stream = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -75,8 +76,8 @@ uf_status enqueue(uf_batch *b, hipStream_t st)
                return r;
            }), "batched propagation");
 
-    // (b) striped jobs: clear state and queue counters, one persistent launch per precision
-    UF_TRY(launch_fill_u32(b->counters.p, 0u, 4, st), "clearing queue counters");
+    // (b) striped jobs: clear state and queue counters, one persistent launch per queue
+    UF_TRY(launch_fill_u32(b->counters.p, 0u, uf_batch::kQueues + 1, st), "clearing queue counters");
     for (int32_t j = 0; j < nj; ++j) {
         if (!is_striped(b->jobs[j])) continue;
         uf_plan *p = b->plans[j];
@@ -87,10 +88,12 @@ uf_status enqueue(uf_batch *b, hipStream_t st)
         UF_TRY(launch_inv_totals(p->totals.as<int32_t>(), p->hp.n_samples, p->inv_t.as<double>(), st),
                "reciprocal totals");
     }
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < uf_batch::kQueues; ++q) {
         if (b->n_stripe_items[q] == 0) continue;
         UF_TRY(timed(b->prof, "stripe", st, [&] {
-                   return launch_stripe_queue(q == 0, b->den_mode, b->tile, b->stripe_jobs[q].as<StripeArgs>(),
+                   return launch_stripe_queue((q & 4) == 0, (q & 2) ? UF_WEIGHTED_NORMALIZED : UF_UNWEIGHTED,
+                                              (q & 1) ? 2 : 4, b->den_mode, b->tile,
+                                              b->stripe_jobs[q].as<StripeArgs>(),
                                               b->stripe_items[q].as<int32_t>(), b->n_stripe_items[q],
                                               b->counters.as<int32_t>() + q,
                                               std::min(b->n_groups, b->n_stripe_items[q]), st);
@@ -104,7 +107,8 @@ uf_status enqueue(uf_batch *b, hipStream_t st)
         if (b->den_mode != 0 && J.method != UF_WEIGHTED_UNNORMALIZED)
             UF_TRY(launch_rowdot(J.method, p->counts.p, p->cw, p->cstride, 0, p->hp.n_nodes - 1,
                                  p->totals.as<int32_t>(), p->len_slot.as<double>(), g.n,
-                                 p->D.as<double>(), true, st), "per-sample sums");
+                                 p->D.as<double>(), true, p->rowdot_part.as<double>(), st),
+                   "per-sample sums");
         UF_TRY(timed(b->prof, "condense", st, [&] {
                    return launch_condense(J.method, p->num.as<double>(),
                                           b->den_mode == 0 ? p->den.as<double>() : nullptr,
@@ -130,7 +134,7 @@ uf_status enqueue(uf_batch *b, hipStream_t st)
         }
         UF_TRY(timed(b->prof, "mfma", st, [&] {
                    return launch_mfma_queue(b->mfma_jobs.as<MfmaArgs>(), b->mfma_items.as<int32_t>(),
-                                            b->n_mfma_items, b->counters.as<int32_t>() + 2,
+                                            b->n_mfma_items, b->counters.as<int32_t>() + uf_batch::kQueues,
                                             std::min(b->n_groups / 2, b->n_mfma_items), st);
                }), "queued matrix-core product");
         for (int32_t j = 0; j < nj; ++j) {
@@ -215,28 +219,30 @@ uf_status build_tables(uf_batch *b, hipStream_t st)
     std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
         return b->plans[x]->hp.n_nodes > b->plans[y]->hp.n_nodes;
     });
-    b->stripe_of_job.assign(nj, -1);
-    for (int q = 0; q < 2; ++q) {
-        const bool fp64 = (q == 0);
+    for (int q = 0; q < uf_batch::kQueues; ++q) {
+        const bool fp64 = (q & 4) == 0;
         std::vector<StripeArgs> sj;
         std::vector<int32_t> items;
         for (int32_t j : order) {
             const uf_job &J = b->jobs[j];
             if (!is_striped(J) || (J.prec == UF_PREC_FP64) != fp64) continue;
+            // the unnormalized variant runs the weighted-normalized numerator
+            const int32_t km = J.method == UF_WEIGHTED_UNNORMALIZED ? UF_WEIGHTED_NORMALIZED : J.method;
             uf_plan *p = b->plans[j];
+            if ((km == UF_WEIGHTED_NORMALIZED) != ((q & 2) != 0) || (p->cw == 2) != ((q & 1) != 0)) continue;
             const HostPrep &hp = p->hp;
             const StripeGeom g = stripe_geometry(hp.n_samples, fp64, b->den_mode, b->tile);
             const size_t state = (size_t)g.spad * g.sstride * sizeof(double);
             UF_TRY(p->num.ensure(state), "allocating stripes");
             if (b->den_mode == 0) UF_TRY(p->den.ensure(state), "allocating stripes");
             UF_TRY(p->D.ensure((size_t)hp.n_samples * sizeof(double)), "allocating sums");
+            if (b->den_mode != 0)
+                UF_TRY(p->rowdot_part.ensure(rowdot_scratch_elems(hp.n_samples, hp.n_nodes - 1) * sizeof(double)),
+                       "allocating sum scratch");
             UF_TRY(p->inv_t.ensure((size_t)hp.n_samples * sizeof(double)), "allocating totals");
             int32_t E = b->emb_batch > 0 ? b->emb_batch : (fp64 ? 1024 : 128);
             E = std::max(1, std::min(E, std::max(1, hp.n_nodes - 1)));
             const int32_t idx = (int32_t)sj.size();
-            b->stripe_of_job[j] = idx;
-            // the unnormalized variant runs the weighted-normalized numerator
-            const int32_t km = J.method == UF_WEIGHTED_UNNORMALIZED ? UF_WEIGHTED_NORMALIZED : J.method;
             sj.push_back(make_stripe_args(km, p->counts.p, p->cw, p->cstride,
                                           p->inv_t.as<double>(), p->len_slot.as<double>(),
                                           hp.n_nodes - 1, E, p->num.as<double>(),
@@ -293,7 +299,7 @@ uf_status build_tables(uf_batch *b, hipStream_t st)
     b->n_mfma_items = (int32_t)(mitems.size() / 2);
     UF_TRY(upload(b->mfma_jobs, mj, st), "uploading matrix-core jobs");
     UF_TRY(upload(b->mfma_items, mitems, st), "uploading matrix-core items");
-    UF_TRY(b->counters.ensure(4 * sizeof(int32_t)), "allocating counters");
+    UF_TRY(b->counters.ensure((uf_batch::kQueues + 1) * sizeof(int32_t)), "allocating counters");
     UF_TRY(hipStreamSynchronize(st), "synchronizing");
     return UF_OK;
 }
@@ -455,8 +461,11 @@ void uf_batch_destroy(uf_batch *b)
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);
     if (b->ev_out) (void)hipEventDestroy(b->ev_out);
     for (uf_plan *p : b->plans) uf_plan_destroy(p);
-    for (DevMem *m : {&b->prop_jobs, &b->scatter_tasks, &b->level_tasks, &b->stripe_jobs[0],
-                      &b->stripe_jobs[1], &b->stripe_items[0], &b->stripe_items[1], &b->mfma_jobs,
+    for (int q = 0; q < uf_batch::kQueues; ++q) {
+        b->stripe_jobs[q].release();
+        b->stripe_items[q].release();
+    }
+    for (DevMem *m : {&b->prop_jobs, &b->scatter_tasks, &b->level_tasks, &b->mfma_jobs,
                       &b->mfma_items, &b->mfma_tiles, &b->counters})
         m->release();
     b->prof.release();

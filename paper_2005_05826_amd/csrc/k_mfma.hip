@@ -8,7 +8,7 @@
 // so the pairwise work is one symmetric product, run on bf16 MFMA.  Each length is split
 // into two bf16 terms, hi = bf16(L) and lo = bf16(L - hi) (the subtraction is exact in
 // FP32), so S = P diag(hi) P^T + P diag(lo) P^T with 0/1 operands exact in bf16.  Products
-// accumulate in FP32 inside chunks of k_chunk branches and are flushed into FP64 registers
+// accumulate in FP32 inside chunks of k_chunk branches and are added into the FP64 output
 // between chunks; the final division is FP64.
 //
 // Layout: presence is stored once per sample as one byte per branch (0x00 or 0xFF),
@@ -96,24 +96,18 @@ __device__ inline bf16x8 as_bf16x8(uint32_t a, uint32_t b, uint32_t c, uint32_t 
 }
 
 // Two LDS stages: the next stage's global loads are in flight while this one computes.
+// hl holds the stage's hi splits followed by its lo splits.
 struct MfmaSmem {
     __align__(16) uint8_t A[2][GM * LDK];
     __align__(16) uint8_t B[2][GM * LDK];
-    __align__(16) uint16_t h[2][GK];
-    __align__(16) uint16_t l[2][GK];
+    __align__(16) uint16_t hl[2][2 * GK];
 };
 
 // One GM x GM tile of S = P diag(hi + lo) P^T (rows row0.., columns col0.., row0 <= col0):
 // writes S_ij (i < j) into the condensed array and S_ii into T.
 __device__ void mfma_tile(const MfmaArgs &a, int32_t row0, int32_t col0, MfmaSmem &sm)
 {
-    auto &sA = sm.A;
-    auto &sB = sm.B;
-    auto &sh = sm.h;
-    auto &sl = sm.l;
     const uint8_t *__restrict__ P = a.P;
-    const uint16_t *__restrict__ hi = a.hi;
-    const uint16_t *__restrict__ lo = a.lo;
     const int64_t k_pad = a.k_pad;
     const int32_t n_kstep = a.n_kstep, chunk_steps = a.chunk_steps, n = a.n;
     double *__restrict__ S = a.S;
@@ -126,48 +120,31 @@ __device__ void mfma_tile(const MfmaArgs &a, int32_t row0, int32_t col0, MfmaSme
     const int lrow = lane & 31;
     const int kg = lane >> 5;
 
-    f32x16 acc[2][2];
-    double acc64[2][2][16];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                acc[a][b][r] = 0.f;
-                acc64[a][b][r] = 0.0;
-            }
-        }
-
-    // each thread stages 32 bytes of one A row and one B row, and (64 threads) one dword
-    // of the hi or lo splits
+    // each thread stages 32 bytes of one A row and one B row, and one dword of the hi or lo
+    // splits (threads 64.. repeat the dwords of threads 0..63, writing the same values)
     const uint8_t *pa = P + (int64_t)(row0 + (tid >> 1)) * k_pad + (tid & 1) * 32;
     const uint8_t *pb = P + (int64_t)(col0 + (tid >> 1)) * k_pad + (tid & 1) * 32;
+    const uint32_t *phl = reinterpret_cast<const uint32_t *>((tid & 32) ? a.lo : a.hi) + (tid & 31);
     const int soff = (tid >> 1) * LDK + (tid & 1) * 32;
+    const int hoff = tid & 63;
     uint4 ra0, ra1, rb0, rb1;
-    uint32_t rhl = 0;
+    uint32_t rhl;
     auto gload = [&](int32_t ks) {
         const int64_t k0 = (int64_t)ks * GK;
         ra0 = *reinterpret_cast<const uint4 *>(pa + k0);
         ra1 = *reinterpret_cast<const uint4 *>(pa + k0 + 16);
         rb0 = *reinterpret_cast<const uint4 *>(pb + k0);
         rb1 = *reinterpret_cast<const uint4 *>(pb + k0 + 16);
-        if (tid < 32)
-            rhl = reinterpret_cast<const uint32_t *>(hi + k0)[tid];
-        else if (tid < 64)
-            rhl = reinterpret_cast<const uint32_t *>(lo + k0)[tid - 32];
+        rhl = phl[k0 / 2];
     };
     auto lstore = [&](int buf) {
-        uint2 *da = reinterpret_cast<uint2 *>(sA[buf] + soff);
-        uint2 *db = reinterpret_cast<uint2 *>(sB[buf] + soff);
+        uint2 *da = reinterpret_cast<uint2 *>(sm.A[buf] + soff);
+        uint2 *db = reinterpret_cast<uint2 *>(sm.B[buf] + soff);
         da[0] = make_uint2(ra0.x, ra0.y); da[1] = make_uint2(ra0.z, ra0.w);
         da[2] = make_uint2(ra1.x, ra1.y); da[3] = make_uint2(ra1.z, ra1.w);
         db[0] = make_uint2(rb0.x, rb0.y); db[1] = make_uint2(rb0.z, rb0.w);
         db[2] = make_uint2(rb1.x, rb1.y); db[3] = make_uint2(rb1.z, rb1.w);
-        if (tid < 32)
-            reinterpret_cast<uint32_t *>(sh[buf])[tid] = rhl;
-        else if (tid < 64)
-            reinterpret_cast<uint32_t *>(sl[buf])[tid - 32] = rhl;
+        reinterpret_cast<uint32_t *>(sm.hl[buf])[hoff] = rhl;
     };
 
     if (n_kstep > 0) {
@@ -175,82 +152,102 @@ __device__ void mfma_tile(const MfmaArgs &a, int32_t row0, int32_t col0, MfmaSme
         lstore(0);
     }
     __syncthreads();
-    for (int32_t ks = 0; ks < n_kstep; ++ks) {
-        const int buf = ks & 1;
-        const bool more = ks + 1 < n_kstep;
-        if (more) gload(ks + 1);
-        const uint8_t *cA = sA[buf];
-        const uint8_t *cB = sB[buf];
+    int32_t ks = 0;
+    while (ks < n_kstep) {
+        // FP32 accumulation inside a chunk of chunk_steps stages, then one FP64 flush
+        const int32_t kend = (n_kstep - ks) < chunk_steps ? n_kstep : ks + chunk_steps;
+        f32x16 acc[2][2];
 #pragma unroll
-        for (int kk = 0; kk < GK / 16; ++kk) {
-            const int koff = kk * 16 + kg * 8;
-            const uint4 h = *reinterpret_cast<const uint4 *>(sh[buf] + koff);
-            const uint4 l = *reinterpret_cast<const uint4 *>(sl[buf] + koff);
-            bf16x8 ahi[2], alo[2], bo[2];
+        for (int x = 0; x < 2; ++x)
 #pragma unroll
-            for (int mb = 0; mb < 2; ++mb) {
-                const uint2 m = *reinterpret_cast<const uint2 *>(cA + (wm * 64 + mb * 32 + lrow) * LDK + koff);
-                const uint32_t m0 = __builtin_amdgcn_perm(m.x, m.x, 0x01010000u);
-                const uint32_t m1 = __builtin_amdgcn_perm(m.x, m.x, 0x03030202u);
-                const uint32_t m2 = __builtin_amdgcn_perm(m.y, m.y, 0x01010000u);
-                const uint32_t m3 = __builtin_amdgcn_perm(m.y, m.y, 0x03030202u);
-                ahi[mb] = as_bf16x8(m0 & h.x, m1 & h.y, m2 & h.z, m3 & h.w);
-                alo[mb] = as_bf16x8(m0 & l.x, m1 & l.y, m2 & l.z, m3 & l.w);
-            }
+            for (int y = 0; y < 2; ++y)
 #pragma unroll
-            for (int nb = 0; nb < 2; ++nb) {
-                const uint2 m = *reinterpret_cast<const uint2 *>(cB + (wn * 64 + nb * 32 + lrow) * LDK + koff);
-                bo[nb] = as_bf16x8(__builtin_amdgcn_perm(m.x, m.x, 0x01010000u) & kOne2,
-                                   __builtin_amdgcn_perm(m.x, m.x, 0x03030202u) & kOne2,
-                                   __builtin_amdgcn_perm(m.y, m.y, 0x01010000u) & kOne2,
-                                   __builtin_amdgcn_perm(m.y, m.y, 0x03030202u) & kOne2);
-            }
+                for (int r = 0; r < 16; ++r) acc[x][y][r] = 0.f;
+        for (; ks < kend; ++ks) {
+            const int buf = ks & 1;
+            const bool more = ks + 1 < n_kstep;
+            if (more) gload(ks + 1);
+            const uint8_t *cA = sm.A[buf];
+            const uint8_t *cB = sm.B[buf];
+            const uint16_t *chl = sm.hl[buf];
 #pragma unroll
-            for (int mb = 0; mb < 2; ++mb)
+            for (int kk = 0; kk < GK / 16; ++kk) {
+                const int koff = kk * 16 + kg * 8;
+                const uint4 h = *reinterpret_cast<const uint4 *>(chl + koff);
+                const uint4 l = *reinterpret_cast<const uint4 *>(chl + GK + koff);
+                bf16x8 ahi[2], alo[2], bo[2];
+#pragma unroll
+                for (int mb = 0; mb < 2; ++mb) {
+                    const uint2 m = *reinterpret_cast<const uint2 *>(cA + (wm * 64 + mb * 32 + lrow) * LDK + koff);
+                    const uint32_t m0 = __builtin_amdgcn_perm(m.x, m.x, 0x01010000u);
+                    const uint32_t m1 = __builtin_amdgcn_perm(m.x, m.x, 0x03030202u);
+                    const uint32_t m2 = __builtin_amdgcn_perm(m.y, m.y, 0x01010000u);
+                    const uint32_t m3 = __builtin_amdgcn_perm(m.y, m.y, 0x03030202u);
+                    ahi[mb] = as_bf16x8(m0 & h.x, m1 & h.y, m2 & h.z, m3 & h.w);
+                    alo[mb] = as_bf16x8(m0 & l.x, m1 & l.y, m2 & l.z, m3 & l.w);
+                }
 #pragma unroll
                 for (int nb = 0; nb < 2; ++nb) {
-                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[mb], bo[nb], acc[mb][nb], 0, 0, 0);
-                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo[mb], bo[nb], acc[mb][nb], 0, 0, 0);
+                    const uint2 m = *reinterpret_cast<const uint2 *>(cB + (wn * 64 + nb * 32 + lrow) * LDK + koff);
+                    bo[nb] = as_bf16x8(__builtin_amdgcn_perm(m.x, m.x, 0x01010000u) & kOne2,
+                                       __builtin_amdgcn_perm(m.x, m.x, 0x03030202u) & kOne2,
+                                       __builtin_amdgcn_perm(m.y, m.y, 0x01010000u) & kOne2,
+                                       __builtin_amdgcn_perm(m.y, m.y, 0x03030202u) & kOne2);
                 }
-        }
-        if ((ks + 1) % chunk_steps == 0 || !more) {
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+                for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-                for (int b = 0; b < 2; ++b)
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        acc64[a][b][r] += (double)acc[a][b][r];
-                        acc[a][b][r] = 0.f;
+                    for (int nb = 0; nb < 2; ++nb) {
+                        acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[mb], bo[nb], acc[mb][nb], 0, 0, 0);
+                        acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo[mb], bo[nb], acc[mb][nb], 0, 0, 0);
                     }
+            }
+            if (more) lstore(buf ^ 1);
+            __syncthreads();
         }
-        if (more) lstore(buf ^ 1);
-        __syncthreads();
-    }
-
-    // 32x32 accumulator layout: lane l, register r holds row 8*(r/4) + 4*(l/32) + r%4 and
-    // column l%32 of the block.
+        // FP64 cross-chunk sum kept in the output itself: the first chunk stores, later
+        // chunks add (each element belongs to this work-group alone, chunks in K order).
+        // 32x32 accumulator layout: lane l, register r holds row 8*(r/4) + 4*(l/32) + r%4
+        // and column l%32 of the block.
+        const bool first = (kend <= chunk_steps);
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
+        for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb)
+            for (int nb = 0; nb < 2; ++nb) {
+                // one 32 x 32 block at a time keeps the flush's live registers small
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int32_t i = row0 + wm * 64 + mb * 32 + 8 * (r >> 2) + 4 * kg + (r & 3);
-                const int32_t j = col0 + wn * 64 + nb * 32 + lrow;
-                if (i < n && j < n) {
-                    if (i < j)
-                        S[(int64_t)n * i - (int64_t)i * (i + 1) / 2 + (j - i - 1)] = acc64[mb][nb][r];
-                    else if (i == j)
-                        T[i] = acc64[mb][nb][r];
+                for (int r = 0; r < 16; ++r) {
+                    const int32_t i = row0 + wm * 64 + mb * 32 + 8 * (r >> 2) + 4 * kg + (r & 3);
+                    const int32_t j = col0 + wn * 64 + nb * 32 + lrow;
+                    if (i < n && j < n && i <= j) {
+                        double *dst = i < j ? S + ((int64_t)n * i - (int64_t)i * (i + 1) / 2 + (j - i - 1)) : T + i;
+                        const double v = (double)acc[mb][nb][r];
+                        *dst = first ? v : *dst + v;
+                    }
                 }
             }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (n_kstep == 0) {   // no branches: every shared length is 0
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int32_t i = row0 + wm * 64 + mb * 32 + 8 * (r >> 2) + 4 * kg + (r & 3);
+                    const int32_t j = col0 + wn * 64 + nb * 32 + lrow;
+                    if (i < n && j < n && i <= j)
+                        *(i < j ? S + ((int64_t)n * i - (int64_t)i * (i + 1) / 2 + (j - i - 1)) : T + i) = 0.0;
+                }
+    }
 }
 
 // Single job.  Work-group b takes tile (b % 8) * per + b / 8 of the upper-triangular list,
 // so the 8 XCDs (which receive work-groups round-robin) each sweep a contiguous run of
 // tiles that share A panels in their L2.
-__global__ __launch_bounds__(256, 1) void k_mfma_gemm(MfmaArgs a, const int2 *__restrict__ tiles,
+__global__ __launch_bounds__(256, 2) void k_mfma_gemm(MfmaArgs a, const int2 *__restrict__ tiles,
                                                      int32_t n_tiles)
 {
     __shared__ MfmaSmem sm;
@@ -263,7 +260,7 @@ __global__ __launch_bounds__(256, 1) void k_mfma_gemm(MfmaArgs a, const int2 *__
 
 // Many jobs: work-groups take (job, tile) items from a global counter (items listed
 // largest job first), leaving at the first fetch past the end.  *counter is zero at launch.
-__global__ __launch_bounds__(256, 1) void k_mfma_queue(const MfmaArgs *__restrict__ jobs,
+__global__ __launch_bounds__(256, 2) void k_mfma_queue(const MfmaArgs *__restrict__ jobs,
                                                       const int2 *__restrict__ items,
                                                       int32_t n_items, int32_t *__restrict__ counter)
 {

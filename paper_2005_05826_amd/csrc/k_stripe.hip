@@ -27,12 +27,12 @@ constexpr int kBlock = 256;  // 4 waves: wave w owns stripes [w*TST, (w+1)*TST) 
 template <typename T, int DEN, int TILE>
 struct StripeCfg;
 template <> struct StripeCfg<double, 0, 0> { static constexpr int TKT = 4, TST = 8, EB = 16; };
-template <> struct StripeCfg<double, 0, 1> { static constexpr int TKT = 2, TST = 16, EB = 16; };
+template <> struct StripeCfg<double, 0, 1> { static constexpr int TKT = 2, TST = 12, EB = 16; };
 template <> struct StripeCfg<double, 1, 0> { static constexpr int TKT = 4, TST = 16, EB = 16; };
-template <> struct StripeCfg<double, 1, 1> { static constexpr int TKT = 2, TST = 32, EB = 16; };
+template <> struct StripeCfg<double, 1, 1> { static constexpr int TKT = 2, TST = 24, EB = 16; };
 template <> struct StripeCfg<float, 0, 0> { static constexpr int TKT = 4, TST = 16, EB = 16; };
 template <> struct StripeCfg<float, 0, 1> { static constexpr int TKT = 8, TST = 8, EB = 16; };
-template <> struct StripeCfg<float, 1, 0> { static constexpr int TKT = 4, TST = 32, EB = 16; };
+template <> struct StripeCfg<float, 1, 0> { static constexpr int TKT = 4, TST = 24, EB = 16; };
 template <> struct StripeCfg<float, 1, 1> { static constexpr int TKT = 8, TST = 16, EB = 16; };
 
 // Pins a register value at this point of the program: the conversions that follow cannot
@@ -172,12 +172,33 @@ __global__ __launch_bounds__(kBlock, 2) void k_stripe(
 // accumulator.
 template <typename T, int DEN, int TILE>
 struct StripeSmem {
-    static constexpr int TKT = StripeCfg<T, DEN, TILE>::TKT, TST = StripeCfg<T, DEN, TILE>::TST,
-                         EB = StripeCfg<T, DEN, TILE>::EB;
+    static constexpr int TKT = StripeCfg<T, DEN, TILE>::TKT, TST = StripeCfg<T, DEN, TILE>::TST;
     static constexpr int TKW = 64 * TKT, TSW = 4 * TST, VW = TKW + TSW;
-    T su[EB * TKW];
-    T sv[EB * VW];
+    // branches per stage: two stages must fit half of the 160 KB LDS (two work-groups per
+    // CU), and the next stage's counts wait in registers (EB x 3 per thread)
+    static constexpr int EBM = 81664 / (2 * (TKW + VW) * (int)sizeof(T));
+    static constexpr int EB = EBM < 8 ? EBM : 8;
+    __align__(16) T su[2][EB * TKW];
+    __align__(16) T sv[2][EB * VW];
+    __align__(16) T sl[2][EB];   // the stage's branch lengths
 };
+
+// Reads N consecutive values from 16-byte aligned LDS with 16-byte loads (N rounded up to
+// whole loads; the caller guarantees the rounded range stays inside the array).
+template <typename T, int N>
+__device__ inline void lds_read_vec(const T *src, T (&dst)[N])
+{
+    constexpr int CH = 16 / (int)sizeof(T);
+    constexpr int NR = (N + CH - 1) / CH;
+    typedef T vec __attribute__((ext_vector_type(CH)));
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        const vec x = *reinterpret_cast<const vec *>(src + q * CH);
+#pragma unroll
+        for (int c = 0; c < CH; ++c)
+            if (q * CH + c < N) dst[q * CH + c] = x[c];
+    }
+}
 
 template <typename T, int METHOD, int DEN, int TILE, typename CT>
 __device__ void stripe_tile(const StripeArgs &a, int32_t k0, int32_t s0, StripeSmem<T, DEN, TILE> &sm)
@@ -192,7 +213,7 @@ __device__ void stripe_tile(const StripeArgs &a, int32_t k0, int32_t s0, StripeS
     const double *__restrict__ len = a.len;
     const int64_t cstride = a.cstride, sstride = a.sstride;
     const int32_t n = a.n, S = a.S, B = a.B, E = a.E;
-    T *su = sm.su, *sv = sm.sv;
+    if (B <= 0) return;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -218,80 +239,112 @@ __device__ void stripe_tile(const StripeArgs &a, int32_t k0, int32_t s0, StripeS
         vs[q] = k >= 0 ? (METHOD == UF_WEIGHTED_NORMALIZED ? (T)a.inv_t[k] : T(1)) : T(0);
     }
 
-    for (int32_t b0 = 0; b0 < B; b0 += E) {
-        const int32_t b1 = (B - b0) < E ? B : b0 + E;
-        T an[TST][TKT], ad[TST][TKT];
+    // Stage pipeline: the count rows of the next stage are loaded into registers while the
+    // current stage computes from LDS, then written to the other LDS buffer; one barrier per
+    // stage.  Rows past a stage's end re-read its last row and are never stored; padding
+    // positions read sample 0 and are zeroed by their scale.
+    int32_t cu[EB][NU_T], cv[EB][NV_T];
+    double rl = 0.0;
+    auto gload = [&](int32_t e0, int32_t eb) {
+        rl = tid < eb ? len[e0 + tid] : 0.0;
 #pragma unroll
-        for (int s = 0; s < TST; ++s)
+        for (int e = 0; e < EB; ++e) {
+            const CT *row = C + (int64_t)(e0 + (e < eb ? e : eb - 1)) * cstride;
 #pragma unroll
-            for (int r = 0; r < TKT; ++r) {
-                an[s][r] = T(0);
-                ad[s][r] = T(0);
-            }
-        for (int32_t e0 = b0; e0 < b1; e0 += EB) {
-            const int eb = (b1 - e0) < EB ? (b1 - e0) : EB;
-            // issue every load of the stage before the first use (rows past the batch end
-            // re-read the last row and are never stored); padding positions read sample 0
-            // and are zeroed by their scale
-            int32_t cu[EB][NU_T], cv[EB][NV_T];
+            for (int q = 0; q < NU_T; ++q) cu[e][q] = (int32_t)row[uk[q]];
 #pragma unroll
-            for (int e = 0; e < EB; ++e) {
-                const CT *row = C + (int64_t)(e0 + (e < eb ? e : eb - 1)) * cstride;
+            for (int q = 0; q < NV_T; ++q) cv[e][q] = (int32_t)row[vk[q]];
+        }
+    };
+    auto lstore = [&](int buf, int32_t eb) {
+        T *su = sm.su[buf], *sv = sm.sv[buf];
+        if (tid < EB) sm.sl[buf][tid] = (T)rl;
 #pragma unroll
-                for (int q = 0; q < NU_T; ++q) cu[e][q] = (int32_t)row[uk[q]];
+        for (int e = 0; e < EB; ++e) {
+            if (e < eb) {
 #pragma unroll
-                for (int q = 0; q < NV_T; ++q) cv[e][q] = (int32_t)row[vk[q]];
-            }
-            __syncthreads();
+                for (int q = 0; q < NU_T; ++q) {
+                    const int32_t x = tid + q * kBlock;
+                    const int32_t c = cu[e][q];
+                    if (x < TKW)
+                        su[e * TKW + x] = METHOD == UF_WEIGHTED_NORMALIZED ? (T)c * us[q]
+                                                                          : (c > 0 ? us[q] : T(0));
+                }
 #pragma unroll
-            for (int e = 0; e < EB; ++e) {
-                if (e < eb) {
-#pragma unroll
-                    for (int q = 0; q < NU_T; ++q) {
-                        const int32_t x = tid + q * kBlock;
-                        const int32_t c = cu[e][q];
-                        if (x < TKW)
-                            su[e * TKW + x] = METHOD == UF_WEIGHTED_NORMALIZED
-                                                  ? (T)c * us[q]
-                                                  : (c > 0 ? us[q] : T(0));
-                    }
-#pragma unroll
-                    for (int q = 0; q < NV_T; ++q) {
-                        const int32_t x = tid + q * kBlock;
-                        const int32_t c = cv[e][q];
-                        if (x < VW)
-                            sv[e * VW + x] = METHOD == UF_WEIGHTED_NORMALIZED
-                                                 ? (T)c * vs[q]
-                                                 : (c > 0 ? vs[q] : T(0));
-                    }
+                for (int q = 0; q < NV_T; ++q) {
+                    const int32_t x = tid + q * kBlock;
+                    const int32_t c = cv[e][q];
+                    if (x < VW)
+                        sv[e * VW + x] = METHOD == UF_WEIGHTED_NORMALIZED ? (T)c * vs[q]
+                                                                         : (c > 0 ? vs[q] : T(0));
                 }
             }
-            __syncthreads();
-#pragma unroll 1
-            for (int e = 0; e < eb; ++e) {
-                const T L = (T)len[e0 + e];
-                T u[TKT], v[NV];
-#pragma unroll
-                for (int r = 0; r < TKT; ++r) u[r] = su[e * TKW + lane * TKT + r];
-#pragma unroll
-                for (int c = 0; c < NV; ++c) v[c] = sv[e * VW + lane * TKT + w * TST + c];
-#pragma unroll
-                for (int s = 0; s < TST; ++s)
-#pragma unroll
-                    for (int r = 0; r < TKT; ++r) {
-                        const T x = v[r + s];
-                        an[s][r] = fma(fabs(u[r] - x), L, an[s][r]);
-                        if (DEN == 0) {
-                            if (METHOD == UF_WEIGHTED_NORMALIZED)
-                                ad[s][r] = fma(u[r] + x, L, ad[s][r]);
-                            else
-                                ad[s][r] = fma(fmax(u[r], x), L, ad[s][r]);
-                        }
-                    }
-            }
         }
-        add_tile<TST, TKT, DEN>(an, ad, a.num, a.den,
-                                (int64_t)(s0 - a.s_base + w * TST) * sstride + k0 + lane * TKT, sstride);
+    };
+
+    T an[TST][TKT], ad[TST][TKT];
+#pragma unroll
+    for (int s = 0; s < TST; ++s)
+#pragma unroll
+        for (int r = 0; r < TKT; ++r) {
+            an[s][r] = T(0);
+            ad[s][r] = T(0);
+        }
+    // stages: windows of at most EB branches inside batches [b0, b1) of E branches
+    int32_t b1 = E < B ? E : B;
+    int32_t e0 = 0;
+    int32_t eb = (b1 - e0) < EB ? (b1 - e0) : EB;
+    int buf = 0;
+    gload(e0, eb);
+    lstore(0, eb);
+    __syncthreads();
+    for (;;) {
+        int32_t ne0 = e0 + eb, nb1 = b1;
+        if (ne0 >= b1) nb1 = (B - b1) < E ? B : b1 + E;
+        const bool more = ne0 < B;
+        const int32_t neb = more ? ((nb1 - ne0) < EB ? (nb1 - ne0) : EB) : 0;
+        if (more) gload(ne0, neb);
+        const T *su = sm.su[buf], *sv = sm.sv[buf], *sl = sm.sl[buf];
+        static_assert((NV + 16 / sizeof(T) - 1) / (16 / sizeof(T)) * (16 / sizeof(T)) <= TKT + TST,
+                      "vector reads of the v window stay inside the staged row");
+#pragma unroll 1
+        for (int e = 0; e < eb; ++e) {
+            const T L = sl[e];
+            T u[TKT], v[NV];
+            lds_read_vec<T, TKT>(su + e * TKW + lane * TKT, u);
+            lds_read_vec<T, NV>(sv + e * VW + lane * TKT + w * TST, v);
+#pragma unroll
+            for (int s = 0; s < TST; ++s)
+#pragma unroll
+                for (int r = 0; r < TKT; ++r) {
+                    const T x = v[r + s];
+                    an[s][r] = fma(fabs(u[r] - x), L, an[s][r]);
+                    if (DEN == 0) {
+                        if (METHOD == UF_WEIGHTED_NORMALIZED)
+                            ad[s][r] = fma(u[r] + x, L, ad[s][r]);
+                        else
+                            ad[s][r] = fma(fmax(u[r], x), L, ad[s][r]);
+                    }
+                }
+        }
+        if (e0 + eb >= b1) {   // end of a batch: add the register tile into the FP64 state
+            add_tile<TST, TKT, DEN>(an, ad, a.num, a.den,
+                                    (int64_t)(s0 - a.s_base + w * TST) * sstride + k0 + lane * TKT, sstride);
+#pragma unroll
+            for (int s = 0; s < TST; ++s)
+#pragma unroll
+                for (int r = 0; r < TKT; ++r) {
+                    an[s][r] = T(0);
+                    ad[s][r] = T(0);
+                }
+        }
+        if (!more) break;
+        lstore(buf ^ 1, neb);
+        __syncthreads();
+        buf ^= 1;
+        e0 = ne0;
+        eb = neb;
+        b1 = nb1;
     }
 }
 
@@ -308,7 +361,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_stripe_fused(StripeArgs a)
 // is proportional to the job's branch count), so the dynamic queue is a longest-processing-
 // time-first schedule over the machine.  The counter must be zero at launch; every
 // work-group leaves the loop at its first fetch past the end.
-template <typename T, int DEN, int TILE>
+template <typename T, int METHOD, int DEN, int TILE, typename CT>
 __global__ __launch_bounds__(kBlock, 2) void k_stripe_queue(
     const StripeArgs *__restrict__ jobs, const int2 *__restrict__ items, int32_t n_items,
     int32_t *__restrict__ counter)
@@ -326,17 +379,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_stripe_queue(
         const StripeArgs a = jobs[item.x];
         const int32_t kt = item.y % a.tiles_k, stile = item.y / a.tiles_k;
         const int32_t k0 = kt * SM::TKW, s0 = a.s_base + stile * SM::TSW;
-        if (a.cw == 2) {
-            if (a.method == UF_WEIGHTED_NORMALIZED)
-                stripe_tile<T, UF_WEIGHTED_NORMALIZED, DEN, TILE, uint16_t>(a, k0, s0, sm);
-            else
-                stripe_tile<T, UF_UNWEIGHTED, DEN, TILE, uint16_t>(a, k0, s0, sm);
-        } else {
-            if (a.method == UF_WEIGHTED_NORMALIZED)
-                stripe_tile<T, UF_WEIGHTED_NORMALIZED, DEN, TILE, int32_t>(a, k0, s0, sm);
-            else
-                stripe_tile<T, UF_UNWEIGHTED, DEN, TILE, int32_t>(a, k0, s0, sm);
-        }
+        stripe_tile<T, METHOD, DEN, TILE, CT>(a, k0, s0, sm);
     }
 }
 
@@ -347,23 +390,39 @@ __global__ void k_inv_totals(const int32_t *__restrict__ totals, int32_t n, doub
     if (k < n) inv_t[k] = 1.0 / (double)totals[k];
 }
 
-// D[k] (+)= sum over the batch of L_e * u_k,e in FP64, for the separable denominator.
+// Separable denominator, D[k] (+)= sum over a batch of branches of L_e * u_k,e in FP64.
+// Pass 1: partial sums over chunks of branches, one thread per (sample, chunk), reading count
+// rows coalesced; the weighted form sums L * count and divides by the total once in pass 2.
+// Pass 2 adds the chunks of each sample in chunk order, so the result is deterministic.
 template <int METHOD, typename CT>
-__global__ void k_rowdot(const CT *__restrict__ C, int64_t cstride, int32_t slot0,
-                         int32_t E, const int32_t *__restrict__ totals,
-                         const double *__restrict__ len, int32_t n, double *__restrict__ D,
-                         int32_t first)
+__global__ void k_rowdot_part(const CT *__restrict__ C, int64_t cstride, int32_t slot0, int32_t E,
+                              int32_t chunk, const double *__restrict__ len, int32_t n,
+                              double *__restrict__ part)
 {
     const int32_t k = blockIdx.x * kBlock + threadIdx.x;
     if (k >= n) return;
-    const double t = (double)totals[k];
-    double acc = first ? 0.0 : D[k];
-    for (int32_t e = 0; e < E; ++e) {
-        const int32_t c = (int32_t)C[(int64_t)(slot0 + e) * cstride + k];
-        const double u = METHOD == UF_WEIGHTED_NORMALIZED ? (double)c / t : (c > 0 ? 1.0 : 0.0);
-        acc = fma(len[e], u, acc);
+    const int32_t e0 = (int32_t)blockIdx.y * chunk;
+    const int32_t e1 = (E - e0) < chunk ? E : e0 + chunk;
+    double acc = 0.0;
+#pragma unroll 8
+    for (int32_t e = e0; e < e1; ++e) {
+        const int32_t x = (int32_t)C[(int64_t)(slot0 + e) * cstride + k];
+        acc = fma(len[e], METHOD == UF_WEIGHTED_NORMALIZED ? (double)x : (x > 0 ? 1.0 : 0.0), acc);
     }
-    D[k] = acc;
+    part[(int64_t)blockIdx.y * n + k] = acc;
+}
+
+template <int METHOD>
+__global__ void k_rowdot_sum(const double *__restrict__ part, int32_t n_chunks,
+                             const int32_t *__restrict__ totals, int32_t n, double *__restrict__ D,
+                             int32_t first)
+{
+    const int32_t k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n) return;
+    double acc = 0.0;
+    for (int32_t c = 0; c < n_chunks; ++c) acc += part[(int64_t)c * n + k];
+    if (METHOD == UF_WEIGHTED_NORMALIZED) acc /= (double)totals[k];
+    D[k] = first ? acc : D[k] + acc;
 }
 
 // One work-group per condensed row i; d = num / den in FP64 (0 when den == 0).
@@ -605,40 +664,80 @@ StripeArgs make_stripe_args(int32_t method, const void *C, int32_t cw, int64_t c
     return a;
 }
 
-hipError_t launch_stripe_queue(bool fp64, int32_t den_mode, int32_t tile, const StripeArgs *jobs,
-                               const int32_t *items_xy, int32_t n_items, int32_t *counter,
-                               int32_t n_groups, hipStream_t st)
+hipError_t launch_stripe_queue(bool fp64, int32_t method, int32_t cw, int32_t den_mode, int32_t tile,
+                               const StripeArgs *jobs, const int32_t *items_xy, int32_t n_items,
+                               int32_t *counter, int32_t n_groups, hipStream_t st)
 {
     if (n_items <= 0) return hipSuccess;
     const int2 *it = reinterpret_cast<const int2 *>(items_xy);
+    const bool wn = (method == UF_WEIGHTED_NORMALIZED), c16 = (cw == 2);
+#define UF_Q(T, M, D, TL, CT) k_stripe_queue<T, M, D, TL, CT><<<n_groups, kBlock, 0, st>>>(jobs, it, n_items, counter)
+#define UF_QM(T, D, TL)                                                             \
+    do {                                                                            \
+        if (wn) {                                                                   \
+            if (c16) UF_Q(T, UF_WEIGHTED_NORMALIZED, D, TL, uint16_t);              \
+            else UF_Q(T, UF_WEIGHTED_NORMALIZED, D, TL, int32_t);                   \
+        } else {                                                                    \
+            if (c16) UF_Q(T, UF_UNWEIGHTED, D, TL, uint16_t);                       \
+            else UF_Q(T, UF_UNWEIGHTED, D, TL, int32_t);                            \
+        }                                                                           \
+    } while (0)
     const int key = (fp64 ? 4 : 0) + (den_mode ? 2 : 0) + (tile ? 1 : 0);
-#define UF_QUEUE(T, D, TL) k_stripe_queue<T, D, TL><<<n_groups, kBlock, 0, st>>>(jobs, it, n_items, counter)
     switch (key) {
-    case 0: UF_QUEUE(float, 0, 0); break;
-    case 1: UF_QUEUE(float, 0, 1); break;
-    case 2: UF_QUEUE(float, 1, 0); break;
-    case 3: UF_QUEUE(float, 1, 1); break;
-    case 4: UF_QUEUE(double, 0, 0); break;
-    case 5: UF_QUEUE(double, 0, 1); break;
-    case 6: UF_QUEUE(double, 1, 0); break;
-    default: UF_QUEUE(double, 1, 1); break;
+    case 0: UF_QM(float, 0, 0); break;
+    case 1: UF_QM(float, 0, 1); break;
+    case 2: UF_QM(float, 1, 0); break;
+    case 3: UF_QM(float, 1, 1); break;
+    case 4: UF_QM(double, 0, 0); break;
+    case 5: UF_QM(double, 0, 1); break;
+    case 6: UF_QM(double, 1, 0); break;
+    default: UF_QM(double, 1, 1); break;
     }
-#undef UF_QUEUE
+#undef UF_QM
+#undef UF_Q
     return hipGetLastError();
+}
+
+int32_t rowdot_chunk_len(int32_t n, int32_t E)
+{
+    // about 2,048 work-groups, chunks of at least 64 branches
+    const int64_t groups = (n + kBlock - 1) / kBlock;
+    int64_t want = std::max<int64_t>(1, (2048 + groups - 1) / groups);
+    want = std::min<int64_t>(want, std::max<int64_t>(1, ((int64_t)E + 63) / 64));
+    return (int32_t)std::max<int64_t>(1, ((int64_t)E + want - 1) / want);
+}
+
+size_t rowdot_scratch_elems(int32_t n, int32_t E)
+{
+    if (n <= 0 || E <= 0) return 1;
+    const int32_t ch = rowdot_chunk_len(n, E);
+    return (size_t)((E + ch - 1) / ch) * (size_t)n;
 }
 
 hipError_t launch_rowdot(int32_t method, const void *C, int32_t cw, int64_t cstride, int32_t slot0,
                          int32_t E, const int32_t *totals, const double *len, int32_t n,
-                         double *D, bool first, hipStream_t st)
+                         double *D, bool first, double *part, hipStream_t st)
 {
+    if (n <= 0) return hipSuccess;
     const int f = first ? 1 : 0;
-#define UF_RD(M, CT) k_rowdot<M, CT><<<grid1(n, kBlock), kBlock, 0, st>>>(static_cast<const CT *>(C), cstride, slot0, E, totals, len, n, D, f)
-    if (method == UF_WEIGHTED_NORMALIZED) {
-        if (cw == 2) UF_RD(UF_WEIGHTED_NORMALIZED, uint16_t); else UF_RD(UF_WEIGHTED_NORMALIZED, int32_t);
-    } else {
-        if (cw == 2) UF_RD(UF_UNWEIGHTED, uint16_t); else UF_RD(UF_UNWEIGHTED, int32_t);
+    const int32_t ch = rowdot_chunk_len(n, E);
+    const int32_t n_chunks = E > 0 ? (E + ch - 1) / ch : 0;
+    const dim3 grid(grid1(n, kBlock), (unsigned)std::max(n_chunks, 1));
+#define UF_RD(M, CT) k_rowdot_part<M, CT><<<grid, kBlock, 0, st>>>(static_cast<const CT *>(C), cstride, slot0, E, ch, len, n, part)
+    if (n_chunks > 0) {
+        if (method == UF_WEIGHTED_NORMALIZED) {
+            if (cw == 2) UF_RD(UF_WEIGHTED_NORMALIZED, uint16_t); else UF_RD(UF_WEIGHTED_NORMALIZED, int32_t);
+        } else {
+            if (cw == 2) UF_RD(UF_UNWEIGHTED, uint16_t); else UF_RD(UF_UNWEIGHTED, int32_t);
+        }
+        const hipError_t r = hipGetLastError();
+        if (r != hipSuccess) return r;
     }
 #undef UF_RD
+    if (method == UF_WEIGHTED_NORMALIZED)
+        k_rowdot_sum<UF_WEIGHTED_NORMALIZED><<<grid1(n, kBlock), kBlock, 0, st>>>(part, n_chunks, totals, n, D, f);
+    else
+        k_rowdot_sum<UF_UNWEIGHTED><<<grid1(n, kBlock), kBlock, 0, st>>>(part, n_chunks, totals, n, D, f);
     return hipGetLastError();
 }
 

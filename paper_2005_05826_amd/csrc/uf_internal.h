@@ -117,9 +117,9 @@ StripeArgs make_stripe_args(int32_t method, const void *C, int32_t cw, int64_t c
                             const double *inv_t, const double *len, int32_t B, int32_t E,
                             double *num, double *den, const StripeGeom &g);
 // items_xy: (job index, tile index) pairs, tile = s_tile * tiles_k + k_tile; *counter == 0.
-hipError_t launch_stripe_queue(bool fp64, int32_t den_mode, int32_t tile, const StripeArgs *jobs,
-                               const int32_t *items_xy, int32_t n_items, int32_t *counter,
-                               int32_t n_groups, hipStream_t st);
+hipError_t launch_stripe_queue(bool fp64, int32_t method, int32_t cw, int32_t den_mode, int32_t tile,
+                               const StripeArgs *jobs, const int32_t *items_xy, int32_t n_items,
+                               int32_t *counter, int32_t n_groups, hipStream_t st);
 hipError_t launch_inv_totals(const int32_t *totals, int32_t n, double *inv_t, hipStream_t st);
 // Covers stripe tiles [tile_s0, tile_s1); state row 0 holds stripe tile_s0 * tsw.
 hipError_t launch_stripe_fused(bool fp64, int32_t method, int32_t den_mode, int32_t tile,
@@ -132,10 +132,12 @@ hipError_t launch_condense_range(int32_t method, const double *num, const double
                                  int64_t sstride, int32_t n, int32_t S, int32_t s_base,
                                  int32_t s_begin, int32_t s_end, int32_t out_f32, void *out,
                                  hipStream_t st);
-// Per-sample sums D_k = sum_b L_b u_kb over a batch (separable denominator).
+// Per-sample sums D_k = sum_b L_b u_kb over a batch of E branches (separable denominator);
+// `part` holds rowdot_scratch_elems(n, E) doubles of scratch.
+size_t rowdot_scratch_elems(int32_t n, int32_t E);
 hipError_t launch_rowdot(int32_t method, const void *C, int32_t cw, int64_t cstride, int32_t slot0,
                          int32_t E, const int32_t *totals, const double *len, int32_t n,
-                         double *D, bool first, hipStream_t st);
+                         double *D, bool first, double *part, hipStream_t st);
 hipError_t launch_condense(int32_t method, const double *num, const double *den, const double *D,
                            int64_t sstride, int32_t n, int32_t S, int32_t out_f32, void *out,
                            hipStream_t st);

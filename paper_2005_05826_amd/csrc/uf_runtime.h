@@ -95,7 +95,7 @@ struct uf_plan {
     ufmi::DevMem indptr, entry_slot, entry_count, totals, child_ptr, child_slot, len_slot,
         slot_of_node;
     // scratch, allocated on first use
-    ufmi::DevMem counts, bits, emb, num, den, D, inv_t, out_tmp, gather_tmp;
+    ufmi::DevMem counts, bits, emb, num, den, D, inv_t, out_tmp, gather_tmp, rowdot_part;
     ufmi::DevMem mfma_scratch[4];
     ufmi::Profiler prof;
     int64_t cstride = 0;  // count elements per row (multiple of 64)

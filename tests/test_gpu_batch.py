@@ -62,8 +62,10 @@ def _check(jobs, outs, want, tag):
     for (p, m, prec), o, w in zip(jobs, outs, want):
         got = o.cpu().numpy()[: w.size].astype(np.float64)
         err = np.abs(got - w).max(initial=0.0)
+        # an FP32 output adds its own rounding, at most 2^-25 for distances in [0, 1]
+        tol = TOL[prec] + (6e-8 if o.dtype == torch.float32 else 0.0)
         print(f"[{tag}] n={p.n_samples} {m} {prec} max_abs_err={err:.3e}", flush=True)
-        assert err <= TOL[prec], (tag, p.n_samples, m, prec, err)
+        assert err <= tol, (tag, p.n_samples, m, prec, err)
 
 
 @pytest.mark.parametrize("den_mode", [0, 1])
