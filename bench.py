@@ -37,13 +37,35 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "sample-pair·branch updates/s + full-matrix wall time, FP32/MFMA vs FP64 plain"
-# VALU issue rate of one MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (lane-ops/s).
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Vector ALU peaks of one MI355X in lane-operations/s (one FMA, add or subtract on one lane
+# is one operation): 256 CUs x 4 SIMDs x 2.4 GHz x lanes per clock, 32 lanes for FP32 and
+# 16 for FP64, i.e. the datasheet's 157.3 and 78.6 TFLOP/s divided by 2 flops per FMA.
+VALU_PEAK_TOPS = {"fp32": 256 * 4 * 32 * 2.4e9 / 1e12, "fp64": 256 * 4 * 16 * 2.4e9 / 1e12}
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 HBM_PEAK_GBS = 8000.0
 # Algorithmic VALU operations per pair-branch update of the striped kernel:
 #   num += L*|u - v|  (sub, fma with |.|)   den += L*(u + v)  (add, fma)
 OPS_PER_UPDATE = {0: 4, 1: 2}   # den_mode 0: both stripes; 1: numerator only
+
+# HBM bytes per launch of the dominant kernel, from two rocprofv3 --pmc runs (FETCH_SIZE,
+# then WRITE_SIZE, KiB per dispatch) of this script's default configuration of each
+# workload, each scaled by what the same counter reads for a 1 GiB device copy
+# (--copy-calibration: FETCH_SIZE reads 0.5 GiB, WRITE_SIZE 1 GiB, so x2.0 and x1.0).
+# Keyed by workload and configuration; each entry records the SHA-256 of the kernel source
+# it was measured on, and is reported as null once that source has changed.
+TRAFFIC = {}
+
+
+def kernel_traffic(key, source):
+    import hashlib
+    ent = TRAFFIC.get(key)
+    if not ent:
+        return None
+    with open(os.path.join(ROOT, "paper_2005_05826_amd", "csrc", source), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest()[:16] != ent["src_sha256"]:
+            return None
+    return {"bytes": ent["bytes"], "fetch_bytes": ent["fetch"], "write_bytes": ent["write"],
+            "profile": ent["profile"]}
 
 
 def parse():
@@ -191,9 +213,11 @@ def bench_striped(args):
     if launches:
         ops = OPS_PER_UPDATE[args.den_mode] * updates
         achieved = ops / (total_ms / args.steps * 1e-3) / 1e12
+        peak = VALU_PEAK_TOPS[prec]
+        key = f"striped/{n}x{B}/{prec}/den{args.den_mode}/tile{args.tile}/E{args.emb_batch or 'default'}"
         roofline = {"kernel": "k_stripe_fused", "bound": "alu", "achieved": round(achieved, 3),
-                    "peak": round(VALU_PEAK_TOPS, 2), "unit": "Tops/s",
-                    "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+                    "peak": round(peak, 2), "unit": "Tops/s",
+                    "frac": round(achieved / peak, 4), "traffic": kernel_traffic(key, "k_stripe.hip"),
                     "launches_per_step": launches // args.steps,
                     "avg_launch_ms": round(total_ms / launches, 4),
                     "ops_per_update": OPS_PER_UPDATE[args.den_mode]}
@@ -211,6 +235,13 @@ def bench_striped(args):
                           "value": round(updates / dt2, 1),
                           "kernels_ms_per_step": {k: round(v[1] / steps2, 3) for k, v in prof2.items()},
                           "speedup_of_headline": round(dt2 / dt, 3)}
+        l2, t2 = prof2.get("stripe", (0, 0.0))
+        if l2 and compare in VALU_PEAK_TOPS:
+            a2 = OPS_PER_UPDATE[args.den_mode] * updates / (t2 / steps2 * 1e-3) / 1e12
+            res["compare"]["roofline"] = {"kernel": "k_stripe_fused", "bound": "alu",
+                                          "achieved": round(a2, 3), "unit": "Tops/s",
+                                          "peak": round(VALU_PEAK_TOPS[compare], 2),
+                                          "frac": round(a2 / VALU_PEAK_TOPS[compare], 4)}
     if not args.no_cpu:
         cpu, pi, pj, want = oracle_sample(prob, method, args.cpu_seconds, 20050526 + 99)
         res["cpu_baseline"] = cpu
@@ -252,9 +283,11 @@ def bench_mfma(args):
                        "n_samples": n, "branches": B, "method": "unweighted",
                        "precision": "mfma_bf16x2", "k_chunk": args.k_chunk or 4096})
     res["kernels_ms_per_step"] = {k: round(v[1] / args.steps, 3) for k, v in prof.items()}
+    key = f"mfma/{n}x{B}/k_chunk{args.k_chunk or 4096}"
     res["roofline"] = {"kernel": "k_mfma_gemm", "bound": "mfma", "achieved": round(achieved, 2),
                        "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
-                       "frac": round(achieved / MFMA_BF16_PEAK_TFLOPS, 4), "traffic": None,
+                       "frac": round(achieved / MFMA_BF16_PEAK_TFLOPS, 4),
+                       "traffic": kernel_traffic(key, "k_mfma.hip"),
                        "avg_launch_ms": round(total_ms / max(1, launches), 3)}
     if compare:
         out2 = torch.empty_like(out)
@@ -401,8 +434,8 @@ def bench_large(args, part):
                            "n_samples": n, "branches": B, "stripes": [s0, s1],
                            "precision": "fp32", "count_width": 2})
         res["roofline"] = {"kernel": "k_stripe_fused", "bound": "alu", "achieved": round(achieved, 3),
-                           "peak": round(VALU_PEAK_TOPS, 2), "unit": "Tops/s",
-                           "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None}
+                           "peak": round(VALU_PEAK_TOPS["fp32"], 2), "unit": "Tops/s",
+                           "frac": round(achieved / VALU_PEAK_TOPS["fp32"], 4), "traffic": None}
         method = "weighted_normalized"
     res["kernels_ms_per_step"] = {k: round(v[1] / args.steps, 3) for k, v in prof.items()}
     if not args.no_cpu:

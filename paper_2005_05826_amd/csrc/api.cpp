@@ -490,7 +490,7 @@ uf_status uf_plan_distance(uf_plan *plan, uf_method method, uf_precision prec,
     if (kn.den_mode != 0 && kn.den_mode != 1) return set_err(ctx, UF_E_ARG, "den_mode must be 0 or 1");
     if (kn.variant != 0 && kn.variant != 1) return set_err(ctx, UF_E_ARG, "variant must be 0 or 1");
     if (method == UF_WEIGHTED_UNNORMALIZED) kn.den_mode = 1;   // no denominator at all
-    if (kn.tile != 0 && kn.tile != 1) return set_err(ctx, UF_E_ARG, "tile must be 0 or 1");
+    if (kn.tile < 0 || kn.tile > 2) return set_err(ctx, UF_E_ARG, "tile must be 0, 1 or 2");
     UF_TRY(hipSetDevice(ctx->device), "hipSetDevice");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const size_t esz = out_dtype == UF_F32 ? sizeof(float) : sizeof(double);
@@ -541,7 +541,7 @@ uf_status uf_plan_distance_stripes(uf_plan *plan, uf_method method, uf_precision
     if (!out) return set_err(ctx, UF_E_ARG, "out must not be NULL");
     Knobs kn = resolve_knobs(tuning, prec, hp.n_nodes - 1);
     if (kn.den_mode != 0 && kn.den_mode != 1) return set_err(ctx, UF_E_ARG, "den_mode must be 0 or 1");
-    if (kn.tile != 0 && kn.tile != 1) return set_err(ctx, UF_E_ARG, "tile must be 0 or 1");
+    if (kn.tile < 0 || kn.tile > 2) return set_err(ctx, UF_E_ARG, "tile must be 0, 1 or 2");
     kn.variant = 0;
     if (method == UF_WEIGHTED_UNNORMALIZED) kn.den_mode = 1;
     UF_TRY(hipSetDevice(ctx->device), "hipSetDevice");

@@ -345,9 +345,9 @@ uf_status uf_batch_create(uf_context *ctx, const uf_job *jobs, int32_t n_jobs,
         b->count_width = tuning->count_width;
         if (tuning->k_chunk > 0) b->k_chunk = tuning->k_chunk;
     }
-    if ((b->den_mode != 0 && b->den_mode != 1) || (b->tile != 0 && b->tile != 1)) {
+    if ((b->den_mode != 0 && b->den_mode != 1) || (b->tile < 0 || b->tile > 2)) {
         delete b;
-        return set_err(ctx, UF_E_ARG, "den_mode and tile must be 0 or 1");
+        return set_err(ctx, UF_E_ARG, "den_mode must be 0 or 1 and tile 0, 1 or 2");
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
     b->jobs.assign(jobs, jobs + n_jobs);

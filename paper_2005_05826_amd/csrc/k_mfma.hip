@@ -317,14 +317,21 @@ MfmaGeom mfma_geometry(int32_t n, int32_t n_branches)
 
 void mfma_tile_list(int32_t n, std::vector<int32_t> *xy)
 {
+    // Upper-triangular tiles in groups of kGroup x kGroup tiles: the work-groups resident on
+    // one XCD at a time (2 per CU x 32 CUs) then cover one group, whose kGroup row panels and
+    // kGroup column panels are each shared by kGroup tiles through that XCD's L2.
+    constexpr int32_t kGroup = 8;
     const int32_t nb = (n + GM - 1) / GM;
+    const int32_t ng = (nb + kGroup - 1) / kGroup;
     xy->clear();
     xy->reserve((size_t)nb * (nb + 1));
-    for (int32_t I = 0; I < nb; ++I)
-        for (int32_t J = I; J < nb; ++J) {
-            xy->push_back(I);
-            xy->push_back(J);
-        }
+    for (int32_t gi = 0; gi < ng; ++gi)
+        for (int32_t gj = gi; gj < ng; ++gj)
+            for (int32_t I = gi * kGroup; I < std::min(nb, gi * kGroup + kGroup); ++I)
+                for (int32_t J = std::max(I, gj * kGroup); J < std::min(nb, gj * kGroup + kGroup); ++J) {
+                    xy->push_back(I);
+                    xy->push_back(J);
+                }
 }
 
 hipError_t launch_split_lengths(const double *len, int32_t B, int64_t k_pad, uint16_t *hi,

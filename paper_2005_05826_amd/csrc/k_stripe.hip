@@ -26,14 +26,20 @@ constexpr int kBlock = 256;  // 4 waves: wave w owns stripes [w*TST, (w+1)*TST) 
 // windows (2 * TKW + TSW values per branch for TKW * TSW updates).
 template <typename T, int DEN, int TILE>
 struct StripeCfg;
-template <> struct StripeCfg<double, 0, 0> { static constexpr int TKT = 4, TST = 8, EB = 16; };
-template <> struct StripeCfg<double, 0, 1> { static constexpr int TKT = 2, TST = 12, EB = 16; };
-template <> struct StripeCfg<double, 1, 0> { static constexpr int TKT = 4, TST = 16, EB = 16; };
-template <> struct StripeCfg<double, 1, 1> { static constexpr int TKT = 2, TST = 24, EB = 16; };
-template <> struct StripeCfg<float, 0, 0> { static constexpr int TKT = 4, TST = 16, EB = 16; };
-template <> struct StripeCfg<float, 0, 1> { static constexpr int TKT = 8, TST = 8, EB = 16; };
-template <> struct StripeCfg<float, 1, 0> { static constexpr int TKT = 4, TST = 24, EB = 16; };
-template <> struct StripeCfg<float, 1, 1> { static constexpr int TKT = 8, TST = 16, EB = 16; };
+// OCC: work-groups per CU the fused and queued kernels are compiled for (tile 2 trades a
+// smaller tile for three waves per SIMD).
+template <> struct StripeCfg<double, 0, 0> { static constexpr int TKT = 4, TST = 8, EB = 16, OCC = 2; };
+template <> struct StripeCfg<double, 0, 1> { static constexpr int TKT = 2, TST = 12, EB = 16, OCC = 2; };
+template <> struct StripeCfg<double, 0, 2> { static constexpr int TKT = 2, TST = 8, EB = 16, OCC = 3; };
+template <> struct StripeCfg<double, 1, 0> { static constexpr int TKT = 4, TST = 16, EB = 16, OCC = 2; };
+template <> struct StripeCfg<double, 1, 1> { static constexpr int TKT = 2, TST = 24, EB = 16, OCC = 2; };
+template <> struct StripeCfg<double, 1, 2> { static constexpr int TKT = 4, TST = 8, EB = 16, OCC = 3; };
+template <> struct StripeCfg<float, 0, 0> { static constexpr int TKT = 4, TST = 16, EB = 16, OCC = 2; };
+template <> struct StripeCfg<float, 0, 1> { static constexpr int TKT = 8, TST = 8, EB = 16, OCC = 2; };
+template <> struct StripeCfg<float, 0, 2> { static constexpr int TKT = 4, TST = 8, EB = 16, OCC = 3; };
+template <> struct StripeCfg<float, 1, 0> { static constexpr int TKT = 4, TST = 24, EB = 16, OCC = 2; };
+template <> struct StripeCfg<float, 1, 1> { static constexpr int TKT = 8, TST = 16, EB = 16, OCC = 2; };
+template <> struct StripeCfg<float, 1, 2> { static constexpr int TKT = 4, TST = 16, EB = 16, OCC = 3; };
 
 // Pins a register value at this point of the program: the conversions that follow cannot
 // be hoisted above it, which keeps the FP64 copies of a tile from being live all at once.
@@ -174,9 +180,10 @@ template <typename T, int DEN, int TILE>
 struct StripeSmem {
     static constexpr int TKT = StripeCfg<T, DEN, TILE>::TKT, TST = StripeCfg<T, DEN, TILE>::TST;
     static constexpr int TKW = 64 * TKT, TSW = 4 * TST, VW = TKW + TSW;
-    // branches per stage: two stages must fit half of the 160 KB LDS (two work-groups per
-    // CU), and the next stage's counts wait in registers (EB x 3 per thread)
-    static constexpr int EBM = 81664 / (2 * (TKW + VW) * (int)sizeof(T));
+    static constexpr int OCC = StripeCfg<T, DEN, TILE>::OCC;
+    // branches per stage: two stages must fit the work-group's share of the 160 KB LDS (OCC
+    // work-groups per CU), and the next stage's counts wait in registers (EB x 3 per thread)
+    static constexpr int EBM = (163840 / OCC - 256) / (2 * (TKW + VW) * (int)sizeof(T));
     static constexpr int EB = EBM < 8 ? EBM : 8;
     __align__(16) T su[2][EB * TKW];
     __align__(16) T sv[2][EB * VW];
@@ -349,7 +356,7 @@ __device__ void stripe_tile(const StripeArgs &a, int32_t k0, int32_t s0, StripeS
 }
 
 template <typename T, int METHOD, int DEN, int TILE, typename CT>
-__global__ __launch_bounds__(kBlock, 2) void k_stripe_fused(StripeArgs a)
+__global__ __launch_bounds__(kBlock, (StripeCfg<T, DEN, TILE>::OCC)) void k_stripe_fused(StripeArgs a)
 {
     using SM = StripeSmem<T, DEN, TILE>;
     __shared__ SM sm;
@@ -362,7 +369,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_stripe_fused(StripeArgs a)
 // time-first schedule over the machine.  The counter must be zero at launch; every
 // work-group leaves the loop at its first fetch past the end.
 template <typename T, int METHOD, int DEN, int TILE, typename CT>
-__global__ __launch_bounds__(kBlock, 2) void k_stripe_queue(
+__global__ __launch_bounds__(kBlock, (StripeCfg<T, DEN, TILE>::OCC)) void k_stripe_queue(
     const StripeArgs *__restrict__ jobs, const int2 *__restrict__ items, int32_t n_items,
     int32_t *__restrict__ counter)
 {
@@ -537,16 +544,20 @@ StripeGeom stripe_geometry(int32_t n, bool fp64, int32_t den_mode, int32_t tile)
     StripeGeom g;
     g.n = n;
     g.S = n / 2;
-    const int key = (fp64 ? 4 : 0) + (den_mode ? 2 : 0) + (tile ? 1 : 0);
+    const int key = (fp64 ? 6 : 0) + (den_mode ? 3 : 0) + (tile == 1 ? 1 : tile == 2 ? 2 : 0);
     switch (key) {
     case 0: tile_dims<float, 0, 0>(&g); break;
     case 1: tile_dims<float, 0, 1>(&g); break;
-    case 2: tile_dims<float, 1, 0>(&g); break;
-    case 3: tile_dims<float, 1, 1>(&g); break;
-    case 4: tile_dims<double, 0, 0>(&g); break;
-    case 5: tile_dims<double, 0, 1>(&g); break;
-    case 6: tile_dims<double, 1, 0>(&g); break;
-    default: tile_dims<double, 1, 1>(&g); break;
+    case 2: tile_dims<float, 0, 2>(&g); break;
+    case 3: tile_dims<float, 1, 0>(&g); break;
+    case 4: tile_dims<float, 1, 1>(&g); break;
+    case 5: tile_dims<float, 1, 2>(&g); break;
+    case 6: tile_dims<double, 0, 0>(&g); break;
+    case 7: tile_dims<double, 0, 1>(&g); break;
+    case 8: tile_dims<double, 0, 2>(&g); break;
+    case 9: tile_dims<double, 1, 0>(&g); break;
+    case 10: tile_dims<double, 1, 1>(&g); break;
+    default: tile_dims<double, 1, 2>(&g); break;
     }
     g.sstride = round_up(n, g.tkw);
     g.spad = (int32_t)round_up(g.S > 0 ? g.S : 1, g.tsw);
@@ -626,16 +637,20 @@ hipError_t launch_stripe_fused(bool fp64, int32_t method, int32_t den_mode, int3
     StripeArgs a = make_stripe_args(method, C, cw, cstride, inv_t, len, B, E, num, den, g);
     a.s_base = tile_s0 * g.tsw;
     a.tiles_s = tile_s1 - tile_s0;
-    const int key = (fp64 ? 4 : 0) + (tile ? 2 : 0) + (cw == 2 ? 1 : 0);
+    const int key = (fp64 ? 6 : 0) + 2 * (tile == 1 ? 1 : tile == 2 ? 2 : 0) + (cw == 2 ? 1 : 0);
     switch (key) {
     case 0: return fused_dispatch<float, 0, int32_t>(a, den_mode, g, st);
     case 1: return fused_dispatch<float, 0, uint16_t>(a, den_mode, g, st);
     case 2: return fused_dispatch<float, 1, int32_t>(a, den_mode, g, st);
     case 3: return fused_dispatch<float, 1, uint16_t>(a, den_mode, g, st);
-    case 4: return fused_dispatch<double, 0, int32_t>(a, den_mode, g, st);
-    case 5: return fused_dispatch<double, 0, uint16_t>(a, den_mode, g, st);
-    case 6: return fused_dispatch<double, 1, int32_t>(a, den_mode, g, st);
-    default: return fused_dispatch<double, 1, uint16_t>(a, den_mode, g, st);
+    case 4: return fused_dispatch<float, 2, int32_t>(a, den_mode, g, st);
+    case 5: return fused_dispatch<float, 2, uint16_t>(a, den_mode, g, st);
+    case 6: return fused_dispatch<double, 0, int32_t>(a, den_mode, g, st);
+    case 7: return fused_dispatch<double, 0, uint16_t>(a, den_mode, g, st);
+    case 8: return fused_dispatch<double, 1, int32_t>(a, den_mode, g, st);
+    case 9: return fused_dispatch<double, 1, uint16_t>(a, den_mode, g, st);
+    case 10: return fused_dispatch<double, 2, int32_t>(a, den_mode, g, st);
+    default: return fused_dispatch<double, 2, uint16_t>(a, den_mode, g, st);
     }
 }
 
@@ -682,16 +697,20 @@ hipError_t launch_stripe_queue(bool fp64, int32_t method, int32_t cw, int32_t de
             else UF_Q(T, UF_UNWEIGHTED, D, TL, int32_t);                            \
         }                                                                           \
     } while (0)
-    const int key = (fp64 ? 4 : 0) + (den_mode ? 2 : 0) + (tile ? 1 : 0);
+    const int key = (fp64 ? 6 : 0) + (den_mode ? 3 : 0) + (tile == 1 ? 1 : tile == 2 ? 2 : 0);
     switch (key) {
     case 0: UF_QM(float, 0, 0); break;
     case 1: UF_QM(float, 0, 1); break;
-    case 2: UF_QM(float, 1, 0); break;
-    case 3: UF_QM(float, 1, 1); break;
-    case 4: UF_QM(double, 0, 0); break;
-    case 5: UF_QM(double, 0, 1); break;
-    case 6: UF_QM(double, 1, 0); break;
-    default: UF_QM(double, 1, 1); break;
+    case 2: UF_QM(float, 0, 2); break;
+    case 3: UF_QM(float, 1, 0); break;
+    case 4: UF_QM(float, 1, 1); break;
+    case 5: UF_QM(float, 1, 2); break;
+    case 6: UF_QM(double, 0, 0); break;
+    case 7: UF_QM(double, 0, 1); break;
+    case 8: UF_QM(double, 0, 2); break;
+    case 9: UF_QM(double, 1, 0); break;
+    case 10: UF_QM(double, 1, 1); break;
+    default: UF_QM(double, 1, 2); break;
     }
 #undef UF_QM
 #undef UF_Q

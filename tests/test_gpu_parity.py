@@ -105,6 +105,21 @@ def test_separable_denominator(uf, ctx, problems, method, prec):
     assert err.max() <= TOL[prec]
 
 
+@pytest.mark.parametrize("tile", [0, 1, 2])
+@pytest.mark.parametrize("den_mode", [0, 1])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("method", [UW, WN])
+def test_tile_shapes_match_oracle(uf, ctx, problems, method, prec, den_mode, tile):
+    # every per-lane tile shape, on a ragged size and on one spanning several tiles
+    for case in ("cfg1_ragged_257", "cfg2_shape_600"):
+        prob = problems[case]
+        plan = _plan(uf, ctx, prob)
+        got = plan.distance(method, prec, tuning=dict(den_mode=den_mode, tile=tile))
+        want = oracle.problem_condensed(prob, OMETHOD[method])
+        err = _report(f"{case} tile={tile} den_mode={den_mode} {method} {prec}", got, want)
+        assert err.max() <= TOL[prec]
+
+
 @pytest.mark.parametrize("emb_batch", [1, 7, 128])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("method", [UW, WN])
