@@ -84,6 +84,8 @@ def parse():
     ap.add_argument("--den-mode", type=int, default=0)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--k-chunk", type=int, default=0)
+    ap.add_argument("--variant", type=int, default=0,
+                    help="matrix-core accumulation: 0 = FP64 registers, 1 = chunk sums added into the output")
     ap.add_argument("--n", type=int, default=None, help="override the sample count")
     ap.add_argument("--tips", type=int, default=None, help="override the tip count")
     ap.add_argument("--jobs", type=int, default=64, help="batch workload: number of jobs")
@@ -269,7 +271,7 @@ def bench_mfma(args):
     ctx = uf.Context(0)
     stream = torch.cuda.current_stream()
     plan = uf.Plan.from_problem(ctx, prob, stream=stream)
-    tuning = dict(k_chunk=args.k_chunk)
+    tuning = dict(k_chunk=args.k_chunk, variant=args.variant)
     out = torch.empty(n_pairs, dtype=torch.float64, device="cuda:0")
     dt, prof = timed_runs(plan, "unweighted", "mfma_bf16x2", tuning, out, args.steps, args.warmup, stream)
     log(f"mfma: {dt * 1e3:.2f} ms/step; kernels {prof}")
@@ -281,9 +283,10 @@ def bench_mfma(args):
                       {"workload": f"unweighted UniFrac on bf16 matrix cores, {n} samples, random "
                                    f"binary tree with {(prob.n_nodes + 1) // 2} tips ({B} branches)",
                        "n_samples": n, "branches": B, "method": "unweighted",
-                       "precision": "mfma_bf16x2", "k_chunk": args.k_chunk or 4096})
+                       "precision": "mfma_bf16x2", "k_chunk": args.k_chunk or 4096,
+                       "variant": args.variant})
     res["kernels_ms_per_step"] = {k: round(v[1] / args.steps, 3) for k, v in prof.items()}
-    key = f"mfma/{n}x{B}/k_chunk{args.k_chunk or 4096}"
+    key = f"mfma/{n}x{B}/k_chunk{args.k_chunk or 4096}/variant{args.variant}"
     res["roofline"] = {"kernel": "k_mfma_gemm", "bound": "mfma", "achieved": round(achieved, 2),
                        "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                        "frac": round(achieved / MFMA_BF16_PEAK_TFLOPS, 4),
@@ -393,7 +396,7 @@ def bench_large(args, part):
     S = n // 2
     if part == "uw":
         out = torch.empty(n_pairs, dtype=torch.float64, device="cuda:0")
-        dt, prof = timed_runs(plan, "unweighted", "mfma_bf16x2", dict(k_chunk=args.k_chunk), out,
+        dt, prof = timed_runs(plan, "unweighted", "mfma_bf16x2", dict(k_chunk=args.k_chunk, variant=args.variant), out,
                               args.steps, args.warmup, stream)
         launches, total_ms = prof.get("mfma", (0, 0.0))
         k_pad = (B + 63) // 64 * 64

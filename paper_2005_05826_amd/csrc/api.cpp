@@ -260,7 +260,7 @@ namespace {
 // Matrix-core form of the unweighted variant: fills `out_dev` with condensed distances.
 // Scratch: [0] presence bytes, [1] hi/lo splits, [2] tile list, [3] T and (for FP32 or
 // host output) the FP64 shared-length array S.
-uf_status run_mfma_unweighted(uf_plan *plan, int32_t k_chunk, int32_t out_f32, void *out_dev,
+uf_status run_mfma_unweighted(uf_plan *plan, int32_t k_chunk, int32_t variant, int32_t out_f32, void *out_dev,
                               hipStream_t st)
 {
     uf_context *ctx = plan->ctx;
@@ -296,7 +296,7 @@ uf_status run_mfma_unweighted(uf_plan *plan, int32_t k_chunk, int32_t out_f32, v
            }), "presence transpose");
     UF_TRY(timed(plan, "mfma", st, [&] {
                return launch_mfma_gemm(Pm.as<uint8_t>(), hi, lo, k_chunk, TL.as<int32_t>(), g, S,
-                                       T, st);
+                                       T, variant, st);
            }), "matrix-core product");
     UF_TRY(timed(plan, "normalize", st, [&] {
                return launch_mfma_normalize(S, T, n, out_f32, out_dev, st);
@@ -500,7 +500,7 @@ uf_status uf_plan_distance(uf_plan *plan, uf_method method, uf_precision prec,
         dst = plan->out_tmp.p;
     }
     if (prec == UF_PREC_MFMA_BF16X2) {
-        s = run_mfma_unweighted(plan, kn.k_chunk, out_dtype == UF_F32, dst, st);
+        s = run_mfma_unweighted(plan, kn.k_chunk, kn.variant, out_dtype == UF_F32, dst, st);
         if (s != UF_OK) return s;
     } else {
         StripeGeom g;

@@ -90,7 +90,8 @@ extern "C" uf_status uf_autotune(uf_plan *plan, uf_method method, uf_precision p
 
     std::vector<uf_tuning> cands;
     if (prec == UF_PREC_MFMA_BF16X2) {
-        for (int32_t kc : {4096, 16384, 2048}) cands.push_back(uf_tuning{0, kc, 0, 0, 0});
+        for (int32_t v : {0, 1})
+            for (int32_t kc : {4096, 16384}) cands.push_back(uf_tuning{0, kc, 0, v, 0, 0});
     } else {
         // FP32 sums inside a batch carry ~E * 2^-24 relative error, so FP32 batches stay <= 256
         const std::vector<int32_t> Es = prec == UF_PREC_FP32 ? std::vector<int32_t>{128, 64, 256}

@@ -23,6 +23,7 @@ struct uf_batch {
     std::vector<uf_plan *> plans;
     std::vector<uf_job> jobs;
     int32_t emb_batch = 0, den_mode = 0, k_chunk = 4096, tile = 0, count_width = 0;
+    int32_t mfma_variant = 0;             // uf_tuning.variant: matrix-core accumulation form
     int32_t n_groups = 512;
     // propagation tables
     DevMem prop_jobs, scatter_tasks, level_tasks;
@@ -135,7 +136,9 @@ uf_status enqueue(uf_batch *b, hipStream_t st)
         UF_TRY(timed(b->prof, "mfma", st, [&] {
                    return launch_mfma_queue(b->mfma_jobs.as<MfmaArgs>(), b->mfma_items.as<int32_t>(),
                                             b->n_mfma_items, b->counters.as<int32_t>() + uf_batch::kQueues,
-                                            std::min(b->n_groups / 2, b->n_mfma_items), st);
+                                            std::min(b->mfma_variant == 0 ? b->n_groups / 2 : b->n_groups,
+                                                     b->n_mfma_items),
+                                            b->mfma_variant, st);
                }), "queued matrix-core product");
         for (int32_t j = 0; j < nj; ++j) {
             if (is_striped(b->jobs[j])) continue;
@@ -343,11 +346,13 @@ uf_status uf_batch_create(uf_context *ctx, const uf_job *jobs, int32_t n_jobs,
         b->den_mode = tuning->den_mode;
         b->tile = tuning->tile;
         b->count_width = tuning->count_width;
+        b->mfma_variant = tuning->variant;
         if (tuning->k_chunk > 0) b->k_chunk = tuning->k_chunk;
     }
-    if ((b->den_mode != 0 && b->den_mode != 1) || (b->tile < 0 || b->tile > 2)) {
+    if ((b->den_mode != 0 && b->den_mode != 1) || (b->tile < 0 || b->tile > 2) ||
+        (b->mfma_variant != 0 && b->mfma_variant != 1)) {
         delete b;
-        return set_err(ctx, UF_E_ARG, "den_mode must be 0 or 1 and tile 0, 1 or 2");
+        return set_err(ctx, UF_E_ARG, "den_mode and variant must be 0 or 1, tile 0, 1 or 2");
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
     b->jobs.assign(jobs, jobs + n_jobs);

@@ -104,7 +104,11 @@ struct MfmaSmem {
 };
 
 // One GM x GM tile of S = P diag(hi + lo) P^T (rows row0.., columns col0.., row0 <= col0):
-// writes S_ij (i < j) into the condensed array and S_ii into T.
+// writes S_ij (i < j) into the condensed array and S_ii into T.  The FP32 chunk sums are
+// added in FP64 either into FP64 registers written once at the end (REG64 = true, one
+// work-group per CU, no extra output traffic; the default) or into the output itself after
+// every chunk (REG64 = false, small register footprint, two work-groups per CU).
+template <bool REG64>
 __device__ void mfma_tile(const MfmaArgs &a, int32_t row0, int32_t col0, MfmaSmem &sm)
 {
     const uint8_t *__restrict__ P = a.P;
@@ -119,6 +123,19 @@ __device__ void mfma_tile(const MfmaArgs &a, int32_t row0, int32_t col0, MfmaSme
     const int wm = w >> 1, wn = w & 1;
     const int lrow = lane & 31;
     const int kg = lane >> 5;
+    // element (mb, nb, r) of the lane: row i, column j of S (32x32 accumulator layout: lane l,
+    // register r holds row 8*(r/4) + 4*(l/32) + r%4 and column l%32 of the block)
+    auto elem_row = [&](int mb, int r) { return row0 + wm * 64 + mb * 32 + 8 * (r >> 2) + 4 * kg + (r & 3); };
+    auto elem_col = [&](int nb) { return col0 + wn * 64 + nb * 32 + lrow; };
+    double acc64[REG64 ? 2 : 1][REG64 ? 2 : 1][REG64 ? 16 : 1];
+    if (REG64) {
+#pragma unroll
+        for (int x = 0; x < (REG64 ? 2 : 1); ++x)
+#pragma unroll
+            for (int y = 0; y < (REG64 ? 2 : 1); ++y)
+#pragma unroll
+                for (int r = 0; r < (REG64 ? 16 : 1); ++r) acc64[x][y][r] = 0.0;
+    }
 
     // each thread stages 32 bytes of one A row and one B row, and one dword of the hi or lo
     // splits (threads 64.. repeat the dwords of threads 0..63, writing the same values)
@@ -127,88 +144,113 @@ __device__ void mfma_tile(const MfmaArgs &a, int32_t row0, int32_t col0, MfmaSme
     const uint32_t *phl = reinterpret_cast<const uint32_t *>((tid & 32) ? a.lo : a.hi) + (tid & 31);
     const int soff = (tid >> 1) * LDK + (tid & 1) * 32;
     const int hoff = tid & 63;
-    uint4 ra0, ra1, rb0, rb1;
-    uint32_t rhl;
-    auto gload = [&](int32_t ks) {
-        const int64_t k0 = (int64_t)ks * GK;
-        ra0 = *reinterpret_cast<const uint4 *>(pa + k0);
-        ra1 = *reinterpret_cast<const uint4 *>(pa + k0 + 16);
-        rb0 = *reinterpret_cast<const uint4 *>(pb + k0);
-        rb1 = *reinterpret_cast<const uint4 *>(pb + k0 + 16);
-        rhl = phl[k0 / 2];
+    // Global loads run two stages ahead of the compute: stage ks + 2 is loaded into one
+    // register set while stage ks + 1 (loaded one stage earlier) waits in the other and is
+    // written to the free LDS buffer after stage ks computes.  chunk_steps is even, so every
+    // chunk starts on an even stage and the two sets alternate with static names.
+    struct Stage {
+        uint4 a0, a1, b0, b1;
+        uint32_t hl;
     };
-    auto lstore = [&](int buf) {
+    Stage R0, R1;
+    auto gload = [&](Stage &R, int32_t ks) {
+        const int64_t k0 = (int64_t)ks * GK;
+        R.a0 = *reinterpret_cast<const uint4 *>(pa + k0);
+        R.a1 = *reinterpret_cast<const uint4 *>(pa + k0 + 16);
+        R.b0 = *reinterpret_cast<const uint4 *>(pb + k0);
+        R.b1 = *reinterpret_cast<const uint4 *>(pb + k0 + 16);
+        R.hl = phl[k0 / 2];
+    };
+    auto lstore = [&](const Stage &R, int buf) {
         uint2 *da = reinterpret_cast<uint2 *>(sm.A[buf] + soff);
         uint2 *db = reinterpret_cast<uint2 *>(sm.B[buf] + soff);
-        da[0] = make_uint2(ra0.x, ra0.y); da[1] = make_uint2(ra0.z, ra0.w);
-        da[2] = make_uint2(ra1.x, ra1.y); da[3] = make_uint2(ra1.z, ra1.w);
-        db[0] = make_uint2(rb0.x, rb0.y); db[1] = make_uint2(rb0.z, rb0.w);
-        db[2] = make_uint2(rb1.x, rb1.y); db[3] = make_uint2(rb1.z, rb1.w);
-        reinterpret_cast<uint32_t *>(sm.hl[buf])[hoff] = rhl;
+        da[0] = make_uint2(R.a0.x, R.a0.y); da[1] = make_uint2(R.a0.z, R.a0.w);
+        da[2] = make_uint2(R.a1.x, R.a1.y); da[3] = make_uint2(R.a1.z, R.a1.w);
+        db[0] = make_uint2(R.b0.x, R.b0.y); db[1] = make_uint2(R.b0.z, R.b0.w);
+        db[2] = make_uint2(R.b1.x, R.b1.y); db[3] = make_uint2(R.b1.z, R.b1.w);
+        reinterpret_cast<uint32_t *>(sm.hl[buf])[hoff] = R.hl;
+    };
+    f32x16 acc[2][2];
+    auto compute = [&](int buf) {
+        const uint8_t *cA = sm.A[buf];
+        const uint8_t *cB = sm.B[buf];
+        const uint16_t *chl = sm.hl[buf];
+#pragma unroll
+        for (int kk = 0; kk < GK / 16; ++kk) {
+            const int koff = kk * 16 + kg * 8;
+            const uint4 h = *reinterpret_cast<const uint4 *>(chl + koff);
+            const uint4 l = *reinterpret_cast<const uint4 *>(chl + GK + koff);
+            bf16x8 ahi[2], alo[2], bo[2];
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb) {
+                const uint2 m = *reinterpret_cast<const uint2 *>(cA + (wm * 64 + mb * 32 + lrow) * LDK + koff);
+                const uint32_t m0 = __builtin_amdgcn_perm(m.x, m.x, 0x01010000u);
+                const uint32_t m1 = __builtin_amdgcn_perm(m.x, m.x, 0x03030202u);
+                const uint32_t m2 = __builtin_amdgcn_perm(m.y, m.y, 0x01010000u);
+                const uint32_t m3 = __builtin_amdgcn_perm(m.y, m.y, 0x03030202u);
+                ahi[mb] = as_bf16x8(m0 & h.x, m1 & h.y, m2 & h.z, m3 & h.w);
+                alo[mb] = as_bf16x8(m0 & l.x, m1 & l.y, m2 & l.z, m3 & l.w);
+            }
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) {
+                const uint2 m = *reinterpret_cast<const uint2 *>(cB + (wn * 64 + nb * 32 + lrow) * LDK + koff);
+                bo[nb] = as_bf16x8(__builtin_amdgcn_perm(m.x, m.x, 0x01010000u) & kOne2,
+                                   __builtin_amdgcn_perm(m.x, m.x, 0x03030202u) & kOne2,
+                                   __builtin_amdgcn_perm(m.y, m.y, 0x01010000u) & kOne2,
+                                   __builtin_amdgcn_perm(m.y, m.y, 0x03030202u) & kOne2);
+            }
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                for (int nb = 0; nb < 2; ++nb) {
+                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[mb], bo[nb], acc[mb][nb], 0, 0, 0);
+                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo[mb], bo[nb], acc[mb][nb], 0, 0, 0);
+                }
+        }
+    };
+    // Rn holds stage ks + 1 (in flight), Rf is free
+    auto step = [&](int32_t ks, Stage &Rn, Stage &Rf) {
+        if (ks + 2 < n_kstep) gload(Rf, ks + 2);
+        compute(ks & 1);
+        if (ks + 1 < n_kstep) lstore(Rn, (ks + 1) & 1);
+        __syncthreads();
     };
 
     if (n_kstep > 0) {
-        gload(0);
-        lstore(0);
+        gload(R0, 0);
+        lstore(R0, 0);
     }
+    if (n_kstep > 1) gload(R1, 1);
     __syncthreads();
     int32_t ks = 0;
     while (ks < n_kstep) {
         // FP32 accumulation inside a chunk of chunk_steps stages, then one FP64 flush
         const int32_t kend = (n_kstep - ks) < chunk_steps ? n_kstep : ks + chunk_steps;
-        f32x16 acc[2][2];
 #pragma unroll
         for (int x = 0; x < 2; ++x)
 #pragma unroll
             for (int y = 0; y < 2; ++y)
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[x][y][r] = 0.f;
-        for (; ks < kend; ++ks) {
-            const int buf = ks & 1;
-            const bool more = ks + 1 < n_kstep;
-            if (more) gload(ks + 1);
-            const uint8_t *cA = sm.A[buf];
-            const uint8_t *cB = sm.B[buf];
-            const uint16_t *chl = sm.hl[buf];
+        for (; ks + 1 < kend; ks += 2) {
+            step(ks, R1, R0);
+            step(ks + 1, R0, R1);
+        }
+        if (ks < kend) {   // odd-length last chunk
+            step(ks, R1, R0);
+            ++ks;
+        }
+        if (REG64) {
 #pragma unroll
-            for (int kk = 0; kk < GK / 16; ++kk) {
-                const int koff = kk * 16 + kg * 8;
-                const uint4 h = *reinterpret_cast<const uint4 *>(chl + koff);
-                const uint4 l = *reinterpret_cast<const uint4 *>(chl + GK + koff);
-                bf16x8 ahi[2], alo[2], bo[2];
+            for (int x = 0; x < (REG64 ? 2 : 1); ++x)
 #pragma unroll
-                for (int mb = 0; mb < 2; ++mb) {
-                    const uint2 m = *reinterpret_cast<const uint2 *>(cA + (wm * 64 + mb * 32 + lrow) * LDK + koff);
-                    const uint32_t m0 = __builtin_amdgcn_perm(m.x, m.x, 0x01010000u);
-                    const uint32_t m1 = __builtin_amdgcn_perm(m.x, m.x, 0x03030202u);
-                    const uint32_t m2 = __builtin_amdgcn_perm(m.y, m.y, 0x01010000u);
-                    const uint32_t m3 = __builtin_amdgcn_perm(m.y, m.y, 0x03030202u);
-                    ahi[mb] = as_bf16x8(m0 & h.x, m1 & h.y, m2 & h.z, m3 & h.w);
-                    alo[mb] = as_bf16x8(m0 & l.x, m1 & l.y, m2 & l.z, m3 & l.w);
-                }
+                for (int y = 0; y < (REG64 ? 2 : 1); ++y)
 #pragma unroll
-                for (int nb = 0; nb < 2; ++nb) {
-                    const uint2 m = *reinterpret_cast<const uint2 *>(cB + (wn * 64 + nb * 32 + lrow) * LDK + koff);
-                    bo[nb] = as_bf16x8(__builtin_amdgcn_perm(m.x, m.x, 0x01010000u) & kOne2,
-                                       __builtin_amdgcn_perm(m.x, m.x, 0x03030202u) & kOne2,
-                                       __builtin_amdgcn_perm(m.y, m.y, 0x01010000u) & kOne2,
-                                       __builtin_amdgcn_perm(m.y, m.y, 0x03030202u) & kOne2);
-                }
-#pragma unroll
-                for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-                    for (int nb = 0; nb < 2; ++nb) {
-                        acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[mb], bo[nb], acc[mb][nb], 0, 0, 0);
-                        acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo[mb], bo[nb], acc[mb][nb], 0, 0, 0);
-                    }
-            }
-            if (more) lstore(buf ^ 1);
-            __syncthreads();
+                    for (int r = 0; r < (REG64 ? 16 : 1); ++r) acc64[x][y][r] += (double)acc[x][y][r];
+            continue;
         }
         // FP64 cross-chunk sum kept in the output itself: the first chunk stores, later
         // chunks add (each element belongs to this work-group alone, chunks in K order).
-        // 32x32 accumulator layout: lane l, register r holds row 8*(r/4) + 4*(l/32) + r%4
-        // and column l%32 of the block.
         const bool first = (kend <= chunk_steps);
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb)
@@ -218,8 +260,8 @@ __device__ void mfma_tile(const MfmaArgs &a, int32_t row0, int32_t col0, MfmaSme
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
-                    const int32_t i = row0 + wm * 64 + mb * 32 + 8 * (r >> 2) + 4 * kg + (r & 3);
-                    const int32_t j = col0 + wn * 64 + nb * 32 + lrow;
+                    const int32_t i = elem_row(mb, r);
+                    const int32_t j = elem_col(nb);
                     if (i < n && j < n && i <= j) {
                         double *dst = i < j ? S + ((int64_t)n * i - (int64_t)i * (i + 1) / 2 + (j - i - 1)) : T + i;
                         const double v = (double)acc[mb][nb][r];
@@ -229,6 +271,21 @@ __device__ void mfma_tile(const MfmaArgs &a, int32_t row0, int32_t col0, MfmaSme
             }
         __builtin_amdgcn_sched_barrier(0);
     }
+    if (REG64) {
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int32_t i = elem_row(mb, r);
+                    const int32_t j = elem_col(nb);
+                    if (i < n && j < n && i <= j)
+                        *(i < j ? S + ((int64_t)n * i - (int64_t)i * (i + 1) / 2 + (j - i - 1)) : T + i) =
+                            acc64[REG64 ? mb : 0][REG64 ? nb : 0][REG64 ? r : 0];
+                }
+        return;
+    }
     if (n_kstep == 0) {   // no branches: every shared length is 0
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb)
@@ -236,8 +293,8 @@ __device__ void mfma_tile(const MfmaArgs &a, int32_t row0, int32_t col0, MfmaSme
             for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
-                    const int32_t i = row0 + wm * 64 + mb * 32 + 8 * (r >> 2) + 4 * kg + (r & 3);
-                    const int32_t j = col0 + wn * 64 + nb * 32 + lrow;
+                    const int32_t i = elem_row(mb, r);
+                    const int32_t j = elem_col(nb);
                     if (i < n && j < n && i <= j)
                         *(i < j ? S + ((int64_t)n * i - (int64_t)i * (i + 1) / 2 + (j - i - 1)) : T + i) = 0.0;
                 }
@@ -247,20 +304,22 @@ __device__ void mfma_tile(const MfmaArgs &a, int32_t row0, int32_t col0, MfmaSme
 // Single job.  Work-group b takes tile (b % 8) * per + b / 8 of the upper-triangular list,
 // so the 8 XCDs (which receive work-groups round-robin) each sweep a contiguous run of
 // tiles that share A panels in their L2.
-__global__ __launch_bounds__(256, 2) void k_mfma_gemm(MfmaArgs a, const int2 *__restrict__ tiles,
-                                                     int32_t n_tiles)
+template <bool REG64>
+__global__ __launch_bounds__(256, REG64 ? 1 : 2) void k_mfma_gemm(MfmaArgs a, const int2 *__restrict__ tiles,
+                                                                 int32_t n_tiles)
 {
     __shared__ MfmaSmem sm;
     const int32_t per = (n_tiles + 7) / 8;
     const int32_t t = (int32_t)(blockIdx.x % 8) * per + (int32_t)(blockIdx.x / 8);
     if (t >= n_tiles) return;
     const int2 tile = tiles[t];
-    mfma_tile(a, tile.x * GM, tile.y * GM, sm);
+    mfma_tile<REG64>(a, tile.x * GM, tile.y * GM, sm);
 }
 
 // Many jobs: work-groups take (job, tile) items from a global counter (items listed
 // largest job first), leaving at the first fetch past the end.  *counter is zero at launch.
-__global__ __launch_bounds__(256, 2) void k_mfma_queue(const MfmaArgs *__restrict__ jobs,
+template <bool REG64>
+__global__ __launch_bounds__(256, REG64 ? 1 : 2) void k_mfma_queue(const MfmaArgs *__restrict__ jobs,
                                                       const int2 *__restrict__ items,
                                                       int32_t n_items, int32_t *__restrict__ counter)
 {
@@ -275,7 +334,7 @@ __global__ __launch_bounds__(256, 2) void k_mfma_queue(const MfmaArgs *__restric
         const int2 item = items[it];
         const MfmaArgs a = jobs[item.x];
         const int2 tile = a.tiles[item.y];
-        mfma_tile(a, tile.x * GM, tile.y * GM, sm);
+        mfma_tile<REG64>(a, tile.x * GM, tile.y * GM, sm);
     }
 }
 
@@ -358,7 +417,9 @@ MfmaArgs make_mfma_args(const uint8_t *P, const uint16_t *hi, const uint16_t *lo
     a.P = P;
     a.k_pad = g.k_pad;
     a.n_kstep = (int32_t)(g.k_pad / GK);
-    a.chunk_steps = k_chunk / GK < 1 ? 1 : k_chunk / GK;
+    // whole stages, an even number of them (the tile loop alternates two register sets)
+    const int32_t cs = k_chunk / GK < 1 ? 1 : k_chunk / GK;
+    a.chunk_steps = (cs + 1) & ~1;
     a.hi = hi;
     a.lo = lo;
     a.n = g.n;
@@ -371,20 +432,26 @@ MfmaArgs make_mfma_args(const uint8_t *P, const uint16_t *hi, const uint16_t *lo
 
 hipError_t launch_mfma_gemm(const uint8_t *P, const uint16_t *hi, const uint16_t *lo,
                             int32_t k_chunk, const int32_t *tiles_xy, const MfmaGeom &g,
-                            double *S, double *T, hipStream_t st)
+                            double *S, double *T, int32_t variant, hipStream_t st)
 {
     const MfmaArgs a = make_mfma_args(P, hi, lo, k_chunk, tiles_xy, g, S, T);
     const int32_t per = (g.n_tiles + 7) / 8;
-    k_mfma_gemm<<<(unsigned)(8 * per), 256, 0, st>>>(a, a.tiles, g.n_tiles);
+    if (variant == 0)
+        k_mfma_gemm<true><<<(unsigned)(8 * per), 256, 0, st>>>(a, a.tiles, g.n_tiles);
+    else
+        k_mfma_gemm<false><<<(unsigned)(8 * per), 256, 0, st>>>(a, a.tiles, g.n_tiles);
     return hipGetLastError();
 }
 
 hipError_t launch_mfma_queue(const MfmaArgs *jobs, const int32_t *items_xy, int32_t n_items,
-                             int32_t *counter, int32_t n_groups, hipStream_t st)
+                             int32_t *counter, int32_t n_groups, int32_t variant, hipStream_t st)
 {
     if (n_items <= 0) return hipSuccess;
-    k_mfma_queue<<<n_groups, 256, 0, st>>>(jobs, reinterpret_cast<const int2 *>(items_xy), n_items,
-                                           counter);
+    const int2 *it = reinterpret_cast<const int2 *>(items_xy);
+    if (variant == 0)
+        k_mfma_queue<true><<<n_groups, 256, 0, st>>>(jobs, it, n_items, counter);
+    else
+        k_mfma_queue<false><<<n_groups, 256, 0, st>>>(jobs, it, n_items, counter);
     return hipGetLastError();
 }
 

@@ -159,7 +159,7 @@ hipError_t launch_bits_to_bytes(const uint32_t *bits, int64_t bstride, const Mfm
                                 uint8_t *P, hipStream_t st);
 hipError_t launch_mfma_gemm(const uint8_t *P, const uint16_t *hi, const uint16_t *lo,
                             int32_t k_chunk, const int32_t *tiles_xy, const MfmaGeom &g,
-                            double *S, double *T, hipStream_t st);
+                            double *S, double *T, int32_t variant, hipStream_t st);
 hipError_t launch_mfma_normalize(const double *S, const double *T, int32_t n, int32_t out_f32,
                                  void *out, hipStream_t st);
 // One job of the matrix-core path, for the single-job and queued kernels.
@@ -176,6 +176,6 @@ MfmaArgs make_mfma_args(const uint8_t *P, const uint16_t *hi, const uint16_t *lo
                         const int32_t *tiles_xy, const MfmaGeom &g, double *S, double *T);
 // items_xy: (job index, tile index) pairs; *counter == 0 at launch.
 hipError_t launch_mfma_queue(const MfmaArgs *jobs, const int32_t *items_xy, int32_t n_items,
-                             int32_t *counter, int32_t n_groups, hipStream_t st);
+                             int32_t *counter, int32_t n_groups, int32_t variant, hipStream_t st);
 
 }  // namespace ufmi

@@ -68,14 +68,14 @@ def _check(jobs, outs, want, tag):
         assert err <= tol, (tag, p.n_samples, m, prec, err)
 
 
-@pytest.mark.parametrize("tile", [0, 2])
+@pytest.mark.parametrize("tile,variant", [(0, 0), (2, 1)])
 @pytest.mark.parametrize("den_mode", [0, 1])
-def test_batch_matches_oracle(uf, ctx, jobs, den_mode, tile):
+def test_batch_matches_oracle(uf, ctx, jobs, den_mode, tile, variant):
     outs = _outs(jobs)
     b = uf.Batch(ctx, [dict(problem=p, method=m, precision=pr, out=o) for (p, m, pr), o in zip(jobs, outs)],
-                 tuning=dict(den_mode=den_mode, tile=tile))
+                 tuning=dict(den_mode=den_mode, tile=tile, variant=variant))
     b.run()
-    _check(jobs, outs, _want(jobs), f"batch den_mode={den_mode} tile={tile}")
+    _check(jobs, outs, _want(jobs), f"batch den_mode={den_mode} tile={tile} variant={variant}")
     b.close()
 
 

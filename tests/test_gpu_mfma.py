@@ -60,21 +60,23 @@ def test_mfma_matches_oracle(uf, ctx, problems, case):
     assert err.max(initial=0.0) <= 1e-5
 
 
-@pytest.mark.parametrize("k_chunk", [64, 512, 4096])
-def test_mfma_k_chunk(uf, ctx, problems, k_chunk):
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("k_chunk", [64, 512, 4096, 16384])
+def test_mfma_k_chunk(uf, ctx, problems, k_chunk, variant):
     prob = problems["cfg3_shape"]
     plan = uf.Plan.from_problem(ctx, prob)
-    got = plan.distance(UW, MF, tuning=dict(k_chunk=k_chunk))
+    got = plan.distance(UW, MF, tuning=dict(k_chunk=k_chunk, variant=variant))
     want = oracle.problem_condensed(prob, oracle.UNWEIGHTED)
-    err = _report(f"mfma k_chunk={k_chunk}", got, want)
+    err = _report(f"mfma k_chunk={k_chunk} variant={variant}", got, want)
     assert err.max() <= 1e-5
 
 
+@pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("n", [2, 3, 127, 128, 257])
-def test_mfma_dyadic_bit_identical(uf, ctx, n):
+def test_mfma_dyadic_bit_identical(uf, ctx, n, variant):
     prob = config_problem(1, n=n, tips=500, p_nonzero=0.3, dyadic=True, depth=256, seed=200 + n)
     plan = uf.Plan.from_problem(ctx, prob)
-    got = plan.distance(UW, MF)
+    got = plan.distance(UW, MF, tuning=dict(variant=variant))
     want = oracle.problem_condensed(prob, oracle.UNWEIGHTED)
     np.testing.assert_array_equal(got, want)
 
