@@ -9,8 +9,10 @@ normalize/condense, ending with the condensed matrix in device memory.
 Workloads (--workload):
   striped (default)  4,096 samples, 32,768-tip random coalescent tree (65,534 branches),
                      ~800 features per sample, NegBin(10, 0.3) counts rarefied to 5,000;
-                     weighted normalized.  Headline: the FP32 path; the FP64 path is timed on
-                     the same inputs for the FP32-vs-FP64 comparison.
+                     weighted normalized.  Headline: the FP32 path with the denominator
+                     from per-sample sums (den_mode 1) on tile shape 2; timed beside it on
+                     the same inputs: plain FP64 (numerator and denominator stripes) and
+                     FP32 in that same numerator-and-denominator form.
   mfma               25,000 samples, 300,000-tip random binary tree, 1,500 Zipf(1.1)
                      presences per sample; unweighted on bf16 matrix cores (hi+lo split).
                      --compare fp64 also times the FP64 striped form (about 20 s a step).
@@ -18,6 +20,10 @@ Workloads (--workload):
                      workload-1 distributions), each run weighted normalized (FP32 striped)
                      and unweighted (matrix core): 128 jobs in one batch, replayed as a
                      captured HIP graph.
+  large-uw           113,000 samples, 500,000-tip random binary tree: the full unweighted
+                     matrix on the matrix cores.
+  large-wn           the same inputs, weighted normalized FP32 striped: one GPU's share (a
+                     contiguous 1/--share of the stripes) of a split of the full matrix.
 
 The oracle (FP64 CPU) is timed on the host cores on a seeded sample of pairs as the CPU
 baseline, and the same sample gives the max and mean absolute error of every GPU result.
@@ -53,19 +59,33 @@ OPS_PER_UPDATE = {0: 4, 1: 2}   # den_mode 0: both stripes; 1: numerator only
 # (--copy-calibration: FETCH_SIZE reads 0.5 GiB, WRITE_SIZE 1 GiB, so x2.0 and x1.0).
 # Keyed by workload and configuration; each entry records the SHA-256 of the kernel source
 # it was measured on, and is reported as null once that source has changed.
-TRAFFIC = {}
+TRAFFIC = {
+    "striped/4096x65534/fp32/den1/tile2/Edefault": {
+        "src_sha256": "a104e7ef4d1cf59e", "fetch": 49178603546, "write": 34359144192,
+        "bytes": 83537747738, "profile": "profiles/k_stripe_fused_wn_fp32_4096x65534.md"},
+    "mfma/25000x599998/k_chunk4096/variant0": {
+        "src_sha256": "b94bf14ccc705725", "fetch": 996104020337, "write": 2567293600,
+        "bytes": 998671313937, "profile": "profiles/k_mfma_gemm_uw_25000x599998.md"},
+}
 
 
-def kernel_traffic(key, source):
+def add_traffic(roofline, key, source, launch_ms):
+    """Sets roofline["traffic"] (HBM bytes per launch, or None) and, when known, the HBM
+    bandwidth that traffic implies at the launch time measured here."""
     import hashlib
+    roofline["traffic"] = None
     ent = TRAFFIC.get(key)
     if not ent:
-        return None
+        return
     with open(os.path.join(ROOT, "paper_2005_05826_amd", "csrc", source), "rb") as f:
         if hashlib.sha256(f.read()).hexdigest()[:16] != ent["src_sha256"]:
-            return None
-    return {"bytes": ent["bytes"], "fetch_bytes": ent["fetch"], "write_bytes": ent["write"],
-            "profile": ent["profile"]}
+            return
+    roofline["traffic"] = ent["bytes"]
+    gbs = ent["bytes"] / (launch_ms * 1e-3) / 1e9
+    roofline["traffic_detail"] = {"fetch_bytes": ent["fetch"], "write_bytes": ent["write"],
+                                  "hbm_GBs_at_measured_time": round(gbs, 1),
+                                  "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                                  "profile": ent["profile"]}
 
 
 def parse():
@@ -79,10 +99,12 @@ def parse():
                     help="large-wn: compute 1/share of the stripes (one GPU's share)")
     ap.add_argument("--method", default=None)
     ap.add_argument("--precision", default=None)
-    ap.add_argument("--compare", default=None, help="second precision timed for comparison ('' = none)")
+    ap.add_argument("--compare", default=None,
+                    help="precision timed for comparison ('' or none: no comparison runs)")
     ap.add_argument("--emb-batch", type=int, default=0)
-    ap.add_argument("--den-mode", type=int, default=0)
-    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--den-mode", type=int, default=None,
+                    help="striped headline: 1 = separable denominator (default), 0 = num+den stripes")
+    ap.add_argument("--tile", type=int, default=None, help="striped headline tile shape (default 2)")
     ap.add_argument("--k-chunk", type=int, default=0)
     ap.add_argument("--variant", type=int, default=0,
                     help="matrix-core accumulation: 0 = FP64 registers, 1 = chunk sums added into the output")
@@ -188,6 +210,8 @@ def bench_striped(args):
     method = args.method or "weighted_normalized"
     prec = args.precision or "fp32"
     compare = "fp64" if args.compare is None else args.compare
+    if compare == "none":
+        compare = ""
     over = {k: v for k, v in (("n", args.n), ("tips", args.tips)) if v}
     t0 = time.time()
     prob = config_problem(2, **over)
@@ -198,60 +222,71 @@ def bench_striped(args):
     ctx = uf.Context(0)
     stream = torch.cuda.current_stream()
     plan = uf.Plan.from_problem(ctx, prob, stream=stream)
-    tuning = dict(emb_batch=args.emb_batch, den_mode=args.den_mode, tile=args.tile)
+    den_mode = 1 if args.den_mode is None else args.den_mode
+    tile = 2 if args.tile is None else args.tile
+    tuning = dict(emb_batch=args.emb_batch, den_mode=den_mode, tile=tile)
     out = torch.empty(n_pairs, dtype=torch.float64, device="cuda:0")
-    log(f"timing {prec}: {args.warmup} warmup + {args.steps} steps")
+    log(f"timing {prec} (den_mode {den_mode}, tile {tile}): {args.warmup} warmup + {args.steps} steps")
     dt, prof = timed_runs(plan, method, prec, tuning, out, args.steps, args.warmup, stream)
     log(f"{prec}: {dt * 1e3:.2f} ms/step; kernels {prof}")
-    out2 = None
+
+    def stripe_roofline(p, tot_ms, steps, dm):
+        ops = OPS_PER_UPDATE[dm] * updates
+        achieved = ops / (tot_ms / steps * 1e-3) / 1e12
+        return {"kernel": "k_stripe_fused", "bound": "alu", "achieved": round(achieved, 3),
+                "peak": round(VALU_PEAK_TOPS[p], 2), "unit": "Tops/s",
+                "frac": round(achieved / VALU_PEAK_TOPS[p], 4), "ops_per_update": OPS_PER_UPDATE[dm]}
+
+    # the comparisons: plain FP64 (both stripes, first tile shape), and the FP32 path in the
+    # same num + den form as the paper's kernel
+    others = {}
     if compare:
-        out2 = torch.empty_like(out)
+        others["compare"] = (compare, dict(emb_batch=args.emb_batch, den_mode=0, tile=0))
+    if compare and prec == "fp32" and (den_mode, tile) != (0, 0):
+        others["fp32_num_den"] = ("fp32", dict(emb_batch=args.emb_batch, den_mode=0, tile=0))
+    outs = {}
+    for name, (p2, tun2) in others.items():
+        o2 = torch.empty_like(out)
         steps2 = max(1, args.steps // 2)
-        dt2, prof2 = timed_runs(plan, method, compare, tuning, out2, steps2, 1, stream)
-        log(f"{compare}: {dt2 * 1e3:.2f} ms/step; kernels {prof2}")
+        d2, pr2 = timed_runs(plan, method, p2, tun2, o2, steps2, 1, stream)
+        log(f"{name} {p2} {tun2}: {d2 * 1e3:.2f} ms/step; kernels {pr2}")
+        rec = {"precision": p2, "den_mode": tun2["den_mode"], "tile": tun2["tile"],
+               "ms_per_step": round(d2 * 1e3, 3), "value": round(updates / d2, 1),
+               "kernels_ms_per_step": {k: round(v[1] / steps2, 3) for k, v in pr2.items()},
+               "headline_speedup": round(d2 / dt, 3)}
+        l2, t2 = pr2.get("stripe", (0, 0.0))
+        if l2 and p2 in VALU_PEAK_TOPS:
+            rec["roofline"] = stripe_roofline(p2, t2, steps2, tun2["den_mode"])
+        outs[name] = (o2, rec)
 
     launches, total_ms = prof.get("stripe", (0, 0.0))
     roofline = None
     if launches:
-        ops = OPS_PER_UPDATE[args.den_mode] * updates
-        achieved = ops / (total_ms / args.steps * 1e-3) / 1e12
-        peak = VALU_PEAK_TOPS[prec]
-        key = f"striped/{n}x{B}/{prec}/den{args.den_mode}/tile{args.tile}/E{args.emb_batch or 'default'}"
-        roofline = {"kernel": "k_stripe_fused", "bound": "alu", "achieved": round(achieved, 3),
-                    "peak": round(peak, 2), "unit": "Tops/s",
-                    "frac": round(achieved / peak, 4), "traffic": kernel_traffic(key, "k_stripe.hip"),
-                    "launches_per_step": launches // args.steps,
-                    "avg_launch_ms": round(total_ms / launches, 4),
-                    "ops_per_update": OPS_PER_UPDATE[args.den_mode]}
+        key = f"striped/{n}x{B}/{prec}/den{den_mode}/tile{tile}/E{args.emb_batch or 'default'}"
+        roofline = stripe_roofline(prec, total_ms, args.steps, den_mode)
+        roofline.update({"launches_per_step": launches // args.steps,
+                         "avg_launch_ms": round(total_ms / launches, 4)})
+        add_traffic(roofline, key, "k_stripe.hip", total_ms / launches)
     res = base_record(args, updates / dt, dt, "f32" if prec == "fp32" else "f64",
                       {"workload": f"{method.replace('_', '-')} striped UniFrac, {n} samples, "
                                    f"coalescent tree with {(prob.n_nodes + 1) // 2} tips ({B} branches)",
                        "n_samples": n, "branches": B, "levels": plan.info.n_levels,
                        "nnz": int(plan.info.nnz), "method": method, "precision": prec,
-                       "emb_batch": args.emb_batch or "default", "den_mode": args.den_mode,
-                       "tile": args.tile})
+                       "emb_batch": args.emb_batch or "default", "den_mode": den_mode,
+                       "denominator": "per-sample sums" if den_mode else "stripes",
+                       "tile": tile})
     res["kernels_ms_per_step"] = {k: round(v[1] / args.steps, 3) for k, v in prof.items()}
     res["roofline"] = roofline
-    if compare:
-        res["compare"] = {"precision": compare, "ms_per_step": round(dt2 * 1e3, 3),
-                          "value": round(updates / dt2, 1),
-                          "kernels_ms_per_step": {k: round(v[1] / steps2, 3) for k, v in prof2.items()},
-                          "speedup_of_headline": round(dt2 / dt, 3)}
-        l2, t2 = prof2.get("stripe", (0, 0.0))
-        if l2 and compare in VALU_PEAK_TOPS:
-            a2 = OPS_PER_UPDATE[args.den_mode] * updates / (t2 / steps2 * 1e-3) / 1e12
-            res["compare"]["roofline"] = {"kernel": "k_stripe_fused", "bound": "alu",
-                                          "achieved": round(a2, 3), "unit": "Tops/s",
-                                          "peak": round(VALU_PEAK_TOPS[compare], 2),
-                                          "frac": round(a2 / VALU_PEAK_TOPS[compare], 4)}
+    for name, (_, rec) in outs.items():
+        res[name] = rec
     if not args.no_cpu:
         cpu, pi, pj, want = oracle_sample(prob, method, args.cpu_seconds, 20050526 + 99)
         res["cpu_baseline"] = cpu
         res["error_vs_oracle"] = {prec: errors(out, n, pi, pj, want)}
-        if compare:
-            res["error_vs_oracle"][compare] = errors(out2, n, pi, pj, want)
-    if compare and n >= 3:
-        r, _, _ = uf.mantel(ctx, out, out2, n)
+        for name, (o2, rec) in outs.items():
+            res["error_vs_oracle"][name] = errors(o2, n, pi, pj, want)
+    if "compare" in outs and n >= 3:
+        r, _, _ = uf.mantel(ctx, out, outs["compare"][0], n)
         res["mantel_r2_vs_compare"] = round(r * r, 12)
     return res
 
@@ -260,7 +295,7 @@ def bench_mfma(args):
     import torch
     import paper_2005_05826_amd as uf
     from synth import config_problem
-    compare = "" if args.compare is None else args.compare
+    compare = "" if args.compare in (None, "none") else args.compare
     over = {k: v for k, v in (("n", args.n), ("tips", args.tips)) if v}
     t0 = time.time()
     prob = config_problem(3, **over)
@@ -290,8 +325,9 @@ def bench_mfma(args):
     res["roofline"] = {"kernel": "k_mfma_gemm", "bound": "mfma", "achieved": round(achieved, 2),
                        "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                        "frac": round(achieved / MFMA_BF16_PEAK_TFLOPS, 4),
-                       "traffic": kernel_traffic(key, "k_mfma.hip"),
                        "avg_launch_ms": round(total_ms / max(1, launches), 3)}
+    if launches:
+        add_traffic(res["roofline"], key, "k_mfma.hip", total_ms / launches)
     if compare:
         out2 = torch.empty_like(out)
         dt2, prof2 = timed_runs(plan, "unweighted", compare, {}, out2, 1, 0, stream)
@@ -324,14 +360,17 @@ def bench_batch(args):
             jobs.append(dict(problem=p, method=method, precision=prec, out=o))
     # knobs: the autotuner times tile shape x batch depth (and the MFMA chunk) on the
     # largest job, unless they are given on the command line
-    tuning = dict(emb_batch=args.emb_batch, tile=args.tile, k_chunk=args.k_chunk)
+    tuning = dict(emb_batch=args.emb_batch, tile=2 if args.tile is None else args.tile,
+                  den_mode=1 if args.den_mode is None else args.den_mode, k_chunk=args.k_chunk,
+                  variant=args.variant)
     tuned = {}
     if not args.emb_batch:
         big = int(np.argmax([p.n_samples * p.n_nodes for p in probs]))
         tplan = uf.Plan.from_problem(ctx, probs[big])
-        best, ms = tplan.autotune("weighted_normalized", "fp32", reps=1)
+        best, ms = tplan.autotune("weighted_normalized", "fp32", base=dict(den_mode=tuning["den_mode"]), reps=1)
         bestm, msm = tplan.autotune("unweighted", "mfma_bf16x2", reps=1)
-        tuning.update(emb_batch=best["emb_batch"], tile=best["tile"], k_chunk=bestm["k_chunk"])
+        tuning.update(emb_batch=best["emb_batch"], tile=best["tile"], k_chunk=bestm["k_chunk"],
+                      variant=bestm["variant"])
         tuned = {"striped": best, "striped_ms": round(ms, 3), "mfma": bestm, "mfma_ms": round(msm, 3),
                  "on_job": {"n_samples": probs[big].n_samples, "branches": probs[big].n_nodes - 1}}
         tplan.close()
@@ -413,7 +452,9 @@ def bench_large(args, part):
     else:
         s0, s1 = 0, (S + args.share - 1) // args.share
         out = torch.empty(n_pairs, dtype=torch.float32, device="cuda:0")
-        tuning = dict(emb_batch=args.emb_batch, tile=args.tile, count_width=2)
+        den_mode = 1 if args.den_mode is None else args.den_mode
+        tuning = dict(emb_batch=args.emb_batch, den_mode=den_mode,
+                      tile=2 if args.tile is None else args.tile, count_width=2)
         for _ in range(args.warmup):
             plan.distance_stripes(s0, s1, out, "weighted_normalized", "fp32", out_dtype="f32",
                                   tuning=tuning, stream=stream)
@@ -429,7 +470,7 @@ def bench_large(args, part):
         plan.set_profiling(False)
         updates = (s1 - s0) * n * B
         launches, total_ms = prof.get("stripe", (0, 0.0))
-        achieved = 4 * updates / (total_ms / args.steps * 1e-3) / 1e12 if launches else 0.0
+        achieved = OPS_PER_UPDATE[den_mode] * updates / (total_ms / args.steps * 1e-3) / 1e12 if launches else 0.0
         res = base_record(args, updates / dt, dt, "f32",
                           {"workload": f"weighted-normalized FP32 striped UniFrac, {n} samples, random "
                                        f"binary tree with {(prob.n_nodes + 1) // 2} tips ({B} branches), "
