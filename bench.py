@@ -107,7 +107,7 @@ def parse():
     ap.add_argument("--tile", type=int, default=None, help="striped headline tile shape (default 2)")
     ap.add_argument("--k-chunk", type=int, default=0)
     ap.add_argument("--variant", type=int, default=0,
-                    help="matrix-core accumulation: 0 = FP64 registers, 1 = chunk sums added into the output")
+                    help="matrix-core accumulation: 0 = chunk sums added into the output, 1 = FP64 registers")
     ap.add_argument("--n", type=int, default=None, help="override the sample count")
     ap.add_argument("--tips", type=int, default=None, help="override the tip count")
     ap.add_argument("--jobs", type=int, default=64, help="batch workload: number of jobs")
@@ -416,7 +416,7 @@ def bench_batch(args):
 def bench_large(args, part):
     """Workload 5 (113,000 samples, 500,000-tip random binary tree, ~1,000 features per
     sample, NegBin(8, 0.3) rarefied to 2,000).  large-uw: the full unweighted matrix on the
-    matrix cores (presence bytes 113 GB, FP64 shared lengths in the output).  large-wn: one
+    matrix cores (presence bits 14 GB, FP64 shared lengths in the output).  large-wn: one
     GPU's share of an N-way split of the weighted normalized FP32 striped computation, a
     contiguous stripe range of 1/share of the stripes, with 16-bit count rows (226 GB);
     the condensed output (FP32, 25.5 GB) stays resident."""

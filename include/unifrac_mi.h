@@ -113,10 +113,10 @@ typedef struct {
                            staging them and loops over every batch in one launch (default);
                            1 = separate transform launch into an embedding buffer and one
                            striped launch per batch (single plans only; batches ignore it).
-                           matrix-core path: 0 = each chunk's FP32 sums are kept in FP64
-                           registers and written once (one work-group per CU, default);
-                           1 = chunk sums are added into the FP64 output after every chunk
-                           (two work-groups per CU)                                          */
+                           matrix-core path: 0 = each chunk's FP32 sums are added into the
+                           FP64 output after every chunk (two work-groups per CU, default);
+                           1 = chunk sums are kept in FP64 registers and written once (one
+                           work-group per CU)                                                */
     int32_t tile;       /* striped fused/queued kernels: per-lane tile shape (samples x
                            stripes), 0, 1 or 2; den_mode 0: FP64 4x8 | 2x12 | 2x8,
                            FP32 4x16 | 8x8 | 4x8; den_mode 1: FP64 4x16 | 2x24 | 4x8,

@@ -258,7 +258,7 @@ uf_status check_enums(uf_context *ctx, uf_method method, uf_precision prec)
 
 namespace {
 // Matrix-core form of the unweighted variant: fills `out_dev` with condensed distances.
-// Scratch: [0] presence bytes, [1] hi/lo splits, [2] tile list, [3] T and (for FP32 or
+// Scratch: [0] presence bits, [1] hi/lo splits, [2] tile list, [3] T and (for FP32 or
 // host output) the FP64 shared-length array S.
 uf_status run_mfma_unweighted(uf_plan *plan, int32_t k_chunk, int32_t variant, int32_t out_f32, void *out_dev,
                               hipStream_t st)
@@ -273,7 +273,7 @@ uf_status run_mfma_unweighted(uf_plan *plan, int32_t k_chunk, int32_t variant, i
     if (s != UF_OK) return s;
     DevMem &Pm = plan->mfma_scratch[0], &HL = plan->mfma_scratch[1];
     DevMem &TL = plan->mfma_scratch[2], &TS = plan->mfma_scratch[3];
-    UF_TRY(Pm.ensure((size_t)g.n_pad * g.k_pad), "allocating presence bytes");
+    UF_TRY(Pm.ensure((size_t)g.n_pad * (g.k_pad / 8)), "allocating presence bits");
     UF_TRY(HL.ensure((size_t)2 * g.k_pad * sizeof(uint16_t)), "allocating length splits");
     std::vector<int32_t> xy;
     mfma_tile_list(n, &xy);
@@ -290,7 +290,7 @@ uf_status run_mfma_unweighted(uf_plan *plan, int32_t k_chunk, int32_t variant, i
     UF_TRY(timed(plan, "bits_transpose", st, [&] {
                hipError_t r = launch_split_lengths(plan->len_slot.as<double>(), B, g.k_pad, hi, lo, st);
                if (r == hipSuccess)
-                   r = launch_bits_to_bytes(plan->bits.as<uint32_t>(), plan->bstride, g,
+                   r = launch_bits_transpose(plan->bits.as<uint32_t>(), plan->bstride, g,
                                             Pm.as<uint8_t>(), st);
                return r;
            }), "presence transpose");

@@ -118,7 +118,7 @@ uf_status enqueue(uf_batch *b, hipStream_t st)
                }), "condense");
     }
 
-    // (c) matrix-core jobs: presence bytes, one persistent MFMA launch, normalize
+    // (c) matrix-core jobs: presence bits, one persistent MFMA launch, normalize
     if (b->n_mfma_items > 0) {
         for (int32_t j = 0; j < nj; ++j) {
             if (is_striped(b->jobs[j])) continue;
@@ -128,7 +128,7 @@ uf_status enqueue(uf_batch *b, hipStream_t st)
             UF_TRY(timed(b->prof, "bits_transpose", st, [&] {
                        hipError_t r = launch_split_lengths(p->len_slot.as<double>(), g.B, g.k_pad, hi, lo, st);
                        if (r == hipSuccess)
-                           r = launch_bits_to_bytes(p->bits.as<uint32_t>(), p->bstride, g,
+                           r = launch_bits_transpose(p->bits.as<uint32_t>(), p->bstride, g,
                                                     p->mfma_scratch[0].as<uint8_t>(), st);
                        return r;
                    }), "presence transpose");
@@ -136,7 +136,7 @@ uf_status enqueue(uf_batch *b, hipStream_t st)
         UF_TRY(timed(b->prof, "mfma", st, [&] {
                    return launch_mfma_queue(b->mfma_jobs.as<MfmaArgs>(), b->mfma_items.as<int32_t>(),
                                             b->n_mfma_items, b->counters.as<int32_t>() + uf_batch::kQueues,
-                                            std::min(b->mfma_variant == 0 ? b->n_groups / 2 : b->n_groups,
+                                            std::min(b->mfma_variant == 1 ? b->n_groups / 2 : b->n_groups,
                                                      b->n_mfma_items),
                                             b->mfma_variant, st);
                }), "queued matrix-core product");
@@ -283,7 +283,7 @@ uf_status build_tables(uf_batch *b, hipStream_t st)
         const MfmaGeom g = mfma_geometry(p->hp.n_samples, p->hp.n_nodes - 1);
         const int64_t n_pairs = (int64_t)g.n * (g.n - 1) / 2;
         UF_TRY(p->bits.ensure((size_t)p->hp.n_nodes * p->bstride * sizeof(uint32_t)), "allocating bits");
-        UF_TRY(p->mfma_scratch[0].ensure((size_t)g.n_pad * g.k_pad), "allocating presence bytes");
+        UF_TRY(p->mfma_scratch[0].ensure((size_t)g.n_pad * (g.k_pad / 8)), "allocating presence bits");
         UF_TRY(p->mfma_scratch[1].ensure((size_t)2 * g.k_pad * sizeof(uint16_t)), "allocating splits");
         const bool s_in_out = J.out_dtype == UF_F64;
         UF_TRY(p->mfma_scratch[3].ensure((size_t)g.n_pad * sizeof(double) +

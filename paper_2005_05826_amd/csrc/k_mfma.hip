@@ -11,10 +11,11 @@
 // accumulate in FP32 inside chunks of k_chunk branches and are added into the FP64 output
 // between chunks; the final division is FP64.
 //
-// Layout: presence is stored once per sample as one byte per branch (0x00 or 0xFF),
-// [n_pad][k_pad].  A byte pair becomes a pair of 16-bit masks with one byte permute, and a
-// mask ANDed with the bf16 pattern of hi, lo or 1.0 is exactly the MFMA operand, so
-// operand construction costs two VALU ops per 32-bit register.
+// Layout: presence is stored once per sample as one bit per branch, [n_pad][k_pad / 8]
+// bytes (bit t of byte q = branch 8q + t).  A work-group stages 128 branches of its row and
+// column panels at a time and expands the bits to bytes (0x00 or 0xFF) on the way into LDS;
+// a byte pair becomes a pair of 16-bit masks with one byte permute, and a mask ANDed with
+// the bf16 pattern of hi, lo or 1.0 is exactly the MFMA operand.
 #include "uf_internal.h"
 
 namespace ufmi {
@@ -25,8 +26,8 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int GM = 128;            // work-group tile: GM x GM outputs, 4 waves of 64 x 64
-constexpr int GK = 64;             // branches per LDS stage
-constexpr int LDK = GK + 8;        // padded LDS row (bytes)
+constexpr int GK = 128;            // branches per LDS stage (16 bytes of presence bits per row)
+constexpr int LDK = GK + 8;        // padded LDS row of expanded bytes (conflict-free operand reads)
 constexpr uint32_t kOne2 = 0x3F803F80u;  // two bf16 1.0
 
 // round-to-nearest-even FP32 -> bf16 (finite, non-negative inputs)
@@ -53,11 +54,11 @@ __global__ void k_split_lengths(const double *__restrict__ len, int32_t B, int32
     lo[b] = l;
 }
 
-// Presence bits [slot][bstride] (bit k%32 of word k/32 = sample k) -> bytes
-// P[k][b] (0xFF if sample k has a read below branch slot b), one 256-sample x 64-branch
-// tile per work-group, transposed through LDS.
-__global__ void k_bits_to_bytes(const uint32_t *__restrict__ bits, int64_t bstride, int32_t B,
-                                int32_t n_pad, int64_t k_pad, uint8_t *__restrict__ P)
+// Presence bits [slot][bstride] (bit k%32 of word k/32 = sample k) -> per-sample rows
+// Pb[k][b / 8] (bit b % 8 = sample k has a read below branch slot b), one 256-sample x
+// 64-branch tile per work-group, transposed through LDS.
+__global__ void k_bits_transpose(const uint32_t *__restrict__ bits, int64_t bstride, int32_t B,
+                                 int32_t n_pad, int64_t kb, uint8_t *__restrict__ Pb)
 {
     __shared__ uint32_t w[64][8];
     const int32_t b0 = blockIdx.x * 64;
@@ -75,17 +76,26 @@ __global__ void k_bits_to_bytes(const uint32_t *__restrict__ bits, int64_t bstri
     const int32_t k = k0 + tid;
     if (k >= n_pad) return;
     const uint32_t sh = tid & 31, wc = tid >> 5;
-    uint32_t out[16];
+    uint32_t lo = 0, hi = 0;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        uint32_t v = 0;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) v |= (((w[q * 4 + t][wc] >> sh) & 1u) * 0xFFu) << (8 * t);
-        out[q] = v;
+    for (int t = 0; t < 32; ++t) {
+        lo |= ((w[t][wc] >> sh) & 1u) << t;
+        hi |= ((w[32 + t][wc] >> sh) & 1u) << t;
     }
-    uint4 *dst = reinterpret_cast<uint4 *>(P + (int64_t)k * k_pad + b0);
+    *reinterpret_cast<uint2 *>(Pb + (int64_t)k * kb + b0 / 8) = make_uint2(lo, hi);
+}
+
+// 32 presence bits -> 32 bytes of 0x00 / 0xFF (byte t of dword d <- bit 4d + t).  A nibble
+// times 0x204081 puts its bit t at bit 8t (the other partial products land on bits that the
+// mask clears); selector byte 12 or 13 of v_perm yields 0x00 or 0xFF.
+__device__ inline void expand_bits(uint32_t x, uint32_t (&out)[8])
+{
 #pragma unroll
-    for (int q = 0; q < 4; ++q) dst[q] = make_uint4(out[4 * q], out[4 * q + 1], out[4 * q + 2], out[4 * q + 3]);
+    for (int d = 0; d < 8; ++d) {
+        const uint32_t nib = (x >> (4 * d)) & 0xFu;
+        const uint32_t sel = ((nib * 0x204081u) & 0x01010101u) | 0x0C0C0C0Cu;
+        out[d] = __builtin_amdgcn_perm(0u, 0u, sel);
+    }
 }
 
 __device__ inline bf16x8 as_bf16x8(uint32_t a, uint32_t b, uint32_t c, uint32_t d)
@@ -105,9 +115,9 @@ struct MfmaSmem {
 
 // One GM x GM tile of S = P diag(hi + lo) P^T (rows row0.., columns col0.., row0 <= col0):
 // writes S_ij (i < j) into the condensed array and S_ii into T.  The FP32 chunk sums are
-// added in FP64 either into FP64 registers written once at the end (REG64 = true, one
-// work-group per CU, no extra output traffic; the default) or into the output itself after
-// every chunk (REG64 = false, small register footprint, two work-groups per CU).
+// added in FP64 either into the output itself after every chunk (REG64 = false, small
+// register footprint, two work-groups per CU; the default) or into FP64 registers written
+// once at the end (REG64 = true, one work-group per CU, no extra output traffic).
 template <bool REG64>
 __device__ void mfma_tile(const MfmaArgs &a, int32_t row0, int32_t col0, MfmaSmem &sm)
 {
@@ -137,37 +147,39 @@ __device__ void mfma_tile(const MfmaArgs &a, int32_t row0, int32_t col0, MfmaSme
                 for (int r = 0; r < (REG64 ? 16 : 1); ++r) acc64[x][y][r] = 0.0;
     }
 
-    // each thread stages 32 bytes of one A row and one B row, and one dword of the hi or lo
-    // splits (threads 64.. repeat the dwords of threads 0..63, writing the same values)
-    const uint8_t *pa = P + (int64_t)(row0 + (tid >> 1)) * k_pad + (tid & 1) * 32;
-    const uint8_t *pb = P + (int64_t)(col0 + (tid >> 1)) * k_pad + (tid & 1) * 32;
-    const uint32_t *phl = reinterpret_cast<const uint32_t *>((tid & 32) ? a.lo : a.hi) + (tid & 31);
-    const int soff = (tid >> 1) * LDK + (tid & 1) * 32;
-    const int hoff = tid & 63;
+    // each thread stages the 16 bytes of presence bits of one row (threads 0..127 the row
+    // panel, 128..255 the column panel) and one dword of the hi or lo splits (threads 128..
+    // repeat the dwords of threads 0..127, writing the same values)
+    const int64_t kb = a.k_pad / 8;
+    const uint8_t *prow = P + (int64_t)((tid < 128 ? row0 : col0) + (tid & 127)) * kb;
+    uint8_t *srow = (tid < 128 ? &sm.A[0][0] : &sm.B[0][0]) + (tid & 127) * LDK;
+    const uint32_t *phl = reinterpret_cast<const uint32_t *>((tid & 64) ? a.lo : a.hi) + (tid & 63);
+    const int hoff = tid & 127;
     // Global loads run two stages ahead of the compute: stage ks + 2 is loaded into one
     // register set while stage ks + 1 (loaded one stage earlier) waits in the other and is
-    // written to the free LDS buffer after stage ks computes.  chunk_steps is even, so every
-    // chunk starts on an even stage and the two sets alternate with static names.
+    // expanded into the free LDS buffer after stage ks computes.  chunk_steps is even, so
+    // every chunk starts on an even stage and the two sets alternate with static names.
     struct Stage {
-        uint4 a0, a1, b0, b1;
+        uint4 bits;
         uint32_t hl;
     };
     Stage R0, R1;
     auto gload = [&](Stage &R, int32_t ks) {
         const int64_t k0 = (int64_t)ks * GK;
-        R.a0 = *reinterpret_cast<const uint4 *>(pa + k0);
-        R.a1 = *reinterpret_cast<const uint4 *>(pa + k0 + 16);
-        R.b0 = *reinterpret_cast<const uint4 *>(pb + k0);
-        R.b1 = *reinterpret_cast<const uint4 *>(pb + k0 + 16);
+        R.bits = *reinterpret_cast<const uint4 *>(prow + k0 / 8);
         R.hl = phl[k0 / 2];
     };
     auto lstore = [&](const Stage &R, int buf) {
-        uint2 *da = reinterpret_cast<uint2 *>(sm.A[buf] + soff);
-        uint2 *db = reinterpret_cast<uint2 *>(sm.B[buf] + soff);
-        da[0] = make_uint2(R.a0.x, R.a0.y); da[1] = make_uint2(R.a0.z, R.a0.w);
-        da[2] = make_uint2(R.a1.x, R.a1.y); da[3] = make_uint2(R.a1.z, R.a1.w);
-        db[0] = make_uint2(R.b0.x, R.b0.y); db[1] = make_uint2(R.b0.z, R.b0.w);
-        db[2] = make_uint2(R.b1.x, R.b1.y); db[3] = make_uint2(R.b1.z, R.b1.w);
+        // rows are LDK = 136 bytes apart: 8-byte aligned stores
+        uint2 *dst = reinterpret_cast<uint2 *>(srow + buf * (GM * LDK));
+        const uint32_t w4[4] = {R.bits.x, R.bits.y, R.bits.z, R.bits.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            uint32_t e[8];
+            expand_bits(w4[q], e);
+#pragma unroll
+            for (int d = 0; d < 4; ++d) dst[4 * q + d] = make_uint2(e[2 * d], e[2 * d + 1]);
+        }
         reinterpret_cast<uint32_t *>(sm.hl[buf])[hoff] = R.hl;
     };
     f32x16 acc[2][2];
@@ -401,12 +413,12 @@ hipError_t launch_split_lengths(const double *len, int32_t B, int64_t k_pad, uin
     return hipGetLastError();
 }
 
-hipError_t launch_bits_to_bytes(const uint32_t *bits, int64_t bstride, const MfmaGeom &g,
-                                uint8_t *P, hipStream_t st)
+hipError_t launch_bits_transpose(const uint32_t *bits, int64_t bstride, const MfmaGeom &g,
+                                 uint8_t *Pb, hipStream_t st)
 {
     if (g.k_pad <= 0) return hipSuccess;
-    dim3 grid((unsigned)(g.k_pad / 64), (unsigned)(g.n_pad / 256));
-    k_bits_to_bytes<<<grid, 256, 0, st>>>(bits, bstride, g.B, g.n_pad, g.k_pad, P);
+    const dim3 grid((unsigned)(g.k_pad / 64), (unsigned)(g.n_pad / 256));
+    k_bits_transpose<<<grid, 256, 0, st>>>(bits, bstride, g.B, g.n_pad, g.k_pad / 8, Pb);
     return hipGetLastError();
 }
 
@@ -436,7 +448,7 @@ hipError_t launch_mfma_gemm(const uint8_t *P, const uint16_t *hi, const uint16_t
 {
     const MfmaArgs a = make_mfma_args(P, hi, lo, k_chunk, tiles_xy, g, S, T);
     const int32_t per = (g.n_tiles + 7) / 8;
-    if (variant == 0)
+    if (variant == 1)
         k_mfma_gemm<true><<<(unsigned)(8 * per), 256, 0, st>>>(a, a.tiles, g.n_tiles);
     else
         k_mfma_gemm<false><<<(unsigned)(8 * per), 256, 0, st>>>(a, a.tiles, g.n_tiles);
@@ -448,7 +460,7 @@ hipError_t launch_mfma_queue(const MfmaArgs *jobs, const int32_t *items_xy, int3
 {
     if (n_items <= 0) return hipSuccess;
     const int2 *it = reinterpret_cast<const int2 *>(items_xy);
-    if (variant == 0)
+    if (variant == 1)
         k_mfma_queue<true><<<n_groups, 256, 0, st>>>(jobs, it, n_items, counter);
     else
         k_mfma_queue<false><<<n_groups, 256, 0, st>>>(jobs, it, n_items, counter);

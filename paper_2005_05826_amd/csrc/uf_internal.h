@@ -142,12 +142,12 @@ hipError_t launch_condense(int32_t method, const double *num, const double *den,
                            int64_t sstride, int32_t n, int32_t S, int32_t out_f32, void *out,
                            hipStream_t st);
 
-// Matrix-core path (unweighted).  Presence bytes P[n_pad][k_pad] (0x00 / 0xFF per branch
-// slot), bf16 length splits hi/lo[k_pad], upper-triangular GM x GM output tiles.
+// Matrix-core path (unweighted).  Presence bits P[n_pad][k_pad / 8] (bit b % 8 of byte b / 8
+// per branch slot b), bf16 length splits hi/lo[k_pad], upper-triangular GM x GM output tiles.
 struct MfmaGeom {
     int32_t n, B;
     int32_t n_pad;      // samples rounded up to 256
-    int64_t k_pad;      // branches rounded up to the K stage (64)
+    int64_t k_pad;      // branches rounded up to the K stage (128)
     int32_t tile, kstep;
     int32_t n_tiles;    // upper-triangular tiles including the diagonal
 };
@@ -155,8 +155,8 @@ MfmaGeom mfma_geometry(int32_t n, int32_t n_branches);
 void mfma_tile_list(int32_t n, std::vector<int32_t> *xy);   // (I, J) pairs, I <= J
 hipError_t launch_split_lengths(const double *len, int32_t B, int64_t k_pad, uint16_t *hi,
                                 uint16_t *lo, hipStream_t st);
-hipError_t launch_bits_to_bytes(const uint32_t *bits, int64_t bstride, const MfmaGeom &g,
-                                uint8_t *P, hipStream_t st);
+hipError_t launch_bits_transpose(const uint32_t *bits, int64_t bstride, const MfmaGeom &g,
+                                 uint8_t *Pb, hipStream_t st);
 hipError_t launch_mfma_gemm(const uint8_t *P, const uint16_t *hi, const uint16_t *lo,
                             int32_t k_chunk, const int32_t *tiles_xy, const MfmaGeom &g,
                             double *S, double *T, int32_t variant, hipStream_t st);
@@ -164,7 +164,7 @@ hipError_t launch_mfma_normalize(const double *S, const double *T, int32_t n, in
                                  void *out, hipStream_t st);
 // One job of the matrix-core path, for the single-job and queued kernels.
 struct MfmaArgs {
-    const uint8_t *P;           // presence bytes [n_pad][k_pad]
+    const uint8_t *P;           // presence bits [n_pad][k_pad / 8]
     int64_t k_pad;
     int32_t n_kstep, chunk_steps;
     const uint16_t *hi, *lo;    // bf16 splits [k_pad]
