@@ -64,8 +64,8 @@ TRAFFIC = {
         "src_sha256": "a104e7ef4d1cf59e", "fetch": 49178603546, "write": 34359144192,
         "bytes": 83537747738, "profile": "profiles/k_stripe_fused_wn_fp32_4096x65534.md"},
     "mfma/25000x599998/k_chunk4096/variant0": {
-        "src_sha256": "b94bf14ccc705725", "fetch": 996104020337, "write": 2567293600,
-        "bytes": 998671313937, "profile": "profiles/k_mfma_gemm_uw_25000x599998.md"},
+        "src_sha256": "3e64b53e71ec43ba", "fetch": 703854942248, "write": 425141495648,
+        "bytes": 1128996437896, "profile": "profiles/k_mfma_gemm_uw_25000x599998.md"},
 }
 
 
