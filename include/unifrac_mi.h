@@ -125,6 +125,12 @@ typedef struct {
     int32_t count_width; /* striped path: bytes per embedding count; 0 = 2 when every sample
                            total fits in 16 bits (halves count memory and traffic), else 4;
                            4 = int32; 2 = uint16 (UF_E_ARG if a total exceeds 65535)         */
+    int32_t k_split;    /* fused striped kernel (single plans): the branches are split into
+                           this many contiguous ranges, each accumulated by its own grid
+                           slice into its own copy of the stripe state, and the copies are
+                           summed in order afterwards (more work-groups when the stripe
+                           tiles alone do not fill the device); 0 = automatic (about two
+                           full device rounds, at most 8), 1 = no split                     */
 } uf_tuning;
 
 typedef struct {

@@ -62,7 +62,8 @@ class UfTable(ctypes.Structure):
 
 class UfTuning(ctypes.Structure):
     _fields_ = [("emb_batch", c_i32), ("k_chunk", c_i32), ("den_mode", c_i32),
-                ("variant", c_i32), ("tile", c_i32), ("count_width", c_i32)]
+                ("variant", c_i32), ("tile", c_i32), ("count_width", c_i32),
+                ("k_split", c_i32)]
 
 
 class UfKernelStat(ctypes.Structure):
@@ -198,7 +199,8 @@ def _tuning(t):
         return ctypes.byref(t)
     return ctypes.byref(UfTuning(int(t.get("emb_batch", 0)), int(t.get("k_chunk", 0)),
                                  int(t.get("den_mode", 0)), int(t.get("variant", 0)),
-                                 int(t.get("tile", 0)), int(t.get("count_width", 0))))
+                                 int(t.get("tile", 0)), int(t.get("count_width", 0)),
+                                 int(t.get("k_split", 0))))
 
 
 class Context:

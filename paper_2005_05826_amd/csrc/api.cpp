@@ -99,7 +99,7 @@ uf_status plan_prepare(uf_context *ctx, const uf_tree *tree, const uf_table *tab
         delete plan;
         return set_err(ctx, s, err);
     }
-    hipError_t e = hipSetDevice(ctx->device);
+    hipError_t e = enter_device(ctx->device);
     if (e != hipSuccess) {
         delete plan;
         return hip_fail(ctx, e, "hipSetDevice");
@@ -130,7 +130,7 @@ uf_status plan_prepare(uf_context *ctx, const uf_tree *tree, const uf_table *tab
 namespace {
 
 struct Knobs {
-    int32_t emb_batch, k_chunk, den_mode, variant, tile, count_width;
+    int32_t emb_batch, k_chunk, den_mode, variant, tile, count_width, k_split;
 };
 
 Knobs resolve_knobs(const uf_tuning *t, uf_precision prec, int32_t n_branches)
@@ -148,7 +148,21 @@ Knobs resolve_knobs(const uf_tuning *t, uf_precision prec, int32_t n_branches)
     k.variant = (t ? t->variant : 0);
     k.tile = (t ? t->tile : 0);
     k.count_width = (t ? t->count_width : 0);
+    k.k_split = (t ? t->k_split : 0);
     return k;
+}
+
+// Branch splits of the fused striped kernel: enough work-groups for about two full rounds
+// of the device (each split keeps its own copy of the stripe state, summed afterwards),
+// at most 8, and none when the stripe tiles alone fill the device twice over.
+int32_t auto_k_split(const uf_context *ctx, const StripeGeom &g, int64_t tiles, int32_t B, int32_t E)
+{
+    const int64_t slots = (int64_t)std::max(ctx->n_cu, 1) * std::max(g.occ, 1);
+    if (tiles <= 0 || tiles >= 2 * slots) return 1;
+    int64_t kz = (2 * slots + tiles - 1) / tiles;
+    kz = std::min<int64_t>(kz, 8);
+    kz = std::min<int64_t>(kz, std::max<int64_t>(1, B / std::max(2 * E, 1)));   // >= 2 batches each
+    return (int32_t)std::max<int64_t>(kz, 1);
 }
 
 // (a)-(b): fills plan->num / den (den_mode 0) or num / D (den_mode 1).
@@ -175,8 +189,12 @@ uf_status run_striped(uf_plan *plan, uf_method method, uf_precision prec, const 
     const int32_t B = hp.n_nodes - 1;
     const size_t tsz = fp64 ? sizeof(double) : sizeof(float);
     const size_t state = (size_t)(tile_s1 - tile_s0) * g.tsw * g.sstride * sizeof(double);
-    UF_TRY(plan->num.ensure(state), "allocating numerator stripes");
-    if (kn.den_mode == 0) UF_TRY(plan->den.ensure(state), "allocating denominator stripes");
+    const int64_t tiles = (int64_t)(g.sstride / g.tkw) * (tile_s1 - tile_s0);
+    const int32_t kz = kn.variant != 0 ? 1
+                       : kn.k_split > 0 ? std::min(kn.k_split, std::max(B, 1))
+                                        : auto_k_split(ctx, g, tiles, B, kn.emb_batch);
+    UF_TRY(plan->num.ensure(state * kz), "allocating numerator stripes");
+    if (kn.den_mode == 0) UF_TRY(plan->den.ensure(state * kz), "allocating denominator stripes");
     UF_TRY(plan->D.ensure((size_t)hp.n_samples * sizeof(double)), "allocating per-sample sums");
     double *num = plan->num.as<double>();
     double *den = kn.den_mode == 0 ? plan->den.as<double>() : nullptr;
@@ -191,8 +209,8 @@ uf_status run_striped(uf_plan *plan, uf_method method, uf_precision prec, const 
     if (s != UF_OK) return s;
     const int32_t cw = plan->cw;
     // the stripe kernels add every batch into the state, so it starts at zero
-    UF_TRY(launch_fill_u32(num, 0u, state / 4, st), "clearing stripes");
-    if (den) UF_TRY(launch_fill_u32(den, 0u, state / 4, st), "clearing stripes");
+    UF_TRY(launch_fill_u32(num, 0u, state * kz / 4, st), "clearing stripes");
+    if (den) UF_TRY(launch_fill_u32(den, 0u, state * kz / 4, st), "clearing stripes");
     const int32_t E = kn.emb_batch;
     const void *C = plan->counts.p;
     const double *len = plan->len_slot.as<double>();
@@ -201,9 +219,17 @@ uf_status run_striped(uf_plan *plan, uf_method method, uf_precision prec, const 
         UF_TRY(launch_inv_totals(plan->totals.as<int32_t>(), hp.n_samples, plan->inv_t.as<double>(), st),
                "reciprocal totals");
         UF_TRY(timed(plan, "stripe", st, [&] {
-                   return launch_stripe_fused(fp64, method, kn.den_mode, kn.tile, C, cw, plan->cstride,
-                                              plan->inv_t.as<double>(), len, B, E, num, den, g,
-                                              tile_s0, tile_s1, st);
+                   hipError_t r = launch_stripe_fused(fp64, method, kn.den_mode, kn.tile, C, cw,
+                                                      plan->cstride, plan->inv_t.as<double>(), len, B,
+                                                      E, num, den, g, tile_s0, tile_s1, kz,
+                                                      (int64_t)(state / sizeof(double)), st);
+                   if (r == hipSuccess)
+                       r = launch_reduce_z(num, (int64_t)(state / sizeof(double)), kz,
+                                           (int64_t)(state / sizeof(double)), st);
+                   if (r == hipSuccess && den)
+                       r = launch_reduce_z(den, (int64_t)(state / sizeof(double)), kz,
+                                           (int64_t)(state / sizeof(double)), st);
+                   return r;
                }), "striped accumulation");
         if (kn.den_mode != 0 && !unnorm) {
             UF_TRY(plan->rowdot_part.ensure(rowdot_scratch_elems(g.n, B) * sizeof(double)),
@@ -351,6 +377,9 @@ uf_status uf_context_create(int32_t device, uf_context **out)
     uf_context *ctx = new (std::nothrow) uf_context;
     if (!ctx) return set_err(nullptr, UF_E_OOM, "host allocation failed");
     ctx->device = device;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+        ctx->n_cu = cus;
     *out = ctx;
     return UF_OK;
 }
@@ -367,7 +396,7 @@ uf_status uf_plan_create(uf_context *ctx, const uf_tree *tree, const uf_table *t
 void uf_plan_destroy(uf_plan *plan)
 {
     if (!plan) return;
-    (void)hipSetDevice(plan->ctx->device);
+    (void)enter_device(plan->ctx->device);
     for (DevMem *m : {&plan->indptr, &plan->entry_slot, &plan->entry_count, &plan->totals,
                       &plan->child_ptr, &plan->child_slot, &plan->len_slot, &plan->slot_of_node,
                       &plan->counts, &plan->bits, &plan->emb, &plan->num, &plan->den, &plan->D,
@@ -381,7 +410,7 @@ void uf_plan_destroy(uf_plan *plan)
 uf_status uf_plan_trim(uf_plan *plan)
 {
     if (!plan) return set_err(nullptr, UF_E_ARG, "plan must not be NULL");
-    (void)hipSetDevice(plan->ctx->device);
+    (void)enter_device(plan->ctx->device);
     for (DevMem *m : {&plan->counts, &plan->bits, &plan->emb, &plan->num, &plan->den, &plan->D,
                       &plan->inv_t, &plan->out_tmp, &plan->gather_tmp, &plan->rowdot_part})
         m->release();
@@ -429,7 +458,7 @@ uf_status uf_plan_embedding_counts(uf_plan *plan, int32_t *out, int32_t out_on_d
 {
     if (!plan || !out) return set_err(plan ? plan->ctx : nullptr, UF_E_ARG, "NULL argument");
     uf_context *ctx = plan->ctx;
-    UF_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    UF_TRY(enter_device(ctx->device), "hipSetDevice");
     hipStream_t st = static_cast<hipStream_t>(stream);
     uf_status s = propagate_counts(plan, st, 4);
     if (s != UF_OK) return s;
@@ -440,7 +469,7 @@ uf_status uf_plan_embedding_counts16(uf_plan *plan, int32_t *out, int32_t out_on
 {
     if (!plan || !out) return set_err(plan ? plan->ctx : nullptr, UF_E_ARG, "NULL argument");
     uf_context *ctx = plan->ctx;
-    UF_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    UF_TRY(enter_device(ctx->device), "hipSetDevice");
     hipStream_t st = static_cast<hipStream_t>(stream);
     uf_status s = propagate_counts(plan, st, 2);
     if (s != UF_OK) return s;
@@ -465,7 +494,7 @@ uf_status uf_plan_embedding_presence(uf_plan *plan, uint32_t *out, int32_t out_o
 {
     if (!plan || !out) return set_err(plan ? plan->ctx : nullptr, UF_E_ARG, "NULL argument");
     uf_context *ctx = plan->ctx;
-    UF_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    UF_TRY(enter_device(ctx->device), "hipSetDevice");
     hipStream_t st = static_cast<hipStream_t>(stream);
     uf_status s = propagate_bits(plan, st);
     if (s != UF_OK) return s;
@@ -491,7 +520,8 @@ uf_status uf_plan_distance(uf_plan *plan, uf_method method, uf_precision prec,
     if (kn.variant != 0 && kn.variant != 1) return set_err(ctx, UF_E_ARG, "variant must be 0 or 1");
     if (method == UF_WEIGHTED_UNNORMALIZED) kn.den_mode = 1;   // no denominator at all
     if (kn.tile < 0 || kn.tile > 2) return set_err(ctx, UF_E_ARG, "tile must be 0, 1 or 2");
-    UF_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    if (kn.k_split < 0 || kn.k_split > 64) return set_err(ctx, UF_E_ARG, "k_split must be in [0, 64]");
+    UF_TRY(enter_device(ctx->device), "hipSetDevice");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const size_t esz = out_dtype == UF_F32 ? sizeof(float) : sizeof(double);
     void *dst = out;
@@ -542,9 +572,10 @@ uf_status uf_plan_distance_stripes(uf_plan *plan, uf_method method, uf_precision
     Knobs kn = resolve_knobs(tuning, prec, hp.n_nodes - 1);
     if (kn.den_mode != 0 && kn.den_mode != 1) return set_err(ctx, UF_E_ARG, "den_mode must be 0 or 1");
     if (kn.tile < 0 || kn.tile > 2) return set_err(ctx, UF_E_ARG, "tile must be 0, 1 or 2");
+    if (kn.k_split < 0 || kn.k_split > 64) return set_err(ctx, UF_E_ARG, "k_split must be in [0, 64]");
     kn.variant = 0;
     if (method == UF_WEIGHTED_UNNORMALIZED) kn.den_mode = 1;
-    UF_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    UF_TRY(enter_device(ctx->device), "hipSetDevice");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t n_pairs = (int64_t)hp.n_samples * (hp.n_samples - 1) / 2;
     const size_t esz = out_dtype == UF_F32 ? sizeof(float) : sizeof(double);
@@ -577,7 +608,7 @@ uf_status uf_plan_distance_stripes(uf_plan *plan, uf_method method, uf_precision
 uf_status uf_plan_set_profiling(uf_plan *plan, int32_t enable)
 {
     if (!plan) return set_err(nullptr, UF_E_ARG, "plan must not be NULL");
-    (void)hipSetDevice(plan->ctx->device);
+    (void)enter_device(plan->ctx->device);
     plan->prof.collect();
     plan->prof.totals.clear();
     plan->prof.on = enable != 0;
@@ -588,7 +619,7 @@ uf_status uf_plan_get_profile(uf_plan *plan, uf_kernel_stat *out, int32_t cap, i
 {
     if (!plan || !n_out || (cap > 0 && !out))
         return set_err(plan ? plan->ctx : nullptr, UF_E_ARG, "NULL argument");
-    (void)hipSetDevice(plan->ctx->device);
+    (void)enter_device(plan->ctx->device);
     plan->prof.collect();
     int32_t n = 0;
     for (const auto &kv : plan->prof.totals) {
@@ -618,7 +649,7 @@ uf_status uf_plan_stripes(uf_plan *plan, uf_method method, uf_precision prec,
     if (method == UF_WEIGHTED_UNNORMALIZED)
         return set_err(ctx, UF_E_ARG, "the unnormalized variant has no denominator stripes");
     if (hp.n_samples / 2 == 0) return UF_OK;
-    UF_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    UF_TRY(enter_device(ctx->device), "hipSetDevice");
     hipStream_t st = static_cast<hipStream_t>(stream);
     StripeGeom g;
     s = run_striped(plan, method, prec, kn, &g, st);

@@ -100,7 +100,7 @@ extern "C" uf_status uf_autotune(uf_plan *plan, uf_method method, uf_precision p
             for (int32_t E : Es) cands.push_back(uf_tuning{E, 0, den_mode, 0, tile});
     }
 
-    UF_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    UF_TRY(enter_device(ctx->device), "hipSetDevice");
     DevMem ref, out, diff;
     UF_TRY(ref.ensure((size_t)std::max<int64_t>(n_pairs, 1) * sizeof(double)), "allocating tuner output");
     UF_TRY(out.ensure((size_t)std::max<int64_t>(n_pairs, 1) * sizeof(double)), "allocating tuner output");

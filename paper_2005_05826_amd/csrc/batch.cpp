@@ -379,7 +379,7 @@ uf_status uf_batch_run(uf_batch *b, void *stream)
 {
     if (!b) return set_err(nullptr, UF_E_ARG, "batch must not be NULL");
     uf_context *ctx = b->ctx;
-    UF_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    UF_TRY(enter_device(ctx->device), "hipSetDevice");
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (b->exec) {
         // the graph runs on the batch's own stream, ordered after the caller's stream work
@@ -404,7 +404,7 @@ uf_status uf_batch_capture(uf_batch *b)
 {
     if (!b) return set_err(nullptr, UF_E_ARG, "batch must not be NULL");
     uf_context *ctx = b->ctx;
-    UF_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    UF_TRY(enter_device(ctx->device), "hipSetDevice");
     destroy_graph(b);
     if (!b->cap_stream)
         UF_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking), "creating capture stream");
@@ -460,7 +460,7 @@ uf_status uf_batch_get_profile(uf_batch *b, uf_kernel_stat *out, int32_t cap, in
 void uf_batch_destroy(uf_batch *b)
 {
     if (!b) return;
-    (void)hipSetDevice(b->ctx->device);
+    (void)enter_device(b->ctx->device);
     destroy_graph(b);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);

@@ -119,7 +119,7 @@ extern "C" uf_status uf_mantel(uf_context *ctx, const double *x, const double *y
 {
     if (!ctx || !x || !y || !r_out || n < 3 || n_perm < 0 || (n_perm > 0 && !perms))
         return set_err(ctx, UF_E_ARG, "invalid Mantel arguments (need n >= 3)");
-    UF_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    UF_TRY(enter_device(ctx->device), "hipSetDevice");
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (n_perm > 0) {
         const int64_t words = (int64_t)n_perm * ((n + 31) / 32);

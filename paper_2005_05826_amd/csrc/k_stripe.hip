@@ -207,8 +207,10 @@ __device__ inline void lds_read_vec(const T *src, T (&dst)[N])
     }
 }
 
+// Branches [bb, be) of one tile, added into the state copy at num / den.
 template <typename T, int METHOD, int DEN, int TILE, typename CT>
-__device__ void stripe_tile(const StripeArgs &a, int32_t k0, int32_t s0, StripeSmem<T, DEN, TILE> &sm)
+__device__ void stripe_tile(const StripeArgs &a, int32_t k0, int32_t s0, int32_t bb, int32_t be,
+                            double *num, double *den, StripeSmem<T, DEN, TILE> &sm)
 {
     using SM = StripeSmem<T, DEN, TILE>;
     constexpr int TKT = SM::TKT, TST = SM::TST, EB = SM::EB;
@@ -219,8 +221,8 @@ __device__ void stripe_tile(const StripeArgs &a, int32_t k0, int32_t s0, StripeS
     const CT *__restrict__ C = static_cast<const CT *>(a.C);
     const double *__restrict__ len = a.len;
     const int64_t cstride = a.cstride, sstride = a.sstride;
-    const int32_t n = a.n, S = a.S, B = a.B, E = a.E;
-    if (B <= 0) return;
+    const int32_t n = a.n, S = a.S, E = a.E;
+    if (be <= bb) return;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -298,8 +300,8 @@ __device__ void stripe_tile(const StripeArgs &a, int32_t k0, int32_t s0, StripeS
             ad[s][r] = T(0);
         }
     // stages: windows of at most EB branches inside batches [b0, b1) of E branches
-    int32_t b1 = E < B ? E : B;
-    int32_t e0 = 0;
+    int32_t b1 = E < be - bb ? bb + E : be;
+    int32_t e0 = bb;
     int32_t eb = (b1 - e0) < EB ? (b1 - e0) : EB;
     int buf = 0;
     gload(e0, eb);
@@ -307,8 +309,8 @@ __device__ void stripe_tile(const StripeArgs &a, int32_t k0, int32_t s0, StripeS
     __syncthreads();
     for (;;) {
         int32_t ne0 = e0 + eb, nb1 = b1;
-        if (ne0 >= b1) nb1 = (B - b1) < E ? B : b1 + E;
-        const bool more = ne0 < B;
+        if (ne0 >= b1) nb1 = (be - b1) < E ? be : b1 + E;
+        const bool more = ne0 < be;
         const int32_t neb = more ? ((nb1 - ne0) < EB ? (nb1 - ne0) : EB) : 0;
         if (more) gload(ne0, neb);
         const T *su = sm.su[buf], *sv = sm.sv[buf], *sl = sm.sl[buf];
@@ -335,7 +337,7 @@ __device__ void stripe_tile(const StripeArgs &a, int32_t k0, int32_t s0, StripeS
                 }
         }
         if (e0 + eb >= b1) {   // end of a batch: add the register tile into the FP64 state
-            add_tile<TST, TKT, DEN>(an, ad, a.num, a.den,
+            add_tile<TST, TKT, DEN>(an, ad, num, den,
                                     (int64_t)(s0 - a.s_base + w * TST) * sstride + k0 + lane * TKT, sstride);
 #pragma unroll
             for (int s = 0; s < TST; ++s)
@@ -360,7 +362,11 @@ __global__ __launch_bounds__(kBlock, (StripeCfg<T, DEN, TILE>::OCC)) void k_stri
 {
     using SM = StripeSmem<T, DEN, TILE>;
     __shared__ SM sm;
-    stripe_tile<T, METHOD, DEN, TILE, CT>(a, blockIdx.x * SM::TKW, a.s_base + blockIdx.y * SM::TSW, sm);
+    // grid z: branch split z of kz, accumulated into its own state copy
+    const int32_t z = blockIdx.z;
+    const int32_t bb = (int32_t)((int64_t)a.B * z / a.kz), be = (int32_t)((int64_t)a.B * (z + 1) / a.kz);
+    stripe_tile<T, METHOD, DEN, TILE, CT>(a, blockIdx.x * SM::TKW, a.s_base + blockIdx.y * SM::TSW, bb, be,
+                                          a.num + z * a.zstride, a.den ? a.den + z * a.zstride : nullptr, sm);
 }
 
 // Persistent form for many jobs: every work-group takes items (job, tile) from a global
@@ -386,8 +392,18 @@ __global__ __launch_bounds__(kBlock, (StripeCfg<T, DEN, TILE>::OCC)) void k_stri
         const StripeArgs a = jobs[item.x];
         const int32_t kt = item.y % a.tiles_k, stile = item.y / a.tiles_k;
         const int32_t k0 = kt * SM::TKW, s0 = a.s_base + stile * SM::TSW;
-        stripe_tile<T, METHOD, DEN, TILE, CT>(a, k0, s0, sm);
+        stripe_tile<T, METHOD, DEN, TILE, CT>(a, k0, s0, 0, a.B, a.num, a.den, sm);
     }
+}
+
+// x[i] = sum_z x[z * zstride + i] over the branch splits, in split order.
+__global__ void k_reduce_z(double *__restrict__ x, int64_t zstride, int32_t kz, int64_t count)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= count) return;
+    double s = x[i];
+    for (int32_t z = 1; z < kz; ++z) s += x[z * zstride + i];
+    x[i] = s;
 }
 
 // 1 / total per sample (FP64), for the fused transform.
@@ -537,6 +553,7 @@ static void tile_dims(StripeGeom *g)
 {
     g->tkw = 64 * StripeCfg<T, DEN, TILE>::TKT;
     g->tsw = 4 * StripeCfg<T, DEN, TILE>::TST;
+    g->occ = StripeCfg<T, DEN, TILE>::OCC;
 }
 
 StripeGeom stripe_geometry(int32_t n, bool fp64, int32_t den_mode, int32_t tile)
@@ -617,7 +634,7 @@ template <typename T, int TILE, typename CT>
 static hipError_t fused_dispatch(const StripeArgs &a, int32_t den_mode, const StripeGeom &g,
                                  hipStream_t st)
 {
-    dim3 grid((unsigned)a.tiles_k, (unsigned)a.tiles_s);
+    dim3 grid((unsigned)a.tiles_k, (unsigned)a.tiles_s, (unsigned)a.kz);
 #define UF_FUSED(M, D) k_stripe_fused<T, M, D, TILE, CT><<<grid, kBlock, 0, st>>>(a)
     if (a.method == UF_WEIGHTED_NORMALIZED) {
         if (den_mode == 0) UF_FUSED(UF_WEIGHTED_NORMALIZED, 0); else UF_FUSED(UF_WEIGHTED_NORMALIZED, 1);
@@ -631,12 +648,15 @@ static hipError_t fused_dispatch(const StripeArgs &a, int32_t den_mode, const St
 hipError_t launch_stripe_fused(bool fp64, int32_t method, int32_t den_mode, int32_t tile,
                                const void *C, int32_t cw, int64_t cstride, const double *inv_t,
                                const double *len, int32_t B, int32_t E, double *num, double *den,
-                               const StripeGeom &g, int32_t tile_s0, int32_t tile_s1, hipStream_t st)
+                               const StripeGeom &g, int32_t tile_s0, int32_t tile_s1,
+                               int32_t kz, int64_t zstride, hipStream_t st)
 {
     if (B <= 0 || tile_s1 <= tile_s0) return hipSuccess;
     StripeArgs a = make_stripe_args(method, C, cw, cstride, inv_t, len, B, E, num, den, g);
     a.s_base = tile_s0 * g.tsw;
     a.tiles_s = tile_s1 - tile_s0;
+    a.kz = kz < 1 ? 1 : kz;
+    a.zstride = zstride;
     const int key = (fp64 ? 6 : 0) + 2 * (tile == 1 ? 1 : tile == 2 ? 2 : 0) + (cw == 2 ? 1 : 0);
     switch (key) {
     case 0: return fused_dispatch<float, 0, int32_t>(a, den_mode, g, st);
@@ -676,6 +696,9 @@ StripeArgs make_stripe_args(int32_t method, const void *C, int32_t cw, int64_t c
     a.tiles_k = (int32_t)(g.sstride / g.tkw);
     a.tiles_s = g.spad / g.tsw;
     a.s_base = 0;
+    a.kz = 1;
+    a.pad2 = 0;
+    a.zstride = 0;
     return a;
 }
 
@@ -714,6 +737,13 @@ hipError_t launch_stripe_queue(bool fp64, int32_t method, int32_t cw, int32_t de
     }
 #undef UF_QM
 #undef UF_Q
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_z(double *x, int64_t zstride, int32_t kz, int64_t count, hipStream_t st)
+{
+    if (kz <= 1 || count <= 0) return hipSuccess;
+    k_reduce_z<<<grid1(count, kBlock), kBlock, 0, st>>>(x, zstride, kz, count);
     return hipGetLastError();
 }
 

@@ -89,6 +89,7 @@ struct StripeGeom {
     int64_t sstride;         // row stride of num/den (multiple of tkw)
     int32_t spad;            // stripes rounded up to tsw
     int64_t estride;         // embedding row stride
+    int32_t occ;             // work-groups per CU the striped kernels are compiled for
 };
 StripeGeom stripe_geometry(int32_t n, bool fp64, int32_t den_mode, int32_t tile = 0);
 
@@ -112,6 +113,8 @@ struct StripeArgs {
     double *num, *den;       // stripe state [spad][sstride]
     int64_t sstride;
     int32_t method, tiles_k, tiles_s, s_base;   // s_base: stripe held by state row 0
+    int32_t kz, pad2;        // branch splits (grid z), each with its own state copy
+    int64_t zstride;         // elements between state copies
 };
 StripeArgs make_stripe_args(int32_t method, const void *C, int32_t cw, int64_t cstride,
                             const double *inv_t, const double *len, int32_t B, int32_t E,
@@ -125,7 +128,10 @@ hipError_t launch_inv_totals(const int32_t *totals, int32_t n, double *inv_t, hi
 hipError_t launch_stripe_fused(bool fp64, int32_t method, int32_t den_mode, int32_t tile,
                                const void *C, int32_t cw, int64_t cstride, const double *inv_t,
                                const double *len, int32_t B, int32_t E, double *num, double *den,
-                               const StripeGeom &g, int32_t tile_s0, int32_t tile_s1, hipStream_t st);
+                               const StripeGeom &g, int32_t tile_s0, int32_t tile_s1,
+                               int32_t kz, int64_t zstride, hipStream_t st);
+// x[i] = sum over z of x[z * zstride + i] (z in order), for i < count.
+hipError_t launch_reduce_z(double *x, int64_t zstride, int32_t kz, int64_t count, hipStream_t st);
 // Writes the pairs of stripes [s_begin, s_end) into a full condensed output; the state
 // block's row 0 holds stripe s_base.
 hipError_t launch_condense_range(int32_t method, const double *num, const double *den, const double *D,

@@ -83,8 +83,17 @@ struct Profiler {
 
 }  // namespace ufmi
 
+// Every entry point starts here: drops an error left pending by earlier, unrelated HIP calls
+// on this thread (so that a later launch check does not report it) and selects the device.
+inline hipError_t enter_device(int device)
+{
+    (void)hipGetLastError();
+    return hipSetDevice(device);
+}
+
 struct uf_context {
     int32_t device = 0;
+    int32_t n_cu = 256;      // compute units of the device
     std::string err;
 };
 

@@ -33,6 +33,29 @@ def test_library_exports_every_declared_symbol():
     assert sorted(binding.EXPORTED) == declared
 
 
+def _header_struct_fields(name):
+    src = open(os.path.join(ROOT, "include", "unifrac_mi.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    end = src.index("} " + name + ";")
+    body = src[src.rindex("typedef struct {", 0, end) + len("typedef struct {"):end]
+    fields = []
+    for decl in body.split(";"):
+        parts = [p.strip() for p in decl.split(",") if p.strip()]
+        for p in parts:   # "const int32_t *parent" or, after a comma, a bare name
+            fields.append(re.findall(r"[A-Za-z_][A-Za-z_0-9]*", p)[-1])
+    return fields
+
+
+@pytest.mark.parametrize("cname,pyname", [("uf_tuning", "UfTuning"), ("uf_tree", "UfTree"),
+                                          ("uf_table", "UfTable"), ("uf_plan_info", "UfPlanInfo"),
+                                          ("uf_job", "UfJob"), ("uf_kernel_stat", "UfKernelStat")])
+def test_binding_structs_match_header(cname, pyname):
+    # the ctypes mirrors must list the header's fields in the header's order
+    want = _header_struct_fields(cname)
+    got = [f for f, _ in getattr(binding, pyname)._fields_]
+    assert got == want, (cname, got, want)
+
+
 def test_status_strings():
     lib = uf.library()
     for code, name in binding.STATUS_NAMES.items():

@@ -120,6 +120,44 @@ def test_tile_shapes_match_oracle(uf, ctx, problems, method, prec, den_mode, til
         assert err.max() <= TOL[prec]
 
 
+@pytest.mark.parametrize("k_split", [1, 2, 5, 0])
+@pytest.mark.parametrize("den_mode", [0, 1])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_branch_splits_match_oracle(uf, ctx, problems, prec, den_mode, k_split):
+    # the fused kernel's branch splits (separate state copies summed in order), explicit and
+    # automatic, on both methods
+    prob = problems["cfg2_shape_600"]
+    plan = _plan(uf, ctx, prob)
+    for method in (UW, WN):
+        got = plan.distance(method, prec, tuning=dict(den_mode=den_mode, tile=2, k_split=k_split, emb_batch=64))
+        want = oracle.problem_condensed(prob, OMETHOD[method])
+        err = _report(f"k_split={k_split} den_mode={den_mode} {method} {prec}", got, want)
+        assert err.max() <= TOL[prec]
+
+
+@pytest.mark.parametrize("k_split", [3, 8])
+def test_branch_splits_dyadic_bit_identical(uf, ctx, k_split):
+    prob = config_problem(1, n=300, tips=600, p_nonzero=0.3, depth=256, dyadic=True, seed=91)
+    plan = _plan(uf, ctx, prob)
+    for method in (UW, WN):
+        for prec in ("fp64", "fp32"):
+            got = plan.distance(method, prec, tuning=dict(k_split=k_split, emb_batch=16))
+            np.testing.assert_array_equal(got, oracle.problem_condensed(prob, OMETHOD[method]))
+
+
+def test_branch_splits_stripe_range(uf, ctx, problems):
+    # a stripe range computed with splits equals the same pairs of the full matrix
+    prob = problems["cfg2_shape_600"]
+    plan = _plan(uf, ctx, prob)
+    full = plan.distance(WN, "fp64", tuning=dict(k_split=1))
+    n = prob.n_samples
+    out = np.full(n * (n - 1) // 2, -1.0)
+    plan.distance_stripes(37, 211, out, WN, "fp64", tuning=dict(k_split=4))
+    sel = out != -1.0
+    assert sel.sum() > 0
+    np.testing.assert_allclose(out[sel], full[sel], rtol=0, atol=1e-12)
+
+
 @pytest.mark.parametrize("emb_batch", [1, 7, 128])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("method", [UW, WN])
