@@ -61,8 +61,8 @@ OPS_PER_UPDATE = {0: 4, 1: 2}   # den_mode 0: both stripes; 1: numerator only
 # it was measured on, and is reported as null once that source has changed.
 TRAFFIC = {
     "striped/4096x65534/fp32/den1/tile2/Edefault": {
-        "src_sha256": "a104e7ef4d1cf59e", "fetch": 49178603546, "write": 34359144192,
-        "bytes": 83537747738, "profile": "profiles/k_stripe_fused_wn_fp32_4096x65534.md"},
+        "src_sha256": "11cc6cf065ad9f92", "fetch": 53476892905, "write": 34422454144,
+        "bytes": 87899347049, "profile": "profiles/k_stripe_fused_wn_fp32_4096x65534.md"},
     "mfma/25000x599998/k_chunk4096/variant0": {
         "src_sha256": "3e64b53e71ec43ba", "fetch": 703854942248, "write": 425141495648,
         "bytes": 1128996437896, "profile": "profiles/k_mfma_gemm_uw_25000x599998.md"},
