@@ -24,6 +24,11 @@ Workloads (--workload):
                      matrix on the matrix cores.
   large-wn           the same inputs, weighted normalized FP32 striped: one GPU's share (a
                      contiguous 1/--share of the stripes) of a split of the full matrix.
+  hbm                the striped kernel in its memory-bound regime: FP64 numerator and
+                     denominator stripes, E = 8 branches per batch, on a 1 GB stripe state
+                     (stripes [0, 2,560) of 25,000 samples; workload-2 distributions on an
+                     8,192-tip coalescent tree), so each batch streams 2 GB of state through
+                     HBM; reported against the HBM roof.
 
 The oracle (FP64 CPU) is timed on the host cores on a seeded sample of pairs as the CPU
 baseline, and the same sample gives the max and mean absolute error of every GPU result.
@@ -66,6 +71,9 @@ TRAFFIC = {
     "mfma/25000x599998/k_chunk4096/variant0": {
         "src_sha256": "3e64b53e71ec43ba", "fetch": 703854942248, "write": 425141495648,
         "bytes": 1128996437896, "profile": "profiles/k_mfma_gemm_uw_25000x599998.md"},
+    "hbm/25000x16382/fp64/den0/tile0/E8": {
+        "src_sha256": "11cc6cf065ad9f92", "fetch": 2204817298427, "write": 2226193665408,
+        "bytes": 4431010963835, "profile": "profiles/k_stripe_fused_hbm_regime_fp64_25000x16382.md"},
 }
 
 
@@ -94,7 +102,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="striped",
-                    choices=["striped", "mfma", "batch", "large-wn", "large-uw"])
+                    choices=["striped", "mfma", "batch", "large-wn", "large-uw", "hbm"])
     ap.add_argument("--share", type=int, default=8,
                     help="large-wn: compute 1/share of the stripes (one GPU's share)")
     ap.add_argument("--method", default=None)
@@ -495,6 +503,67 @@ def bench_large(args, part):
     return res
 
 
+def bench_hbm(args):
+    import torch
+    import paper_2005_05826_amd as uf
+    from synth import config_problem
+    n = args.n or 25000
+    prob = config_problem(2, n=n, tips=args.tips or 8192, k=800, seed=20050526 + 7)
+    n, B = prob.n_samples, prob.n_nodes - 1
+    s0, s1 = 0, 2560
+    E = args.emb_batch or 8
+    ctx = uf.Context(0)
+    stream = torch.cuda.current_stream()
+    plan = uf.Plan.from_problem(ctx, prob, stream=stream)
+    out = torch.empty(n * (n - 1) // 2, dtype=torch.float64, device="cuda:0")
+    tuning = dict(emb_batch=E, den_mode=0, tile=0, k_split=1)
+    for _ in range(args.warmup):
+        plan.distance_stripes(s0, s1, out, "weighted_normalized", "fp64", tuning=tuning, stream=stream)
+    plan.set_profiling(True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        plan.distance_stripes(s0, s1, out, "weighted_normalized", "fp64", tuning=tuning, stream=stream)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / args.steps
+    prof = plan.profile()
+    plan.set_profiling(False)
+    launches, total_ms = prof.get("stripe", (0, 0.0))
+    # FP64 tile 0: 256-sample x 32-stripe work-group tiles; the state rows are padded to them
+    sstride = -(-n // 256) * 256
+    rows = -(-(s1 - s0) // 32) * 32
+    batches = -(-B // E)
+    state = rows * sstride * 8 * 2                      # num + den, FP64
+    alg = batches * state * 2 + B * sstride * 2         # read + write per batch, counts once
+    gbs = alg / (total_ms / max(1, launches) * 1e-3) / 1e9 if launches else 0.0
+    updates = (s1 - s0) * n * B
+    res = base_record(args, updates / dt, dt, "f64",
+                      {"workload": f"memory-bound striped regime: weighted normalized FP64 "
+                                   f"(numerator and denominator stripes), E = {E}, stripes "
+                                   f"[{s0}, {s1}) of {n // 2} for {n} samples, coalescent tree "
+                                   f"with {(prob.n_nodes + 1) // 2} tips ({B} branches)",
+                       "n_samples": n, "branches": B, "stripes": [s0, s1], "emb_batch": E,
+                       "state_bytes": state})
+    res["kernels_ms_per_step"] = {k: round(v[1] / args.steps, 3) for k, v in prof.items()}
+    res["roofline"] = {"kernel": "k_stripe_fused", "bound": "hbm", "achieved": round(gbs, 1),
+                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                       "algorithmic_bytes": alg,
+                       "avg_launch_ms": round(total_ms / max(1, launches), 3)}
+    if launches:
+        add_traffic(res["roofline"], f"hbm/{n}x{B}/fp64/den0/tile0/E{E}", "k_stripe.hip",
+                    total_ms / launches)
+    if not args.no_cpu:
+        cpu, pi, pj, want = oracle_sample(prob, "weighted_normalized", args.cpu_seconds, 20050526 + 94,
+                                          subset=600)
+        res["cpu_baseline"] = cpu
+        d = pj - pi
+        st = np.where(d <= n // 2, d - 1, n - d - 1)
+        keep = (st >= s0) & (st < s1)
+        if keep.any():
+            res["error_vs_oracle"] = {"fp64": errors(out, n, pi[keep], pj[keep], want[keep])}
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -513,7 +582,8 @@ def main():
     if args.workload.startswith("large"):
         res = bench_large(args, args.workload.split("-")[1])
     else:
-        res = {"striped": bench_striped, "mfma": bench_mfma, "batch": bench_batch}[args.workload](args)
+        res = {"striped": bench_striped, "mfma": bench_mfma, "batch": bench_batch,
+               "hbm": bench_hbm}[args.workload](args)
     print(json.dumps(res), flush=True)
 
 
