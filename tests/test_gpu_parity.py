@@ -298,20 +298,23 @@ def cfg2():
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_workload2_full_size_sampled(uf, ctx, cfg2, prec):
-    """The benchmark workload (4,096 samples, 32,768-tip coalescent tree), default knobs:
-    every output checked for range, a seeded sample of pairs checked against the oracle."""
+@pytest.mark.parametrize("tuning", [{}, dict(den_mode=1, tile=2)], ids=["default", "bench_headline"])
+def test_workload2_full_size_sampled(uf, ctx, cfg2, prec, tuning):
+    """The benchmark workload (4,096 samples, 32,768-tip coalescent tree), with the default
+    knobs and with the configuration the benchmark times (separable denominator, tile shape
+    2, automatic branch splits): every output checked for range, a seeded sample of pairs
+    checked against the oracle."""
     import torch
     plan = _plan(uf, ctx, cfg2)
     n = cfg2.n_samples
     out = torch.empty(n * (n - 1) // 2, dtype=torch.float64, device="cuda:0")
-    plan.distance(WN, prec, out=out)
+    plan.distance(WN, prec, out=out, tuning=tuning)
     torch.cuda.synchronize()
     got = out.cpu().numpy()
     assert np.all(got >= 0) and np.all(got <= 1)
     pi, pj = _sampled_pairs(n, 1500, 48, seed=11)
     want = oracle.problem_pairs(cfg2, oracle.WEIGHTED_NORMALIZED, pi, pj)
-    err = _report(f"workload2 WN {prec} sampled", got[condensed_index(n, pi, pj)], want)
+    err = _report(f"workload2 WN {prec} {tuning} sampled", got[condensed_index(n, pi, pj)], want)
     assert err.max() <= TOL[prec]
 
 
