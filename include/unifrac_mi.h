@@ -104,8 +104,9 @@ typedef struct {
 typedef struct {
     int32_t emb_batch;  /* branches per embedding batch streamed through the striped kernel
                            (the batch depth of Section 3, Fig. 2)                            */
-    int32_t k_chunk;    /* matrix-core path: branches accumulated in FP32 before each FP64
-                           flush (rounded to a multiple of 64)                               */
+    int32_t k_chunk;    /* matrix-core path: branches per FP32 accumulation chunk (rounded
+                           to an even number of 64-branch stages); chunk sums go to FP64 one
+                           by one (variant 1) or four at a time, added in FP32 (variant 0)  */
     int32_t den_mode;   /* striped path: 0 = numerator and denominator stripes (default);
                            1 = numerator stripes only, denominator from per-sample sums
                            (weighted normalized: sum_b L_b p_ib + sum_b L_b p_jb)            */

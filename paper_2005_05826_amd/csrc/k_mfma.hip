@@ -234,6 +234,21 @@ __device__ void mfma_tile(const MfmaArgs &a, int32_t row0, int32_t col0, MfmaSme
     }
     if (n_kstep > 1) gload(R1, 1);
     __syncthreads();
+    // Variant 0 (REG64 = false): the FP32 sums of kGroupChunks consecutive chunks are added
+    // in FP32 (a few roundings on top of each chunk's) before one FP64 read-modify-write of
+    // the output, which cuts that traffic kGroupChunks-fold.
+    constexpr int kGroupChunks = 4;
+    float acc2[REG64 ? 1 : 2][REG64 ? 1 : 2][REG64 ? 1 : 16];
+    if (!REG64) {
+#pragma unroll
+        for (int x = 0; x < (REG64 ? 1 : 2); ++x)
+#pragma unroll
+            for (int y = 0; y < (REG64 ? 1 : 2); ++y)
+#pragma unroll
+                for (int r = 0; r < (REG64 ? 1 : 16); ++r) acc2[x][y][r] = 0.f;
+    }
+    int32_t grouped = 0;
+    bool flushed = false;
     int32_t ks = 0;
     while (ks < n_kstep) {
         // FP32 accumulation inside a chunk of chunk_steps stages, then one FP64 flush
@@ -261,9 +276,23 @@ __device__ void mfma_tile(const MfmaArgs &a, int32_t row0, int32_t col0, MfmaSme
                     for (int r = 0; r < (REG64 ? 16 : 1); ++r) acc64[x][y][r] += (double)acc[x][y][r];
             continue;
         }
-        // FP64 cross-chunk sum kept in the output itself: the first chunk stores, later
-        // chunks add (each element belongs to this work-group alone, chunks in K order).
-        const bool first = (kend <= chunk_steps);
+#pragma unroll
+        for (int x = 0; x < (REG64 ? 1 : 2); ++x)
+#pragma unroll
+            for (int y = 0; y < (REG64 ? 1 : 2); ++y)
+#pragma unroll
+                for (int r = 0; r < (REG64 ? 1 : 16); ++r) acc2[x][y][r] += acc[REG64 ? 0 : x][REG64 ? 0 : y][REG64 ? 0 : r];
+        if (++grouped < kGroupChunks && ks < n_kstep) continue;
+        grouped = 0;
+        // FP64 cross-chunk sum kept in the output itself: the first flush stores, later
+        // flushes add (each element belongs to this work-group alone, chunks in K order).
+        const bool first = !flushed;
+        flushed = true;
+        // the lane's row and column origins pass through an empty asm so that the element
+        // addresses are computed here, per flush, instead of being hoisted out of the
+        // chunk loop into 64 live pointer registers
+        int32_t ib = row0 + wm * 64 + 4 * kg, jb = col0 + wn * 64 + lrow;
+        asm volatile("" : "+v"(ib), "+v"(jb));
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
@@ -272,16 +301,22 @@ __device__ void mfma_tile(const MfmaArgs &a, int32_t row0, int32_t col0, MfmaSme
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
-                    const int32_t i = elem_row(mb, r);
-                    const int32_t j = elem_col(nb);
+                    const int32_t i = ib + mb * 32 + 8 * (r >> 2) + (r & 3);
+                    const int32_t j = jb + nb * 32;
                     if (i < n && j < n && i <= j) {
                         double *dst = i < j ? S + ((int64_t)n * i - (int64_t)i * (i + 1) / 2 + (j - i - 1)) : T + i;
-                        const double v = (double)acc[mb][nb][r];
+                        const double v = (double)acc2[REG64 ? 0 : mb][REG64 ? 0 : nb][REG64 ? 0 : r];
                         *dst = first ? v : *dst + v;
                     }
                 }
             }
         __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int x = 0; x < (REG64 ? 1 : 2); ++x)
+#pragma unroll
+            for (int y = 0; y < (REG64 ? 1 : 2); ++y)
+#pragma unroll
+                for (int r = 0; r < (REG64 ? 1 : 16); ++r) acc2[x][y][r] = 0.f;
     }
     if (REG64) {
 #pragma unroll
