@@ -69,8 +69,8 @@ TRAFFIC = {
         "src_sha256": "11cc6cf065ad9f92", "fetch": 53476892905, "write": 34422454144,
         "bytes": 87899347049, "profile": "profiles/k_stripe_fused_wn_fp32_4096x65534.md"},
     "mfma/25000x599998/k_chunk4096/variant0": {
-        "src_sha256": "3e64b53e71ec43ba", "fetch": 703854942248, "write": 425141495648,
-        "bytes": 1128996437896, "profile": "profiles/k_mfma_gemm_uw_25000x599998.md"},
+        "src_sha256": "5d48aca7be669671", "fetch": 204218464352, "write": 102445921984,
+        "bytes": 306664386336, "profile": "profiles/k_mfma_gemm_uw_25000x599998.md"},
     "hbm/25000x16382/fp64/den0/tile0/E8": {
         "src_sha256": "11cc6cf065ad9f92", "fetch": 2204817298427, "write": 2226193665408,
         "bytes": 4431010963835, "profile": "profiles/k_stripe_fused_hbm_regime_fp64_25000x16382.md"},
