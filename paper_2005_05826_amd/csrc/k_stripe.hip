@@ -337,8 +337,11 @@ __device__ void stripe_tile(const StripeArgs &a, int32_t k0, int32_t s0, int32_t
                 }
         }
         if (e0 + eb >= b1) {   // end of a batch: add the register tile into the FP64 state
-            add_tile<TST, TKT, DEN>(an, ad, num, den,
-                                    (int64_t)(s0 - a.s_base + w * TST) * sstride + k0 + lane * TKT, sstride);
+            // the offset passes through an empty asm so that the row addresses are formed
+            // here rather than hoisted out of the stage loop into live registers
+            int64_t off = (int64_t)(s0 - a.s_base + w * TST) * sstride + k0 + lane * TKT;
+            asm volatile("" : "+v"(off));
+            add_tile<TST, TKT, DEN>(an, ad, num, den, off, sstride);
 #pragma unroll
             for (int s = 0; s < TST; ++s)
 #pragma unroll
