@@ -66,14 +66,14 @@ OPS_PER_UPDATE = {0: 4, 1: 2}   # den_mode 0: both stripes; 1: numerator only
 # it was measured on, and is reported as null once that source has changed.
 TRAFFIC = {
     "striped/4096x65534/fp32/den1/tile2/Edefault": {
-        "src_sha256": "11cc6cf065ad9f92", "fetch": 53476892905, "write": 34422454144,
-        "bytes": 87899347049, "profile": "profiles/k_stripe_fused_wn_fp32_4096x65534.md"},
+        "src_sha256": "6bec7535a45a79f0", "fetch": 52223576073, "write": 34424087936,
+        "bytes": 86647664009, "profile": "profiles/k_stripe_fused_wn_fp32_4096x65534.md"},
     "mfma/25000x599998/k_chunk4096/variant0": {
         "src_sha256": "5d48aca7be669671", "fetch": 204218464352, "write": 102445921984,
         "bytes": 306664386336, "profile": "profiles/k_mfma_gemm_uw_25000x599998.md"},
     "hbm/25000x16382/fp64/den0/tile0/E8": {
-        "src_sha256": "11cc6cf065ad9f92", "fetch": 2204817298427, "write": 2226193665408,
-        "bytes": 4431010963835, "profile": "profiles/k_stripe_fused_hbm_regime_fp64_25000x16382.md"},
+        "src_sha256": "6bec7535a45a79f0", "fetch": 2199719646728, "write": 2220552224768,
+        "bytes": 4420271871496, "profile": "profiles/k_stripe_fused_hbm_regime_fp64_25000x16382.md"},
 }
 
 
