@@ -105,6 +105,8 @@ def parse():
                     choices=["striped", "mfma", "batch", "large-wn", "large-uw", "hbm"])
     ap.add_argument("--share", type=int, default=8,
                     help="large-wn: compute 1/share of the stripes (one GPU's share)")
+    ap.add_argument("--all-shares", action="store_true",
+                    help="large-wn: compute every share in turn, i.e. the full matrix")
     ap.add_argument("--method", default=None)
     ap.add_argument("--precision", default=None)
     ap.add_argument("--compare", default=None,
@@ -159,11 +161,15 @@ def oracle_sample(prob, method, seconds, seed, subset=None):
         a, b = sample_pairs(rng, pool.size, m)
         return pool[a], pool[b]
 
-    pi, pj = draw(64)
-    t = time.perf_counter()
-    oracle.problem_pairs(prob, om, pi, pj)
-    per_pair = (time.perf_counter() - t) / max(1, pi.size)
-    m = int(min(max(seconds / max(per_pair, 1e-9), 200), 2_000_000))
+    # two calibration runs: a tiny one, then one of about a tenth of the target (the tiny
+    # one is dominated by fixed costs and would undersize the sample on many threads)
+    m = 64
+    for frac in (0.1, 1.0):
+        pi, pj = draw(m)
+        t = time.perf_counter()
+        oracle.problem_pairs(prob, om, pi, pj)
+        per_pair = (time.perf_counter() - t) / max(1, pi.size)
+        m = int(min(max(frac * seconds / max(per_pair, 1e-9), 200), 2_000_000))
     pi, pj = draw(m)
     threads = oracle.max_threads()
     log(f"oracle: {pi.size} sampled pairs on {threads} threads")
@@ -201,6 +207,26 @@ def timed_runs(plan, method, prec, tuning, out, steps, warmup, stream):
     prof = plan.profile()
     plan.set_profiling(False)
     return dt, prof
+
+
+def end_to_end(uf, ctx, prob, method, prec, tuning, stream, runs):
+    """Wall time from host inputs to host output: a new plan from the host tree and CSR table
+    (validation, host preparation, uploads), the distances, and the condensed FP64 matrix
+    copied back to host memory.  Best of `runs`."""
+    import torch
+    best = float("inf")
+    for _ in range(runs):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        p2 = uf.Plan.from_problem(ctx, prob, stream=stream)
+        host = p2.distance(method, prec, tuning=tuning, stream=stream)
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t)
+        p2.close()
+        del host
+    return {"ms": round(best * 1e3, 3), "runs": runs,
+            "what": "host tree + CSR table -> new plan (validation, preparation, upload) -> "
+                    "distances -> condensed FP64 matrix in host memory"}
 
 
 def base_record(args, value, dt, dtype, config):
@@ -287,6 +313,8 @@ def bench_striped(args):
     res["roofline"] = roofline
     for name, (_, rec) in outs.items():
         res[name] = rec
+    res["end_to_end"] = end_to_end(uf, ctx, prob, method, prec, tuning, stream, 3)
+    log(f"end to end: {res['end_to_end']['ms']:.1f} ms")
     if not args.no_cpu:
         cpu, pi, pj, want = oracle_sample(prob, method, args.cpu_seconds, 20050526 + 99)
         res["cpu_baseline"] = cpu
@@ -341,6 +369,8 @@ def bench_mfma(args):
         dt2, prof2 = timed_runs(plan, "unweighted", compare, {}, out2, 1, 0, stream)
         res["compare"] = {"precision": compare, "ms_per_step": round(dt2 * 1e3, 3),
                           "value": round(updates / dt2, 1), "speedup_of_headline": round(dt2 / dt, 3)}
+    res["end_to_end"] = end_to_end(uf, ctx, prob, "unweighted", "mfma_bf16x2", tuning, stream, 1)
+    log(f"end to end: {res['end_to_end']['ms']:.1f} ms")
     if not args.no_cpu:
         cpu, pi, pj, want = oracle_sample(prob, "unweighted", args.cpu_seconds, 20050526 + 98, subset=400)
         res["cpu_baseline"] = cpu
@@ -458,31 +488,47 @@ def bench_large(args, part):
                            "frac": round(achieved / MFMA_BF16_PEAK_TFLOPS, 4), "traffic": None}
         method = "unweighted"
     else:
-        s0, s1 = 0, (S + args.share - 1) // args.share
+        chunk = (S + args.share - 1) // args.share
+        # the stripe ranges one step computes: one share, or all of them in turn (the full
+        # matrix; the count rows stay resident and each range's state is freed after it)
+        ranges = [(g * chunk, min(S, (g + 1) * chunk)) for g in range(args.share)] \
+            if args.all_shares else [(0, chunk)]
+        s0, s1 = ranges[0][0], ranges[-1][1]
         out = torch.empty(n_pairs, dtype=torch.float32, device="cuda:0")
         den_mode = 1 if args.den_mode is None else args.den_mode
         tuning = dict(emb_batch=args.emb_batch, den_mode=den_mode,
                       tile=2 if args.tile is None else args.tile, count_width=2)
+
+        def step():
+            for a, b in ranges:
+                plan.distance_stripes(a, b, out, "weighted_normalized", "fp32", out_dtype="f32",
+                                      tuning=tuning, stream=stream)
+                if len(ranges) > 1:
+                    torch.cuda.synchronize()
+                    log(f"stripes [{a}, {b}) done")
+
         for _ in range(args.warmup):
-            plan.distance_stripes(s0, s1, out, "weighted_normalized", "fp32", out_dtype="f32",
-                                  tuning=tuning, stream=stream)
+            step()
         plan.set_profiling(True)
         torch.cuda.synchronize()
         t = time.perf_counter()
         for _ in range(args.steps):
-            plan.distance_stripes(s0, s1, out, "weighted_normalized", "fp32", out_dtype="f32",
-                                  tuning=tuning, stream=stream)
+            step()
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t) / args.steps
         prof = plan.profile()
         plan.set_profiling(False)
-        updates = (s1 - s0) * n * B
+        # pair-branch updates: every pair once for the full matrix (the last stripe of an
+        # even n holds n/2 pairs), else n per stripe of the range
+        updates = n_pairs * B if s1 == S else (s1 - s0) * n * B
         launches, total_ms = prof.get("stripe", (0, 0.0))
         achieved = OPS_PER_UPDATE[den_mode] * updates / (total_ms / args.steps * 1e-3) / 1e12 if launches else 0.0
         res = base_record(args, updates / dt, dt, "f32",
                           {"workload": f"weighted-normalized FP32 striped UniFrac, {n} samples, random "
                                        f"binary tree with {(prob.n_nodes + 1) // 2} tips ({B} branches), "
-                                       f"stripes [{s0}, {s1}) = 1/{args.share} of {S}",
+                                       + (f"full matrix, stripes in {len(ranges)} ranges of {chunk}"
+                                          if len(ranges) > 1 else
+                                          f"stripes [{s0}, {s1}) = 1/{args.share} of {S}"),
                            "n_samples": n, "branches": B, "stripes": [s0, s1],
                            "precision": "fp32", "count_width": 2})
         res["roofline"] = {"kernel": "k_stripe_fused", "bound": "alu", "achieved": round(achieved, 3),

@@ -26,20 +26,20 @@ constexpr int kBlock = 256;  // 4 waves: wave w owns stripes [w*TST, (w+1)*TST) 
 // windows (2 * TKW + TSW values per branch for TKW * TSW updates).
 template <typename T, int DEN, int TILE>
 struct StripeCfg;
-// OCC: work-groups per CU the fused and queued kernels are compiled for (tile 2 trades a
-// smaller tile for three waves per SIMD).
-template <> struct StripeCfg<double, 0, 0> { static constexpr int TKT = 4, TST = 8, EB = 16, OCC = 2; };
-template <> struct StripeCfg<double, 0, 1> { static constexpr int TKT = 2, TST = 12, EB = 16, OCC = 2; };
-template <> struct StripeCfg<double, 0, 2> { static constexpr int TKT = 2, TST = 8, EB = 16, OCC = 3; };
-template <> struct StripeCfg<double, 1, 0> { static constexpr int TKT = 4, TST = 16, EB = 16, OCC = 2; };
-template <> struct StripeCfg<double, 1, 1> { static constexpr int TKT = 2, TST = 24, EB = 16, OCC = 2; };
-template <> struct StripeCfg<double, 1, 2> { static constexpr int TKT = 4, TST = 8, EB = 16, OCC = 3; };
-template <> struct StripeCfg<float, 0, 0> { static constexpr int TKT = 4, TST = 16, EB = 16, OCC = 2; };
-template <> struct StripeCfg<float, 0, 1> { static constexpr int TKT = 8, TST = 8, EB = 16, OCC = 2; };
-template <> struct StripeCfg<float, 0, 2> { static constexpr int TKT = 4, TST = 8, EB = 16, OCC = 3; };
-template <> struct StripeCfg<float, 1, 0> { static constexpr int TKT = 4, TST = 24, EB = 16, OCC = 2; };
-template <> struct StripeCfg<float, 1, 1> { static constexpr int TKT = 8, TST = 16, EB = 16, OCC = 2; };
-template <> struct StripeCfg<float, 1, 2> { static constexpr int TKT = 4, TST = 16, EB = 16, OCC = 3; };
+// EB: most branches per LDS stage.  OCC: work-groups per CU the fused and queued kernels
+// are compiled for (tile 2 trades a smaller tile for three waves per SIMD).
+template <> struct StripeCfg<double, 0, 0> { static constexpr int TKT = 4, TST = 8, EB = 8, OCC = 2; };
+template <> struct StripeCfg<double, 0, 1> { static constexpr int TKT = 2, TST = 12, EB = 8, OCC = 2; };
+template <> struct StripeCfg<double, 0, 2> { static constexpr int TKT = 2, TST = 8, EB = 8, OCC = 3; };
+template <> struct StripeCfg<double, 1, 0> { static constexpr int TKT = 4, TST = 16, EB = 8, OCC = 2; };
+template <> struct StripeCfg<double, 1, 1> { static constexpr int TKT = 2, TST = 24, EB = 8, OCC = 2; };
+template <> struct StripeCfg<double, 1, 2> { static constexpr int TKT = 4, TST = 8, EB = 8, OCC = 3; };
+template <> struct StripeCfg<float, 0, 0> { static constexpr int TKT = 4, TST = 16, EB = 8, OCC = 2; };
+template <> struct StripeCfg<float, 0, 1> { static constexpr int TKT = 8, TST = 8, EB = 8, OCC = 2; };
+template <> struct StripeCfg<float, 0, 2> { static constexpr int TKT = 4, TST = 8, EB = 8, OCC = 3; };
+template <> struct StripeCfg<float, 1, 0> { static constexpr int TKT = 4, TST = 24, EB = 8, OCC = 2; };
+template <> struct StripeCfg<float, 1, 1> { static constexpr int TKT = 8, TST = 16, EB = 8, OCC = 2; };
+template <> struct StripeCfg<float, 1, 2> { static constexpr int TKT = 4, TST = 16, EB = 8, OCC = 3; };
 
 // Pins a register value at this point of the program: the conversions that follow cannot
 // be hoisted above it, which keeps the FP64 copies of a tile from being live all at once.
@@ -184,26 +184,42 @@ struct StripeSmem {
     // branches per stage: two stages must fit the work-group's share of the 160 KB LDS (OCC
     // work-groups per CU), and the next stage's counts wait in registers (EB x 3 per thread)
     static constexpr int EBM = (163840 / OCC - 256) / (2 * (TKW + VW) * (int)sizeof(T));
-    static constexpr int EB = EBM < 8 ? EBM : 8;
+    static constexpr int EBC = StripeCfg<T, DEN, TILE>::EB;
+    static constexpr int EB = EBM < EBC ? EBM : EBC;
     __align__(16) T su[2][EB * TKW];
     __align__(16) T sv[2][EB * VW];
     __align__(16) T sl[2][EB];   // the stage's branch lengths
 };
 
-// Reads N consecutive values from 16-byte aligned LDS with 16-byte loads (N rounded up to
-// whole loads; the caller guarantees the rounded range stays inside the array).
+// Reads N consecutive values from 16-byte aligned LDS: whole 16-byte loads, then one
+// narrower load for the remainder, so that every register a pending read writes is one the
+// caller uses (a register left unused by a wider load could be handed out as a temporary
+// while the load is in flight, which forces a wait for it).
 template <typename T, int N>
 __device__ inline void lds_read_vec(const T *src, T (&dst)[N])
 {
     constexpr int CH = 16 / (int)sizeof(T);
-    constexpr int NR = (N + CH - 1) / CH;
+    constexpr int NF = N / CH, RM = N % CH;
     typedef T vec __attribute__((ext_vector_type(CH)));
 #pragma unroll
-    for (int q = 0; q < NR; ++q) {
+    for (int q = 0; q < NF; ++q) {
         const vec x = *reinterpret_cast<const vec *>(src + q * CH);
 #pragma unroll
-        for (int c = 0; c < CH; ++c)
-            if (q * CH + c < N) dst[q * CH + c] = x[c];
+        for (int c = 0; c < CH; ++c) dst[q * CH + c] = x[c];
+    }
+    if constexpr (RM == 3) {
+        typedef T vec3 __attribute__((ext_vector_type(3)));
+        const vec3 x = *reinterpret_cast<const vec3 *>(src + NF * CH);
+        dst[NF * CH] = x[0];
+        dst[NF * CH + 1] = x[1];
+        dst[NF * CH + 2] = x[2];
+    } else if constexpr (RM == 2) {
+        typedef T vec2 __attribute__((ext_vector_type(2)));
+        const vec2 x = *reinterpret_cast<const vec2 *>(src + NF * CH);
+        dst[NF * CH] = x[0];
+        dst[NF * CH + 1] = x[1];
+    } else if constexpr (RM == 1) {
+        dst[NF * CH] = src[NF * CH];
     }
 }
 
@@ -314,8 +330,7 @@ __device__ void stripe_tile(const StripeArgs &a, int32_t k0, int32_t s0, int32_t
         const int32_t neb = more ? ((nb1 - ne0) < EB ? (nb1 - ne0) : EB) : 0;
         if (more) gload(ne0, neb);
         const T *su = sm.su[buf], *sv = sm.sv[buf], *sl = sm.sl[buf];
-        static_assert((NV + 16 / sizeof(T) - 1) / (16 / sizeof(T)) * (16 / sizeof(T)) <= TKT + TST,
-                      "vector reads of the v window stay inside the staged row");
+        static_assert(NV <= TKT + TST, "reads of the v window stay inside the staged row");
 #pragma unroll 1
         for (int e = 0; e < eb; ++e) {
             const T L = sl[e];
