@@ -66,14 +66,14 @@ OPS_PER_UPDATE = {0: 4, 1: 2}   # den_mode 0: both stripes; 1: numerator only
 # it was measured on, and is reported as null once that source has changed.
 TRAFFIC = {
     "striped/4096x65534/fp32/den1/tile2/Edefault": {
-        "src_sha256": "6bec7535a45a79f0", "fetch": 52223576073, "write": 34424087936,
-        "bytes": 86647664009, "profile": "profiles/k_stripe_fused_wn_fp32_4096x65534.md"},
+        "src_sha256": "7b92a5456d75ca39", "fetch": 53107397178, "write": 34423977536,
+        "bytes": 87531374714, "profile": "profiles/k_stripe_fused_wn_fp32_4096x65534.md"},
     "mfma/25000x599998/k_chunk4096/variant0": {
         "src_sha256": "5d48aca7be669671", "fetch": 204218464352, "write": 102445921984,
         "bytes": 306664386336, "profile": "profiles/k_mfma_gemm_uw_25000x599998.md"},
     "hbm/25000x16382/fp64/den0/tile0/E8": {
-        "src_sha256": "6bec7535a45a79f0", "fetch": 2199719646728, "write": 2220552224768,
-        "bytes": 4420271871496, "profile": "profiles/k_stripe_fused_hbm_regime_fp64_25000x16382.md"},
+        "src_sha256": "7b92a5456d75ca39", "fetch": 2178462920517, "write": 2228750978816,
+        "bytes": 4407213899333, "profile": "profiles/k_stripe_fused_hbm_regime_fp64_25000x16382.md"},
 }
 
 
@@ -121,7 +121,7 @@ def parse():
     ap.add_argument("--n", type=int, default=None, help="override the sample count")
     ap.add_argument("--tips", type=int, default=None, help="override the tip count")
     ap.add_argument("--jobs", type=int, default=64, help="batch workload: number of jobs")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle CPU time")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target oracle CPU time")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy 3 times (HBM counter scale)")
@@ -161,21 +161,20 @@ def oracle_sample(prob, method, seconds, seed, subset=None):
         a, b = sample_pairs(rng, pool.size, m)
         return pool[a], pool[b]
 
-    # two calibration runs: a tiny one, then one of about a tenth of the target (the tiny
-    # one is dominated by fixed costs and would undersize the sample on many threads)
+    # Grow the sample until one run takes at least half the target: each next size is the
+    # current one scaled by target / time, which cannot overshoot the target because the
+    # fixed part of the cost (walking up the counts of the touched samples) stops growing.
+    threads = oracle.max_threads()
     m = 64
-    for frac in (0.1, 1.0):
+    for _ in range(6):
         pi, pj = draw(m)
         t = time.perf_counter()
-        oracle.problem_pairs(prob, om, pi, pj)
-        per_pair = (time.perf_counter() - t) / max(1, pi.size)
-        m = int(min(max(frac * seconds / max(per_pair, 1e-9), 200), 2_000_000))
-    pi, pj = draw(m)
-    threads = oracle.max_threads()
-    log(f"oracle: {pi.size} sampled pairs on {threads} threads")
-    t = time.perf_counter()
-    want = oracle.problem_pairs(prob, om, pi, pj)
-    cpu_s = time.perf_counter() - t
+        want = oracle.problem_pairs(prob, om, pi, pj)
+        cpu_s = time.perf_counter() - t
+        if cpu_s >= 0.5 * seconds or m >= 2_000_000:
+            break
+        m = int(min(max(m * seconds / max(cpu_s, 1e-3), 2 * m), 2_000_000))
+    log(f"oracle: {pi.size} sampled pairs on {threads} threads in {cpu_s:.1f} s")
     where = f" among {subset} random samples" if pool is not None else ""
     cpu = {"value": round(pi.size * B / cpu_s, 1), "unit": "pair-branch updates/s",
            "cores": threads, "kind": "oracle",
