@@ -105,6 +105,8 @@ def parse():
                     choices=["striped", "mfma", "batch", "large-wn", "large-uw", "hbm"])
     ap.add_argument("--share", type=int, default=8,
                     help="large-wn: compute 1/share of the stripes (one GPU's share)")
+    ap.add_argument("--k-split", type=int, default=0,
+                    help="striped: branch ranges over grid z (0 = automatic)")
     ap.add_argument("--all-shares", action="store_true",
                     help="large-wn: compute every share in turn, i.e. the full matrix")
     ap.add_argument("--method", default=None)
@@ -257,7 +259,7 @@ def bench_striped(args):
     plan = uf.Plan.from_problem(ctx, prob, stream=stream)
     den_mode = 1 if args.den_mode is None else args.den_mode
     tile = 2 if args.tile is None else args.tile
-    tuning = dict(emb_batch=args.emb_batch, den_mode=den_mode, tile=tile)
+    tuning = dict(emb_batch=args.emb_batch, den_mode=den_mode, tile=tile, k_split=args.k_split)
     out = torch.empty(n_pairs, dtype=torch.float64, device="cuda:0")
     log(f"timing {prec} (den_mode {den_mode}, tile {tile}): {args.warmup} warmup + {args.steps} steps")
     dt, prof = timed_runs(plan, method, prec, tuning, out, args.steps, args.warmup, stream)
