@@ -438,6 +438,16 @@ def bench_batch(args):
                        "tips_range": [min((p.n_nodes + 1) // 2 for p in probs),
                                       max((p.n_nodes + 1) // 2 for p in probs)]})
     res["eager_run_ms"] = round(eager * 1e3, 3)
+    # one graph holds both kernel families, so the roofline is the time the work would take
+    # at the two peaks (FP32 VALU for the weighted updates, bf16 matrix cores for the
+    # unweighted products) over the measured time
+    wn_ops = OPS_PER_UPDATE[tuning["den_mode"]] * updates // 2
+    uw_flops = sum(4 * (p.n_nodes - 1) * p.n_samples * (p.n_samples + 1) // 2 for p in probs)
+    t_peak = wn_ops / (VALU_PEAK_TOPS["fp32"] * 1e12) + uw_flops / (MFMA_BF16_PEAK_TFLOPS * 1e12)
+    res["roofline"] = {"kernel": "k_stripe_queue + k_mfma_queue (one graph)", "bound": "alu",
+                       "achieved": round(t_peak * 1e3, 3), "peak": round(dt * 1e3, 3),
+                       "unit": "ms at peak vs ms measured", "frac": round(t_peak / dt, 4),
+                       "wn_fp32_ops": wn_ops, "uw_bf16_flops": uw_flops, "traffic": None}
     res["tuning"] = {"used": tuning, "autotune": tuned}
     res["kernels_ms_per_step"] = {k: round(v[1] / args.steps, 3) for k, v in prof.items()}
     if not args.no_cpu:
