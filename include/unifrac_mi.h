@@ -130,8 +130,9 @@ typedef struct {
                            this many contiguous ranges, each accumulated by its own grid
                            slice into its own copy of the stripe state, and the copies are
                            summed in order afterwards (more work-groups when the stripe
-                           tiles alone do not fill the device); 0 = automatic (about two
-                           full device rounds, at most 8), 1 = no split                     */
+                           tiles alone do not fill the device many times over); 0 =
+                           automatic (about ten device rounds, at most 16 splits, the state
+                           copies within 4 GB), 1 = no split                                */
 } uf_tuning;
 
 typedef struct {

@@ -152,16 +152,22 @@ Knobs resolve_knobs(const uf_tuning *t, uf_precision prec, int32_t n_branches)
     return k;
 }
 
-// Branch splits of the fused striped kernel: enough work-groups for about two full rounds
-// of the device (each split keeps its own copy of the stripe state, summed afterwards),
-// at most 8, and none when the stripe tiles alone fill the device twice over.
-int32_t auto_k_split(const uf_context *ctx, const StripeGeom &g, int64_t tiles, int32_t B, int32_t E)
+// Branch splits of the fused striped kernel: enough work-groups for about ten rounds of the
+// device, so that the work-groups that finish last hold a small part of the run (two rounds
+// left a measured 5 % behind), at most 16 splits, at least two batches per split, and the
+// copies of the stripe state within 4 GB.  No split when the stripe tiles alone give ten
+// rounds.
+int32_t auto_k_split(const uf_context *ctx, const StripeGeom &g, int64_t tiles, int32_t B, int32_t E,
+                     size_t state_bytes)
 {
     const int64_t slots = (int64_t)std::max(ctx->n_cu, 1) * std::max(g.occ, 1);
-    if (tiles <= 0 || tiles >= 2 * slots) return 1;
-    int64_t kz = (2 * slots + tiles - 1) / tiles;
-    kz = std::min<int64_t>(kz, 8);
+    constexpr int64_t kRounds = 10;
+    if (tiles <= 0 || tiles >= kRounds * slots) return 1;
+    int64_t kz = (kRounds * slots + tiles - 1) / tiles;
+    kz = std::min<int64_t>(kz, 16);
     kz = std::min<int64_t>(kz, std::max<int64_t>(1, B / std::max(2 * E, 1)));   // >= 2 batches each
+    const size_t budget = (size_t)4 << 30;
+    if (state_bytes > 0) kz = std::min<int64_t>(kz, std::max<int64_t>(1, (int64_t)(budget / state_bytes)));
     return (int32_t)std::max<int64_t>(kz, 1);
 }
 
@@ -192,7 +198,8 @@ uf_status run_striped(uf_plan *plan, uf_method method, uf_precision prec, const 
     const int64_t tiles = (int64_t)(g.sstride / g.tkw) * (tile_s1 - tile_s0);
     const int32_t kz = kn.variant != 0 ? 1
                        : kn.k_split > 0 ? std::min(kn.k_split, std::max(B, 1))
-                                        : auto_k_split(ctx, g, tiles, B, kn.emb_batch);
+                                        : auto_k_split(ctx, g, tiles, B, kn.emb_batch,
+                                                       kn.den_mode == 0 ? 2 * state : state);
     UF_TRY(plan->num.ensure(state * kz), "allocating numerator stripes");
     if (kn.den_mode == 0) UF_TRY(plan->den.ensure(state * kz), "allocating denominator stripes");
     UF_TRY(plan->D.ensure((size_t)hp.n_samples * sizeof(double)), "allocating per-sample sums");
