@@ -332,7 +332,9 @@ def bench_mfma(args):
     import torch
     import paper_2005_05826_amd as uf
     from synth import config_problem
-    compare = "" if args.compare in (None, "none") else args.compare
+    # the matrix-core path against plain FP64 striped (numerator and denominator stripes)
+    # on the same plan, unless --compare none
+    compare = "fp64" if args.compare is None else ("" if args.compare == "none" else args.compare)
     over = {k: v for k, v in (("n", args.n), ("tips", args.tips)) if v}
     t0 = time.time()
     prob = config_problem(3, **over)
@@ -367,9 +369,11 @@ def bench_mfma(args):
         add_traffic(res["roofline"], key, "k_mfma.hip", total_ms / launches)
     if compare:
         out2 = torch.empty_like(out)
-        dt2, prof2 = timed_runs(plan, "unweighted", compare, {}, out2, 1, 0, stream)
-        res["compare"] = {"precision": compare, "ms_per_step": round(dt2 * 1e3, 3),
-                          "value": round(updates / dt2, 1), "speedup_of_headline": round(dt2 / dt, 3)}
+        dt2, prof2 = timed_runs(plan, "unweighted", compare, dict(den_mode=0, tile=0), out2, 1, 0, stream)
+        log(f"compare {compare}: {dt2 * 1e3:.1f} ms")
+        res["compare"] = {"precision": compare, "den_mode": 0, "tile": 0, "ms_per_step": round(dt2 * 1e3, 3),
+                          "value": round(updates / dt2, 1), "speedup_of_headline": round(dt2 / dt, 3),
+                          "kernels_ms_per_step": {k: round(v[1], 3) for k, v in prof2.items()}}
     res["end_to_end"] = end_to_end(uf, ctx, prob, "unweighted", "mfma_bf16x2", tuning, stream, 1)
     log(f"end to end: {res['end_to_end']['ms']:.1f} ms")
     if not args.no_cpu:
