@@ -183,6 +183,12 @@ def oracle_sample(prob, method, seconds, seed, subset=None):
            "sample": f"{pi.size} seeded random pairs{where} ({method}, all {B} branches each), "
                      f"{cpu_s:.1f} s including walk-up counts of the touched samples",
            "seconds": round(cpu_s, 2)}
+    # the per-core rate: one thread on the first pairs of the sample, about two seconds
+    m1 = int(max(16, min(pi.size, pi.size * 2.0 / max(cpu_s * threads, 1e-3))))
+    t = time.perf_counter()
+    oracle.problem_pairs(prob, om, pi[:m1], pj[:m1], n_threads=1)
+    t1 = time.perf_counter() - t
+    cpu["one_thread"] = {"value": round(m1 * B / t1, 1), "pairs": m1, "seconds": round(t1, 2)}
     return cpu, pi, pj, want
 
 
