@@ -92,13 +92,15 @@ int uf_oracle_pairs(int32_t n_nodes, const int32_t *parent, const double *length
     if (method < 0 || method > 2) return OR_E_ARG;
     for (int64_t p = 0; p < n_pairs; ++p)
         if (a[p] < 0 || a[p] >= n_rows || b[p] < 0 || b[p] >= n_rows) return OR_E_ARG;
+    /* the thread count applies to this call only (a num_threads clause, not the
+     * process-wide default) */
 #ifdef _OPENMP
-    if (n_threads > 0) omp_set_num_threads(n_threads);
+    const int nt = n_threads > 0 ? n_threads : omp_get_max_threads();
 #else
     (void)n_threads;
 #endif
 
-#pragma omp parallel for schedule(dynamic, 64)
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nt)
     for (int64_t p = 0; p < n_pairs; ++p) {
         const int64_t *ci = rows + (int64_t)a[p] * n_nodes;
         const int64_t *cj = rows + (int64_t)b[p] * n_nodes;

@@ -24,7 +24,8 @@ struct uf_batch {
     std::vector<uf_job> jobs;
     int32_t emb_batch = 0, den_mode = 0, k_chunk = 4096, tile = 0, count_width = 0;
     int32_t mfma_variant = 0;             // uf_tuning.variant: matrix-core accumulation form
-    int32_t n_groups = 512;
+    int32_t n_groups = 512;   // persistent matrix-core work-groups (two per CU)
+    int32_t n_cus = 256;
     // propagation tables
     DevMem prop_jobs, scatter_tasks, level_tasks;
     std::vector<int32_t> level_ptr;       // per height level, range of level_tasks
@@ -91,13 +92,15 @@ uf_status enqueue(uf_batch *b, hipStream_t st)
     }
     for (int q = 0; q < uf_batch::kQueues; ++q) {
         if (b->n_stripe_items[q] == 0) continue;
+        // as many persistent work-groups as the tile shape keeps resident (2 or 3 per CU)
+        const int32_t groups = b->n_cus * stripe_geometry(256, (q & 4) == 0, b->den_mode, b->tile).occ;
         UF_TRY(timed(b->prof, "stripe", st, [&] {
                    return launch_stripe_queue((q & 4) == 0, (q & 2) ? UF_WEIGHTED_NORMALIZED : UF_UNWEIGHTED,
                                               (q & 1) ? 2 : 4, b->den_mode, b->tile,
                                               b->stripe_jobs[q].as<StripeArgs>(),
                                               b->stripe_items[q].as<int32_t>(), b->n_stripe_items[q],
                                               b->counters.as<int32_t>() + q,
-                                              std::min(b->n_groups, b->n_stripe_items[q]), st);
+                                              std::min(groups, b->n_stripe_items[q]), st);
                }), "queued striped accumulation");
     }
     for (int32_t j = 0; j < nj; ++j) {
@@ -161,7 +164,8 @@ uf_status build_tables(uf_batch *b, hipStream_t st)
     const int32_t nj = (int32_t)b->plans.size();
     int dev_cus = 256;
     (void)hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
-    b->n_groups = 2 * std::max(dev_cus, 1);
+    b->n_cus = std::max(dev_cus, 1);
+    b->n_groups = 2 * b->n_cus;
 
     // propagation tables and per-job scratch
     std::vector<PropJob> pj(nj);
