@@ -66,14 +66,14 @@ OPS_PER_UPDATE = {0: 4, 1: 2}   # den_mode 0: both stripes; 1: numerator only
 # it was measured on, and is reported as null once that source has changed.
 TRAFFIC = {
     "striped/4096x65534/fp32/den1/tile2/Edefault": {
-        "src_sha256": "7b92a5456d75ca39", "fetch": 47519944195, "write": 35188788672,
-        "bytes": 82708732867, "profile": "profiles/k_stripe_fused_wn_fp32_4096x65534.md"},
+        "src_sha256": "7ac7fdd242d76870", "fetch": 44192166645, "write": 34360248000,
+        "bytes": 78552414645, "profile": "profiles/k_stripe_fused_wn_fp32_4096x65534.md"},
     "mfma/25000x599998/k_chunk4096/variant0": {
         "src_sha256": "5d48aca7be669671", "fetch": 204218464352, "write": 102445921984,
         "bytes": 306664386336, "profile": "profiles/k_mfma_gemm_uw_25000x599998.md"},
     "hbm/25000x16382/fp64/den0/tile0/E8": {
-        "src_sha256": "7b92a5456d75ca39", "fetch": 2187933086222, "write": 2230224268416,
-        "bytes": 4418157354638, "profile": "profiles/k_stripe_fused_hbm_regime_fp64_25000x16382.md"},
+        "src_sha256": "7ac7fdd242d76870", "fetch": 2180796671129, "write": 2228479093760,
+        "bytes": 4409275764889, "profile": "profiles/k_stripe_fused_hbm_regime_fp64_25000x16382.md"},
 }
 
 

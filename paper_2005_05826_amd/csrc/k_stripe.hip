@@ -27,7 +27,8 @@ constexpr int kBlock = 256;  // 4 waves: wave w owns stripes [w*TST, (w+1)*TST) 
 template <typename T, int DEN, int TILE>
 struct StripeCfg;
 // EB: most branches per LDS stage.  OCC: work-groups per CU the fused and queued kernels
-// are compiled for (tile 2 trades a smaller tile for three waves per SIMD).
+// are compiled for (tile 2 trades a smaller tile for three or four waves per SIMD; the FP32
+// 4 x 16 shape takes shorter stages so that its staging registers fit four).
 template <> struct StripeCfg<double, 0, 0> { static constexpr int TKT = 4, TST = 8, EB = 8, OCC = 2; };
 template <> struct StripeCfg<double, 0, 1> { static constexpr int TKT = 2, TST = 12, EB = 8, OCC = 2; };
 template <> struct StripeCfg<double, 0, 2> { static constexpr int TKT = 2, TST = 8, EB = 8, OCC = 3; };
@@ -39,7 +40,7 @@ template <> struct StripeCfg<float, 0, 1> { static constexpr int TKT = 8, TST = 
 template <> struct StripeCfg<float, 0, 2> { static constexpr int TKT = 4, TST = 8, EB = 8, OCC = 3; };
 template <> struct StripeCfg<float, 1, 0> { static constexpr int TKT = 4, TST = 24, EB = 8, OCC = 2; };
 template <> struct StripeCfg<float, 1, 1> { static constexpr int TKT = 8, TST = 16, EB = 8, OCC = 2; };
-template <> struct StripeCfg<float, 1, 2> { static constexpr int TKT = 4, TST = 16, EB = 8, OCC = 3; };
+template <> struct StripeCfg<float, 1, 2> { static constexpr int TKT = 4, TST = 16, EB = 6, OCC = 4; };
 
 // Pins a register value at this point of the program: the conversions that follow cannot
 // be hoisted above it, which keeps the FP64 copies of a tile from being live all at once.
