@@ -120,7 +120,7 @@ def test_tile_shapes_match_oracle(uf, ctx, problems, method, prec, den_mode, til
         assert err.max() <= TOL[prec]
 
 
-@pytest.mark.parametrize("k_split", [1, 2, 5, 0])
+@pytest.mark.parametrize("k_split", [1, 2, 5, 16, 0])
 @pytest.mark.parametrize("den_mode", [0, 1])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_branch_splits_match_oracle(uf, ctx, problems, prec, den_mode, k_split):
@@ -135,7 +135,7 @@ def test_branch_splits_match_oracle(uf, ctx, problems, prec, den_mode, k_split):
         assert err.max() <= TOL[prec]
 
 
-@pytest.mark.parametrize("k_split", [3, 8])
+@pytest.mark.parametrize("k_split", [3, 8, 16])
 def test_branch_splits_dyadic_bit_identical(uf, ctx, k_split):
     prob = config_problem(1, n=300, tips=600, p_nonzero=0.3, depth=256, dyadic=True, seed=91)
     plan = _plan(uf, ctx, prob)
