@@ -122,7 +122,9 @@ typedef struct {
                            stripes), 0, 1 or 2; den_mode 0: FP64 4x8 | 2x12 | 2x8,
                            FP32 4x16 | 8x8 | 4x8; den_mode 1: FP64 4x16 | 2x24 | 4x8,
                            FP32 4x24 | 8x16 | 4x16; shape 2 runs three work-groups per CU
-                           (four for FP32 4x16; the others two)                              */
+                           (four for FP32 4x16; the others two).  A NULL tuning selects
+                           shape 2 (fastest measured for den_mode 0); a zero field here
+                           means shape 0                                                     */
     int32_t count_width; /* striped path: bytes per embedding count; 0 = 2 when every sample
                            total fits in 16 bits (halves count memory and traffic), else 4;
                            4 = int32; 2 = uint16 (UF_E_ARG if a total exceeds 65535)         */

@@ -146,7 +146,9 @@ Knobs resolve_knobs(const uf_tuning *t, uf_precision prec, int32_t n_branches)
     k.k_chunk = (t && t->k_chunk > 0) ? t->k_chunk : 4096;
     k.den_mode = (t ? t->den_mode : 0);
     k.variant = (t ? t->variant : 0);
-    k.tile = (t ? t->tile : 0);
+    // without knobs, tile shape 2: the fastest measured for the default den_mode 0 in both
+    // precisions (and for the FP32 per-sample denominator form)
+    k.tile = (t ? t->tile : 2);
     k.count_width = (t ? t->count_width : 0);
     k.k_split = (t ? t->k_split : 0);
     return k;

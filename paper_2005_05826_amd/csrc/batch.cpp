@@ -345,6 +345,7 @@ uf_status uf_batch_create(uf_context *ctx, const uf_job *jobs, int32_t n_jobs,
     uf_batch *b = new (std::nothrow) uf_batch;
     if (!b) return set_err(ctx, UF_E_OOM, "host allocation failed");
     b->ctx = ctx;
+    b->tile = 2;   // without knobs, the fastest measured shape for den_mode 0
     if (tuning) {
         b->emb_batch = tuning->emb_batch;
         b->den_mode = tuning->den_mode;
