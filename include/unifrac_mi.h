@@ -235,10 +235,10 @@ uf_status uf_plan_get_profile(uf_plan *plan, uf_kernel_stat *out, int32_t cap, i
 
 /* Autotuner for the grouping parameters (Section 3: tile and batch sizes decide the run
  * time).  Times candidate settings of `prec` on this plan's resident inputs with HIP events
- * (one warm-up, then `reps` calls each; reps <= 0 means 3): striped paths try both tile
- * shapes with three embedding-batch depths each (FP32 depths stay <= 256 to bound the
- * FP32 in-batch error), the matrix-core path tries k_chunk 4096, 2048, 1024.  den_mode is
- * taken from `base` (NULL = 0).  A candidate whose output differs from the first
+ * (one warm-up, then `reps` calls each; reps <= 0 means 3): striped paths try the three
+ * tile shapes with embedding-batch depths 128, 64, 256 and 512 (FP32) or 1024, 256 and 4096
+ * (FP64) each; the matrix-core path tries variants 0 and 1 with k_chunk 4096 and 16384.
+ * den_mode is taken from `base` (NULL = 0).  A candidate whose output differs from the first
  * candidate's by more than the path's tolerance (FP64 1e-12, else 1e-5) is rejected.  The
  * winner goes to *best (and its milliseconds per call to *best_ms if non-NULL).  With a
  * non-NULL cache_path the winner is appended to that text file under a key of device

@@ -93,8 +93,10 @@ extern "C" uf_status uf_autotune(uf_plan *plan, uf_method method, uf_precision p
         for (int32_t v : {0, 1})
             for (int32_t kc : {4096, 16384}) cands.push_back(uf_tuning{0, kc, 0, v, 0, 0});
     } else {
-        // FP32 sums inside a batch carry ~E * 2^-24 relative error, so FP32 batches stay <= 256
-        const std::vector<int32_t> Es = prec == UF_PREC_FP32 ? std::vector<int32_t>{128, 64, 256}
+        // FP32 sums inside a batch carry up to ~E * 2^-24 relative error: deeper FP32 batches
+        // are candidates too, and win only if their output stays within the tolerance of the
+        // first (E = 128) candidate
+        const std::vector<int32_t> Es = prec == UF_PREC_FP32 ? std::vector<int32_t>{128, 64, 256, 512}
                                                              : std::vector<int32_t>{1024, 256, 4096};
         for (int32_t tile : {0, 1, 2})
             for (int32_t E : Es) cands.push_back(uf_tuning{E, 0, den_mode, 0, tile});
