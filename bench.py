@@ -11,23 +11,27 @@ Workloads (--workload):
                      ~800 features per sample, NegBin(10, 0.3) counts rarefied to 5,000;
                      weighted normalized.  Headline: the FP32 path with the denominator
                      from per-sample sums (den_mode 1) on tile shape 2; timed beside it on
-                     the same inputs: plain FP64 (numerator and denominator stripes) and
-                     FP32 in that same numerator-and-denominator form.
+                     the same inputs: plain FP64 (numerator and denominator stripes), FP32
+                     in that same numerator-and-denominator form, and FP64 with the
+                     per-sample denominator.
   mfma               25,000 samples, 300,000-tip random binary tree, 1,500 Zipf(1.1)
-                     presences per sample; unweighted on bf16 matrix cores (hi+lo split).
-                     --compare fp64 also times the FP64 striped form (about 20 s a step).
+                     presences per sample; unweighted on bf16 matrix cores (hi+lo split),
+                     timed beside plain FP64 striped (about 28 s a step; --compare none
+                     skips it).
   batch              64 jobs (samples uniform in 200..8,000, tips uniform in 1,000..64,000,
-                     workload-1 distributions), each run weighted normalized (FP32 striped)
+                     distributions of the 256-sample binary-tree case), each run weighted
+                     normalized (FP32 striped)
                      and unweighted (matrix core): 128 jobs in one batch, replayed as a
                      captured HIP graph.
   large-uw           113,000 samples, 500,000-tip random binary tree: the full unweighted
                      matrix on the matrix cores.
   large-wn           the same inputs, weighted normalized FP32 striped: one GPU's share (a
-                     contiguous 1/--share of the stripes) of a split of the full matrix.
+                     contiguous 1/--share of the stripes) of a split of the full matrix, or
+                     with --all-shares every share in turn (the full matrix).
   hbm                the striped kernel in its memory-bound regime: FP64 numerator and
                      denominator stripes, E = 8 branches per batch, on a 1 GB stripe state
-                     (stripes [0, 2,560) of 25,000 samples; workload-2 distributions on an
-                     8,192-tip coalescent tree), so each batch streams 2 GB of state through
+                     (stripes [0, 2,560) of 25,000 samples; the distributions of the
+                     striped workload on an 8,192-tip coalescent tree), so each batch streams 2 GB of state through
                      HBM; reported against the HBM roof.
 
 The oracle (FP64 CPU) is timed on the host cores on a seeded sample of pairs as the CPU
@@ -247,7 +251,7 @@ def base_record(args, value, dt, dtype, config):
 def bench_striped(args):
     import torch
     import paper_2005_05826_amd as uf
-    from synth import config_problem
+    from synth import workload_problem
     method = args.method or "weighted_normalized"
     prec = args.precision or "fp32"
     compare = "fp64" if args.compare is None else args.compare
@@ -255,7 +259,7 @@ def bench_striped(args):
         compare = ""
     over = {k: v for k, v in (("n", args.n), ("tips", args.tips)) if v}
     t0 = time.time()
-    prob = config_problem(2, **over)
+    prob = workload_problem("coalescent_4096", **over)
     log(f"generated in {time.time() - t0:.1f}s: n={prob.n_samples} nodes={prob.n_nodes} nnz={prob.indices.size}")
     n, B = prob.n_samples, prob.n_nodes - 1
     n_pairs = n * (n - 1) // 2
@@ -341,13 +345,13 @@ def bench_striped(args):
 def bench_mfma(args):
     import torch
     import paper_2005_05826_amd as uf
-    from synth import config_problem
+    from synth import workload_problem
     # the matrix-core path against plain FP64 striped (numerator and denominator stripes)
     # on the same plan, unless --compare none
     compare = "fp64" if args.compare is None else ("" if args.compare == "none" else args.compare)
     over = {k: v for k, v in (("n", args.n), ("tips", args.tips)) if v}
     t0 = time.time()
-    prob = config_problem(3, **over)
+    prob = workload_problem("zipf_25000", **over)
     log(f"generated in {time.time() - t0:.1f}s: n={prob.n_samples} nodes={prob.n_nodes}")
     n, B = prob.n_samples, prob.n_nodes - 1
     n_pairs = n * (n - 1) // 2
@@ -477,7 +481,7 @@ def bench_batch(args):
 
 
 def bench_large(args, part):
-    """Workload 5 (113,000 samples, 500,000-tip random binary tree, ~1,000 features per
+    """The 113,000-sample workload (500,000-tip random binary tree, ~1,000 features per
     sample, NegBin(8, 0.3) rarefied to 2,000).  large-uw: the full unweighted matrix on the
     matrix cores (presence bits 14 GB, FP64 shared lengths in the output).  large-wn: one
     GPU's share of an N-way split of the weighted normalized FP32 striped computation, a
@@ -485,10 +489,10 @@ def bench_large(args, part):
     the condensed output (FP32, 25.5 GB) stays resident."""
     import torch
     import paper_2005_05826_amd as uf
-    from synth import config_problem
+    from synth import workload_problem
     over = {k: v for k, v in (("n", args.n), ("tips", args.tips)) if v}
     t0 = time.time()
-    prob = config_problem(5, **over)
+    prob = workload_problem("binary_113000", **over)
     log(f"generated in {time.time() - t0:.1f}s: n={prob.n_samples} nodes={prob.n_nodes} nnz={prob.indices.size}")
     n, B = prob.n_samples, prob.n_nodes - 1
     n_pairs = n * (n - 1) // 2
@@ -577,9 +581,9 @@ def bench_large(args, part):
 def bench_hbm(args):
     import torch
     import paper_2005_05826_amd as uf
-    from synth import config_problem
+    from synth import workload_problem
     n = args.n or 25000
-    prob = config_problem(2, n=n, tips=args.tips or 8192, k=800, seed=20050526 + 7)
+    prob = workload_problem("coalescent_4096", n=n, tips=args.tips or 8192, k=800, seed=20050526 + 7)
     n, B = prob.n_samples, prob.n_nodes - 1
     s0, s1 = 0, 2560
     E = args.emb_batch or 8

@@ -17,9 +17,9 @@ from .generators import (  # noqa: F401
     table_sparse_nb,
     table_fixed_nb,
     table_zipf_presence,
-    config_problem,
+    workload_problem,
     batch_job_specs,
-    CONFIGS,
+    WORKLOADS,
     build_job,
     permutations,
 )

@@ -260,25 +260,26 @@ def table_zipf_presence(n_samples: int, n_features: int, k_per_sample: int, zipf
     return _to_csr(rows_idx, rows_cnt)
 
 
-# ----------------------------------------------------------------------------- configs
+# ----------------------------------------------------------------------------- workloads
 
-CONFIGS = {
+# Named synthetic workloads; seed_offset fixes each one's default seed (MASTER_SEED + offset).
+WORKLOADS = {
     # 256 samples, random binary tree with 2,048 tips, Exp(0.05) lengths, 95 % zeros,
     # ZTNB(20, 0.5) counts rarefied to 1,000; FP64 unweighted + weighted normalized.
-    1: dict(n=256, tips=2048, tree="binary", mean_len=0.05, table="sparse_nb",
-            p_nonzero=0.05, nb_mean=20.0, nb_alpha=0.5, depth=1000),
+    "binary_256": dict(n=256, tips=2048, tree="binary", mean_len=0.05, table="sparse_nb",
+                       p_nonzero=0.05, nb_mean=20.0, nb_alpha=0.5, depth=1000, seed_offset=1),
     # 4,096 samples, coalescent tree with 32,768 tips, ~800 features/sample, ZTNB(10, 0.3)
     # rarefied to 5,000; weighted normalized, FP64 vs FP32.
-    2: dict(n=4096, tips=32768, tree="coalescent", mean_len=0.05, table="fixed_nb",
-            k=800, nb_mean=10.0, nb_alpha=0.3, depth=5000),
+    "coalescent_4096": dict(n=4096, tips=32768, tree="coalescent", mean_len=0.05, table="fixed_nb",
+                            k=800, nb_mean=10.0, nb_alpha=0.3, depth=5000, seed_offset=2),
     # 25,000 samples, random binary tree with 300,000 tips, Exp(0.02), 1,500 present
     # features/sample with Zipf(1.1) prevalence; unweighted (MFMA vs FP64 striped).
-    3: dict(n=25000, tips=300000, tree="binary", mean_len=0.02, table="zipf_presence",
-            k=1500, zipf_s=1.1),
+    "zipf_25000": dict(n=25000, tips=300000, tree="binary", mean_len=0.02, table="zipf_presence",
+                       k=1500, zipf_s=1.1, seed_offset=3),
     # 113,000 samples, random binary tree with 500,000 tips, ~1,000 features/sample,
     # ZTNB(8, 0.3) rarefied to 2,000.
-    5: dict(n=113000, tips=500000, tree="binary", mean_len=0.02, table="fixed_nb",
-            k=1000, nb_mean=8.0, nb_alpha=0.3, depth=2000),
+    "binary_113000": dict(n=113000, tips=500000, tree="binary", mean_len=0.02, table="fixed_nb",
+                          k=1000, nb_mean=8.0, nb_alpha=0.3, depth=2000, seed_offset=5),
 }
 
 
@@ -311,22 +312,22 @@ def _build(spec: dict, rng: np.random.Generator) -> Problem:
                    meta=dict(spec))
 
 
-def config_problem(cfg: int, seed: int | None = None, **overrides) -> Problem:
-    """The synthetic problem of workload `cfg` (1, 2, 3 or 5), optionally with fields
-    overridden (e.g. n=300, tips=3000 for a scaled-down case of the same kind)."""
-    spec = dict(CONFIGS[cfg])
+def workload_problem(name: str, seed: int | None = None, **overrides) -> Problem:
+    """The synthetic problem of the named workload, optionally with fields overridden (e.g.
+    n=300, tips=3000 for a scaled-down case of the same kind)."""
+    spec = dict(WORKLOADS[name])
     spec.update(overrides)
     if seed is None:
-        seed = MASTER_SEED + cfg
+        seed = MASTER_SEED + spec["seed_offset"]
     spec["seed"] = int(seed)
-    spec["config"] = cfg
+    spec["workload"] = name
     return _build(spec, make_rng(seed))
 
 
 def batch_job_specs(n_jobs: int = 64, seed: int | None = None, n_range=(200, 8000),
                     tips_range=(1000, 64000)) -> list[dict]:
     """Specs of the uneven batch: n ~ U{n_range}, tips ~ U{tips_range}, everything else as
-    workload 1.  Job j is generated from seed + 1000*j."""
+    the 256-sample binary-tree workload.  Job j is generated from seed + 1000*j."""
     if seed is None:
         seed = MASTER_SEED + 4
     rng = make_rng(seed)
@@ -334,7 +335,7 @@ def batch_job_specs(n_jobs: int = 64, seed: int | None = None, n_range=(200, 800
     ts = rng.integers(tips_range[0], tips_range[1] + 1, size=n_jobs)
     specs = []
     for j in range(n_jobs):
-        spec = dict(CONFIGS[1])
+        spec = dict(WORKLOADS["binary_256"])
         spec.update(n=int(ns[j]), tips=int(ts[j]), seed=int(seed + 1000 * (j + 1)), job=j)
         specs.append(spec)
     return specs

@@ -11,7 +11,7 @@ import pytest
 
 import paper_2005_05826_amd as uf
 from paper_2005_05826_amd import binding
-from synth import config_problem
+from synth import workload_problem
 
 from helpers import tiny_problem
 
@@ -82,7 +82,7 @@ def _status(**kw):
 def test_valid_inputs_pass():
     p = _prob()
     assert _status(**_args(p))[0] == "UF_OK"
-    assert uf.validate_problem(config_problem(1, n=16))[0] == 0
+    assert uf.validate_problem(workload_problem("binary_256", n=16))[0] == 0
 
 
 def test_tree_errors():

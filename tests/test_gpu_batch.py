@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from oracle import oracle
-from synth import batch_job_specs, build_job, config_problem
+from synth import batch_job_specs, build_job, workload_problem
 
 pytestmark = pytest.mark.gpu
 
@@ -35,7 +35,7 @@ def _jobs():
         spec["p_nonzero"] = 0.2
         spec["depth"] = 200      # small trees: keep the rarefaction depth reachable
         probs.append((build_job(spec), m, p))
-    probs.append((config_problem(1, n=1, tips=50, p_nonzero=0.5, depth=200, seed=3), "weighted_normalized", "fp32"))
+    probs.append((workload_problem("binary_256", n=1, tips=50, p_nonzero=0.5, depth=200, seed=3), "weighted_normalized", "fp32"))
     return probs
 
 
@@ -128,7 +128,7 @@ def test_batch_errors(uf, ctx, jobs):
     with pytest.raises(uf.UniFracError) as ei:
         uf.Batch(ctx, [dict(problem=p, method="weighted_normalized", precision="mfma_bf16x2", out=out)])
     assert ei.value.status_name == "UF_E_UNSUPPORTED"
-    bad = config_problem(1, n=5, tips=40, p_nonzero=0.5, depth=200, seed=8)
+    bad = workload_problem("binary_256", n=5, tips=40, p_nonzero=0.5, depth=200, seed=8)
     bad.parent = bad.parent.copy()
     bad.parent[0] = bad.parent.shape[0] + 5
     with pytest.raises(uf.UniFracError) as ei:
@@ -140,7 +140,7 @@ def test_batch_errors(uf, ctx, jobs):
 @pytest.mark.parametrize("method,prec", [("weighted_normalized", "fp32"), ("unweighted", "mfma_bf16x2"),
                                          ("unweighted", "fp64")])
 def test_autotune_picks_valid_knobs_and_caches(uf, ctx, tmp_path, method, prec):
-    prob = config_problem(2, n=700, tips=4000, k=300, depth=1500, seed=77)
+    prob = workload_problem("coalescent_4096", n=700, tips=4000, k=300, depth=1500, seed=77)
     plan = uf.Plan.from_problem(ctx, prob)
     cache = tmp_path / "tune.txt"
     best, ms = plan.autotune(method, prec, reps=2, cache_path=cache)

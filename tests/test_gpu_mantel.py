@@ -6,7 +6,7 @@ import pytest
 
 from oracle import mantel as M
 from oracle import oracle
-from synth import config_problem, permutations
+from synth import workload_problem, permutations
 
 pytestmark = pytest.mark.gpu
 
@@ -24,7 +24,7 @@ def ctx(uf):
 
 def test_mantel_matches_numpy(uf, ctx):
     import torch
-    prob = config_problem(1, n=120, tips=800, p_nonzero=0.2, seed=31)
+    prob = workload_problem("binary_256", n=120, tips=800, p_nonzero=0.2, seed=31)
     plan = uf.Plan.from_problem(ctx, prob)
     n = prob.n_samples
     x = plan.distance("weighted_normalized", "fp64")

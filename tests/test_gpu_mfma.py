@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 from oracle import oracle
-from synth import Problem, config_problem, make_rng
+from synth import Problem, workload_problem, make_rng
 
 from helpers import condensed_index, tiny_problem
 
@@ -37,11 +37,11 @@ def _report(tag, got, want):
 
 CASES = {
     "tiny": lambda: tiny_problem(41, max_nodes=30, max_samples=8),
-    "cfg1": lambda: config_problem(1),
-    "n129": lambda: config_problem(1, n=129, tips=700, p_nonzero=0.2, seed=61),
-    "n300": lambda: config_problem(1, n=300, tips=3000, seed=62),
-    "cfg3_shape": lambda: config_problem(3, n=600, tips=8000, k=400, seed=63),
-    "cfg2_shape": lambda: config_problem(2, n=513, tips=3000, k=200, depth=1000, seed=64),
+    "binary_256": lambda: workload_problem("binary_256"),
+    "n129": lambda: workload_problem("binary_256", n=129, tips=700, p_nonzero=0.2, seed=61),
+    "n300": lambda: workload_problem("binary_256", n=300, tips=3000, seed=62),
+    "zipf_600": lambda: workload_problem("zipf_25000", n=600, tips=8000, k=400, seed=63),
+    "coalescent_513": lambda: workload_problem("coalescent_4096", n=513, tips=3000, k=200, depth=1000, seed=64),
 }
 
 
@@ -63,7 +63,7 @@ def test_mfma_matches_oracle(uf, ctx, problems, case):
 @pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("k_chunk", [64, 512, 4096, 16384])
 def test_mfma_k_chunk(uf, ctx, problems, k_chunk, variant):
-    prob = problems["cfg3_shape"]
+    prob = problems["zipf_600"]
     plan = uf.Plan.from_problem(ctx, prob)
     got = plan.distance(UW, MF, tuning=dict(k_chunk=k_chunk, variant=variant))
     want = oracle.problem_condensed(prob, oracle.UNWEIGHTED)
@@ -74,7 +74,7 @@ def test_mfma_k_chunk(uf, ctx, problems, k_chunk, variant):
 @pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("n", [2, 3, 127, 128, 257])
 def test_mfma_dyadic_bit_identical(uf, ctx, n, variant):
-    prob = config_problem(1, n=n, tips=500, p_nonzero=0.3, dyadic=True, depth=256, seed=200 + n)
+    prob = workload_problem("binary_256", n=n, tips=500, p_nonzero=0.3, dyadic=True, depth=256, seed=200 + n)
     plan = uf.Plan.from_problem(ctx, prob)
     got = plan.distance(UW, MF, tuning=dict(variant=variant))
     want = oracle.problem_condensed(prob, oracle.UNWEIGHTED)
@@ -82,7 +82,7 @@ def test_mfma_dyadic_bit_identical(uf, ctx, n, variant):
 
 
 def test_mfma_identical_samples_exact_zero(uf, ctx):
-    base = config_problem(1, n=200, tips=1500, seed=7)
+    base = workload_problem("binary_256", n=200, tips=1500, seed=7)
     rows = [(base.indices[base.indptr[k]:base.indptr[k + 1]], base.counts[base.indptr[k]:base.indptr[k + 1]])
             for k in list(range(base.n_samples)) + [3, 150]]
     indptr = np.zeros(len(rows) + 1, np.int64)
@@ -111,7 +111,7 @@ def test_mfma_f32_output_and_single_node(uf, ctx, problems):
 
 
 def test_mfma_matches_striped_fp64(uf, ctx, problems):
-    prob = problems["cfg3_shape"]
+    prob = problems["zipf_600"]
     plan = uf.Plan.from_problem(ctx, prob)
     a = plan.distance(UW, MF)
     b = plan.distance(UW, "fp64")
@@ -119,21 +119,21 @@ def test_mfma_matches_striped_fp64(uf, ctx, problems):
 
 
 def test_mfma_deterministic(uf, ctx, problems):
-    plan = uf.Plan.from_problem(ctx, problems["cfg3_shape"])
+    plan = uf.Plan.from_problem(ctx, problems["zipf_600"])
     np.testing.assert_array_equal(plan.distance(UW, MF), plan.distance(UW, MF))
 
 
 @pytest.fixture(scope="module")
-def cfg3():
-    return config_problem(3)
+def zipf_25000():
+    return workload_problem("zipf_25000")
 
 
-def test_workload3_full_size_sampled(uf, ctx, cfg3):
+def test_zipf_25000_full_size_sampled(uf, ctx, zipf_25000):
     """25,000 samples on a 300,000-tip tree, default k_chunk 4,096: all outputs in [0, 1],
     a seeded sample of pairs among 160 random samples checked against the oracle."""
     import torch
-    plan = uf.Plan.from_problem(ctx, cfg3)
-    n = cfg3.n_samples
+    plan = uf.Plan.from_problem(ctx, zipf_25000)
+    n = zipf_25000.n_samples
     out = torch.empty(n * (n - 1) // 2, dtype=torch.float64, device="cuda:0")
     plan.distance(UW, MF, out=out)
     torch.cuda.synchronize()
@@ -145,7 +145,7 @@ def test_workload3_full_size_sampled(uf, ctx, cfg3):
     keep = a != b
     pi = np.minimum(subset[a[keep]], subset[b[keep]])
     pj = np.maximum(subset[a[keep]], subset[b[keep]])
-    want = oracle.problem_pairs(cfg3, oracle.UNWEIGHTED, pi, pj)
+    want = oracle.problem_pairs(zipf_25000, oracle.UNWEIGHTED, pi, pj)
     got = out[torch.from_numpy(condensed_index(n, pi, pj)).to("cuda:0")].cpu().numpy()
-    err = _report("workload3 mfma sampled", got, want)
+    err = _report("zipf_25000 mfma sampled", got, want)
     assert err.max() <= 1e-5

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 from oracle import oracle
-from synth import Problem, config_problem, make_rng
+from synth import Problem, workload_problem, make_rng
 
 from helpers import condensed_index, tiny_problem
 
@@ -44,10 +44,10 @@ def _report(tag, got, want):
 CASES = {
     "tiny_a": lambda: tiny_problem(31, max_nodes=16, max_samples=6),
     "tiny_b": lambda: tiny_problem(32, max_nodes=40, max_samples=9),
-    "cfg1": lambda: config_problem(1),
-    "cfg1_ragged_257": lambda: config_problem(1, n=257, seed=71),
-    "cfg2_shape_600": lambda: config_problem(2, n=600, tips=4000, k=300, depth=1500, seed=72),
-    "cfg2_shape_513": lambda: config_problem(2, n=513, tips=3000, k=200, depth=1000, seed=73),
+    "binary_256": lambda: workload_problem("binary_256"),
+    "binary_ragged_257": lambda: workload_problem("binary_256", n=257, seed=71),
+    "coalescent_600": lambda: workload_problem("coalescent_4096", n=600, tips=4000, k=300, depth=1500, seed=72),
+    "coalescent_513": lambda: workload_problem("coalescent_4096", n=513, tips=3000, k=200, depth=1000, seed=73),
 }
 
 
@@ -97,7 +97,7 @@ def test_distance_matches_oracle(uf, ctx, problems, case, method, prec):
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("method", [UW, WN])
 def test_separable_denominator(uf, ctx, problems, method, prec):
-    prob = problems["cfg2_shape_600"]
+    prob = problems["coalescent_600"]
     plan = _plan(uf, ctx, prob)
     got = plan.distance(method, prec, tuning=dict(den_mode=1))
     want = oracle.problem_condensed(prob, OMETHOD[method])
@@ -111,7 +111,7 @@ def test_separable_denominator(uf, ctx, problems, method, prec):
 @pytest.mark.parametrize("method", [UW, WN])
 def test_tile_shapes_match_oracle(uf, ctx, problems, method, prec, den_mode, tile):
     # every per-lane tile shape, on a ragged size and on one spanning several tiles
-    for case in ("cfg1_ragged_257", "cfg2_shape_600"):
+    for case in ("binary_ragged_257", "coalescent_600"):
         prob = problems[case]
         plan = _plan(uf, ctx, prob)
         got = plan.distance(method, prec, tuning=dict(den_mode=den_mode, tile=tile))
@@ -126,7 +126,7 @@ def test_tile_shapes_match_oracle(uf, ctx, problems, method, prec, den_mode, til
 def test_branch_splits_match_oracle(uf, ctx, problems, prec, den_mode, k_split):
     # the fused kernel's branch splits (separate state copies summed in order), explicit and
     # automatic, on both methods
-    prob = problems["cfg2_shape_600"]
+    prob = problems["coalescent_600"]
     plan = _plan(uf, ctx, prob)
     for method in (UW, WN):
         got = plan.distance(method, prec, tuning=dict(den_mode=den_mode, tile=2, k_split=k_split, emb_batch=64))
@@ -137,7 +137,7 @@ def test_branch_splits_match_oracle(uf, ctx, problems, prec, den_mode, k_split):
 
 @pytest.mark.parametrize("k_split", [3, 8, 16])
 def test_branch_splits_dyadic_bit_identical(uf, ctx, k_split):
-    prob = config_problem(1, n=300, tips=600, p_nonzero=0.3, depth=256, dyadic=True, seed=91)
+    prob = workload_problem("binary_256", n=300, tips=600, p_nonzero=0.3, depth=256, dyadic=True, seed=91)
     plan = _plan(uf, ctx, prob)
     for method in (UW, WN):
         for prec in ("fp64", "fp32"):
@@ -147,7 +147,7 @@ def test_branch_splits_dyadic_bit_identical(uf, ctx, k_split):
 
 def test_branch_splits_stripe_range(uf, ctx, problems):
     # a stripe range computed with splits equals the same pairs of the full matrix
-    prob = problems["cfg2_shape_600"]
+    prob = problems["coalescent_600"]
     plan = _plan(uf, ctx, prob)
     full = plan.distance(WN, "fp64", tuning=dict(k_split=1))
     n = prob.n_samples
@@ -164,7 +164,7 @@ def test_branch_splits_stripe_range(uf, ctx, problems):
 def test_dyadic_inputs_bit_identical(uf, ctx, method, prec, emb_batch):
     # lengths m/256 and rarefaction depth 256: every product and every partial sum of a
     # batch is exactly representable, so all paths must equal the oracle bit for bit
-    prob = config_problem(1, n=300, tips=600, p_nonzero=0.3, depth=256, dyadic=True, seed=90)
+    prob = workload_problem("binary_256", n=300, tips=600, p_nonzero=0.3, depth=256, dyadic=True, seed=90)
     plan = _plan(uf, ctx, prob)
     got = plan.distance(method, prec, tuning=dict(emb_batch=emb_batch))
     want = oracle.problem_condensed(prob, OMETHOD[method])
@@ -173,7 +173,7 @@ def test_dyadic_inputs_bit_identical(uf, ctx, method, prec, emb_batch):
 
 @pytest.mark.parametrize("n", [2, 3, 4, 5, 64, 255, 256])
 def test_stripe_layout(uf, ctx, n):
-    prob = config_problem(1, n=n, tips=300, p_nonzero=0.3, seed=100 + n)
+    prob = workload_problem("binary_256", n=n, tips=300, p_nonzero=0.3, seed=100 + n)
     plan = _plan(uf, ctx, prob)
     for method in (UW, WN):
         num, den = plan.stripes(method, "fp64")
@@ -229,7 +229,7 @@ def test_one_sample_has_no_pairs(uf, ctx):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_identical_samples_give_exact_zero(uf, ctx, prec):
-    base = config_problem(1, n=50, tips=400, p_nonzero=0.3, seed=5)
+    base = workload_problem("binary_256", n=50, tips=400, p_nonzero=0.3, seed=5)
     # append copies of samples 0 and 7
     rows = [(base.indices[base.indptr[k]:base.indptr[k + 1]], base.counts[base.indptr[k]:base.indptr[k + 1]])
             for k in list(range(base.n_samples)) + [0, 7]]
@@ -247,7 +247,7 @@ def test_identical_samples_give_exact_zero(uf, ctx, prec):
 
 
 def test_deterministic_runs(uf, ctx, problems):
-    plan = _plan(uf, ctx, problems["cfg2_shape_600"])
+    plan = _plan(uf, ctx, problems["coalescent_600"])
     for prec in ("fp64", "fp32"):
         a = plan.distance(WN, prec)
         b = plan.distance(WN, prec)
@@ -256,7 +256,7 @@ def test_deterministic_runs(uf, ctx, problems):
 
 def test_f32_output_and_device_output(uf, ctx, problems):
     import torch
-    prob = problems["cfg1_ragged_257"]
+    prob = problems["binary_ragged_257"]
     plan = _plan(uf, ctx, prob)
     want = oracle.problem_condensed(prob, oracle.WEIGHTED_NORMALIZED)
     got32 = plan.distance(WN, "fp64", out_dtype="f32")
@@ -293,34 +293,34 @@ def _sampled_pairs(n, n_random, first, seed):
 
 
 @pytest.fixture(scope="module")
-def cfg2():
-    return config_problem(2)
+def coalescent_4096():
+    return workload_problem("coalescent_4096")
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("tuning", [{}, dict(den_mode=1, tile=2)], ids=["default", "bench_headline"])
-def test_workload2_full_size_sampled(uf, ctx, cfg2, prec, tuning):
+def test_coalescent_4096_full_size_sampled(uf, ctx, coalescent_4096, prec, tuning):
     """The benchmark workload (4,096 samples, 32,768-tip coalescent tree), with the default
     knobs and with the configuration the benchmark times (separable denominator, tile shape
     2, automatic branch splits): every output checked for range, a seeded sample of pairs
     checked against the oracle."""
     import torch
-    plan = _plan(uf, ctx, cfg2)
-    n = cfg2.n_samples
+    plan = _plan(uf, ctx, coalescent_4096)
+    n = coalescent_4096.n_samples
     out = torch.empty(n * (n - 1) // 2, dtype=torch.float64, device="cuda:0")
     plan.distance(WN, prec, out=out, tuning=tuning)
     torch.cuda.synchronize()
     got = out.cpu().numpy()
     assert np.all(got >= 0) and np.all(got <= 1)
     pi, pj = _sampled_pairs(n, 1500, 48, seed=11)
-    want = oracle.problem_pairs(cfg2, oracle.WEIGHTED_NORMALIZED, pi, pj)
-    err = _report(f"workload2 WN {prec} {tuning} sampled", got[condensed_index(n, pi, pj)], want)
+    want = oracle.problem_pairs(coalescent_4096, oracle.WEIGHTED_NORMALIZED, pi, pj)
+    err = _report(f"coalescent_4096 WN {prec} {tuning} sampled", got[condensed_index(n, pi, pj)], want)
     assert err.max() <= TOL[prec]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("method", [UW, WN])
-@pytest.mark.parametrize("case", ["cfg1_ragged_257", "cfg2_shape_513"])
+@pytest.mark.parametrize("case", ["binary_ragged_257", "coalescent_513"])
 def test_separate_transform_variant(uf, ctx, problems, case, method, prec):
     """variant 1: transform into an embedding buffer, one striped launch per batch"""
     prob = problems[case]
@@ -338,7 +338,7 @@ def test_stripe_ranges_partition_equals_full(uf, ctx, problems, prec, den_mode):
     """Independent stripe-range chunks (uneven, not tile-aligned) fill the matrix with the
     values of the full computation, bit for bit; host and device outputs."""
     import torch
-    prob = problems["cfg2_shape_600"]
+    prob = problems["coalescent_600"]
     plan = _plan(uf, ctx, prob)
     S = prob.n_samples // 2
     cuts = [0, 5, 37, 40, 161, S]
@@ -355,7 +355,7 @@ def test_stripe_ranges_partition_equals_full(uf, ctx, problems, prec, den_mode):
 
 
 def test_stripe_range_leaves_other_pairs(uf, ctx, problems):
-    prob = problems["cfg1_ragged_257"]
+    prob = problems["binary_ragged_257"]
     plan = _plan(uf, ctx, prob)
     out = np.full(prob.n_samples * (prob.n_samples - 1) // 2, -3.0)
     plan.distance_stripes(10, 20, out, WN, "fp64")
@@ -370,7 +370,7 @@ def test_stripe_range_leaves_other_pairs(uf, ctx, problems):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("case", ["cfg1_ragged_257", "cfg2_shape_600", "tiny_b"])
+@pytest.mark.parametrize("case", ["binary_ragged_257", "coalescent_600", "tiny_b"])
 def test_weighted_unnormalized(uf, ctx, problems, case, prec):
     """Weighted unnormalized (numerator only) values are lengths, not fractions: the bar is
     relative to max(1, |d|)."""
@@ -389,7 +389,7 @@ def test_weighted_unnormalized(uf, ctx, problems, case, prec):
         np.testing.assert_array_equal(host, got)
 
 
-@pytest.mark.parametrize("case", ["cfg1_ragged_257", "cfg2_shape_513", "tiny_b"])
+@pytest.mark.parametrize("case", ["binary_ragged_257", "coalescent_513", "tiny_b"])
 def test_count_width_16_and_32_agree(uf, ctx, problems, case):
     """uint16 count rows (packed two per word) and int32 rows give the same counts and the
     same distances bit for bit."""

@@ -13,7 +13,7 @@ import pytest
 from scipy.spatial import distance as spd
 
 from oracle import exact, oracle
-from synth import Problem, config_problem, make_rng
+from synth import Problem, workload_problem, make_rng
 
 from helpers import euler_tour_counts, leaves_of, relabel, table_rows, tiny_problem
 
@@ -86,7 +86,7 @@ def test_walkup_counts_match_euler_tour_and_exact(seed):
 
 
 def test_walkup_counts_invariants_config1_shape():
-    prob = config_problem(1, n=64)
+    prob = workload_problem("binary_256", n=64)
     c = oracle.problem_counts(prob)
     np.testing.assert_array_equal(c, euler_tour_counts(prob))
     root = int(np.flatnonzero(prob.parent < 0)[0])
@@ -144,7 +144,7 @@ def _moderate(seed=5, dyadic=False, **kw):
     if dyadic:
         spec["dyadic"] = True
         spec["depth"] = 512
-    return config_problem(1, seed=seed, **spec)
+    return workload_problem("binary_256", seed=seed, **spec)
 
 
 @pytest.mark.parametrize("method", [UW, WN])
