@@ -73,8 +73,8 @@ TRAFFIC = {
         "src_sha256": "7ac7fdd242d76870", "fetch": 44192166645, "write": 34360248000,
         "bytes": 78552414645, "profile": "profiles/k_stripe_fused_wn_fp32_4096x65534.md"},
     "mfma/25000x599998/k_chunk4096/variant0": {
-        "src_sha256": "5d48aca7be669671", "fetch": 204218464352, "write": 102445921984,
-        "bytes": 306664386336, "profile": "profiles/k_mfma_gemm_uw_25000x599998.md"},
+        "src_sha256": "0dafb66920d275d8", "fetch": 216550308040, "write": 102893162048,
+        "bytes": 319443470088, "profile": "profiles/k_mfma_gemm_uw_25000x599998.md"},
     "hbm/25000x16382/fp64/den0/tile2/E8": {
         "src_sha256": "7ac7fdd242d76870", "fetch": 1868219062746, "write": 2016079277952,
         "bytes": 3884298340698, "profile": "profiles/k_stripe_fused_hbm_regime_fp64_25000x16382.md"},
