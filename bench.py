@@ -306,6 +306,8 @@ def bench_striped(args):
         l2, t2 = pr2.get("stripe", (0, 0.0))
         if l2 and p2 in VALU_PEAK_TOPS:
             rec["roofline"] = stripe_roofline(p2, t2, steps2, tun2["den_mode"])
+        if name == "compare":   # the paper's form, host to host
+            rec["end_to_end"] = end_to_end(uf, ctx, prob, method, p2, tun2, stream, 1)
         outs[name] = (o2, rec)
 
     launches, total_ms = prof.get("stripe", (0, 0.0))
