@@ -234,6 +234,42 @@ def test_relabel_unary_and_empty_tips_dyadic_exact(method):
     np.testing.assert_array_equal(oracle.problem_condensed(p2, method), base)
 
 
+def _ill_conditioned_star(n_tiny: int = 4096):
+    """Two samples on a star tree whose branch sums lose every small term under plain
+    FP64 summation in node-id order: tip 0 (length 1) holds a read of both samples, tip 1
+    (length 1) one of sample 0 only, then n_tiny tips of length 2^-53 a read of sample 0
+    only.  Each tiny term is below half an ulp of the running sum, so an uncompensated sum
+    drops all of them (a relative error near n_tiny * 2^-54 ~ 2e-13), while the exact
+    value, and a compensated sum, keep them."""
+    n_tips = 2 + n_tiny
+    parent = np.full(n_tips + 1, n_tips, np.int32)
+    parent[n_tips] = -1
+    length = np.empty(n_tips + 1)
+    length[:2] = 1.0
+    length[2:n_tips] = 2.0 ** -53
+    length[n_tips] = 0.0
+    s0 = np.arange(n_tips, dtype=np.int32)
+    s1 = np.array([0], np.int32)
+    prob = Problem(parent=parent, length=length, feature_node=np.arange(n_tips, dtype=np.int32),
+                   indptr=np.array([0, s0.size, s0.size + 1], np.int64),
+                   indices=np.concatenate([s0, s1]),
+                   counts=np.ones(s0.size + 1, np.int32), n_features=n_tips)
+    return prob
+
+
+def test_compensated_sums_ill_conditioned_exact():
+    """The oracle's sums must be compensated: plain summation fails this exact case."""
+    prob = _ill_conditioned_star()
+    rows = table_rows(prob)
+    for method, fn in ((UW, exact.unweighted), (WN, exact.weighted_normalized),
+                       (WU, exact.weighted_unnormalized)):
+        want = fn(prob.parent, prob.length, rows, prob.feature_node)[0]
+        got = oracle.problem_condensed(prob, method)[0]
+        # the exact value differs from what plain summation gives by ~2e-13 relative;
+        # compensated FP64 stays within a few ulp
+        assert abs(Fraction(float(got)) - want) <= Fraction(1, 10 ** 15) * abs(want), method
+
+
 def test_zero_length_tree_gives_zero():
     prob = tiny_problem(5, max_nodes=10)
     p0 = Problem(**{**prob.__dict__, "length": np.zeros_like(prob.length)})
@@ -251,6 +287,8 @@ MUTANTS = {
     "root branch kept": ("if (parent[v] < 0) continue;            /* the root has no branch */", ""),
     "wrong total": ("double pj = (double)cj[v] / tj;", "double pj = (double)cj[v] / ti;"),
     "tip not counted": ("row[v] += c;\n                v = parent[v];", "v = parent[v];\n                if (v >= 0) row[v] += c;"),
+    "no compensation": ("double N = num + num_c, D = den + den_c;", "double N = num, D = den;"),
+    "Neumaier branch swapped": ("if (fabs(*sum) >= fabs(x))", "if (fabs(*sum) < fabs(x))"),
 }
 
 
@@ -286,6 +324,11 @@ def test_planted_mistakes_are_caught(name, tmp_path, golden_dir):
                 break
             try:
                 test_bruteforce_exact(seed)
+            except AssertionError:
+                caught = True
+        if not caught:
+            try:
+                test_compensated_sums_ill_conditioned_exact()
             except AssertionError:
                 caught = True
         assert caught, f"mutant '{name}' survived the pins"
