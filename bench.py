@@ -14,6 +14,10 @@ Workloads (--workload):
                      the same inputs: plain FP64 (numerator and denominator stripes), FP32
                      in that same numerator-and-denominator form, and FP64 with the
                      per-sample denominator.
+  binary_256         256 samples, 2,048-tip random binary tree, 95 % zeros, NegBin(20, 0.5)
+                     counts rarefied to 1,000: plain FP64 unweighted and weighted normalized,
+                     each timed on the GPU, and the oracle over the full matrix on all host
+                     cores and on one thread.
   mfma               25,000 samples, 300,000-tip random binary tree, 1,500 Zipf(1.1)
                      presences per sample; unweighted on bf16 matrix cores (hi+lo split),
                      timed beside plain FP64 striped (about 28 s a step; --compare none
@@ -36,6 +40,11 @@ Workloads (--workload):
 
 The oracle (FP64 CPU) is timed on the host cores on a seeded sample of pairs as the CPU
 baseline, and the same sample gives the max and mean absolute error of every GPU result.
+
+The default run (the striped workload) also nests shorter records of the other targets in
+its JSON line (--extras none leaves them out): the matrix-core workload against plain FP64
+striped, the memory-bound regime against the HBM roof, the 256-sample FP64 workload with the
+full-matrix oracle, and the oracle over the full matrix of the striped workload itself.
 """
 from __future__ import annotations
 
@@ -100,13 +109,16 @@ def add_traffic(roofline, key, source, launch_ms):
                                   "profile": ent["profile"]}
 
 
-def parse():
+def parse(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="striped",
-                    choices=["striped", "mfma", "batch", "large-wn", "large-uw", "hbm"])
+                    choices=["striped", "binary_256", "mfma", "batch", "large-wn", "large-uw", "hbm"])
+    ap.add_argument("--extras", default="all",
+                    help="striped workload: nested records, comma-separated from "
+                         "mfma,hbm,binary_256,full_oracle, or all / none")
     ap.add_argument("--share", type=int, default=8,
                     help="large-wn: compute 1/share of the stripes (one GPU's share)")
     ap.add_argument("--k-split", type=int, default=0,
@@ -131,11 +143,22 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy 3 times (HBM counter scale)")
-    return ap.parse_args()
+    return ap.parse_args(argv)
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def sample_pairs(rng, n, m):
@@ -183,7 +206,7 @@ def oracle_sample(prob, method, seconds, seed, subset=None):
     log(f"oracle: {pi.size} sampled pairs on {threads} threads in {cpu_s:.1f} s")
     where = f" among {subset} random samples" if pool is not None else ""
     cpu = {"value": round(pi.size * B / cpu_s, 1), "unit": "pair-branch updates/s",
-           "cores": threads, "kind": "oracle",
+           "cores": threads, "kind": "oracle", "cpu_model": cpu_model(),
            "sample": f"{pi.size} seeded random pairs{where} ({method}, all {B} branches each), "
                      f"{cpu_s:.1f} s including walk-up counts of the touched samples",
            "seconds": round(cpu_s, 2)}
@@ -341,6 +364,86 @@ def bench_striped(args):
     if "compare" in outs and n >= 3:
         r, _, _ = uf.mantel(ctx, out, outs["compare"][0], n)
         res["mantel_r2_vs_compare"] = round(r * r, 12)
+    if getattr(args, "full_oracle", False):
+        # every pair of the matrix against the oracle (about a minute and a half on 16 cores)
+        from oracle import oracle
+        om = {"unweighted": oracle.UNWEIGHTED, "weighted_normalized": oracle.WEIGHTED_NORMALIZED,
+              "weighted_unnormalized": oracle.WEIGHTED_UNNORMALIZED}[method]
+        log(f"oracle over the full matrix ({n_pairs} pairs x {B} branches)")
+        t = time.perf_counter()
+        want = oracle.problem_condensed(prob, om)
+        cpu_s = time.perf_counter() - t
+        log(f"full-matrix oracle: {cpu_s:.1f} s")
+
+        def full_err(o):
+            e = np.abs(o.double().cpu().numpy() - want)
+            return {"max_abs": float(e.max()), "mean_abs": float(e.mean()), "pairs": int(e.size)}
+
+        res["full_matrix_check"] = {
+            "pairs": n_pairs, "oracle_seconds": round(cpu_s, 2), "oracle_threads": oracle.max_threads(),
+            "oracle_rate": round(updates / cpu_s, 1), "unit": "pair-branch updates/s",
+            "error_vs_oracle": dict({prec: full_err(out)}, **{k: full_err(o2) for k, (o2, _) in outs.items()})}
+    return res
+
+
+def bench_binary_256(args):
+    """256 samples, 2,048-tip random binary tree: plain FP64 unweighted and weighted
+    normalized (the default knobs) on the GPU, and the oracle over the full matrix on all
+    host cores and on one thread."""
+    import torch
+    import paper_2005_05826_amd as uf
+    from oracle import oracle
+    from synth import workload_problem
+    over = {k: v for k, v in (("n", args.n), ("tips", args.tips)) if v}
+    prob = workload_problem("binary_256", **over)
+    n, B = prob.n_samples, prob.n_nodes - 1
+    n_pairs = n * (n - 1) // 2
+    updates = n_pairs * B
+    ctx = uf.Context(0)
+    stream = torch.cuda.current_stream()
+    plan = uf.Plan.from_problem(ctx, prob, stream=stream)
+    om = {"unweighted": oracle.UNWEIGHTED, "weighted_normalized": oracle.WEIGHTED_NORMALIZED}
+    per, outs = {}, {}
+    for method in om:
+        out = torch.empty(n_pairs, dtype=torch.float64, device="cuda:0")
+        dt, prof = timed_runs(plan, method, "fp64", None, out, args.steps, args.warmup, stream)
+        per[method] = {"ms_per_step": round(dt * 1e3, 4), "value": round(updates / dt, 1),
+                       "kernels_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in prof.items()}}
+        outs[method] = out
+        log(f"binary_256 {method} fp64: {dt * 1e3:.3f} ms/step")
+    dt = sum(v["ms_per_step"] for v in per.values()) * 1e-3
+    res = base_record(args, 2 * updates / dt, dt, "f64",
+                      {"workload": f"unweighted + weighted-normalized plain FP64 striped UniFrac, {n} "
+                                   f"samples, random binary tree with {(prob.n_nodes + 1) // 2} tips "
+                                   f"({B} branches)", "n_samples": n, "branches": B, "precision": "fp64"})
+    res["methods"] = per
+    stripe_ms = sum(v["kernels_ms_per_step"].get("stripe", 0.0) for v in per.values())
+    if stripe_ms > 0:
+        ach = OPS_PER_UPDATE[0] * 2 * updates / (stripe_ms * 1e-3) / 1e12
+        res["roofline"] = {"kernel": "k_stripe_fused", "bound": "alu", "achieved": round(ach, 3),
+                           "peak": round(VALU_PEAK_TOPS["fp64"], 2), "unit": "Tops/s",
+                           "frac": round(ach / VALU_PEAK_TOPS["fp64"], 4), "traffic": None,
+                           "note": "a 256-sample matrix fills a fraction of the device: launch "
+                                   "and latency bound"}
+    if not args.no_cpu:
+        threads = oracle.max_threads()
+        errs, t_all, t_one = {}, 0.0, 0.0
+        for method, m in om.items():
+            t = time.perf_counter()
+            want = oracle.problem_condensed(prob, m)
+            t_all += time.perf_counter() - t
+            t = time.perf_counter()
+            oracle.problem_condensed(prob, m, n_threads=1)
+            t_one += time.perf_counter() - t
+            e = np.abs(outs[method].cpu().numpy() - want)
+            errs[method] = {"max_abs": float(e.max()), "mean_abs": float(e.mean()), "pairs": int(e.size)}
+        res["cpu_baseline"] = {"value": round(2 * updates / t_all, 1), "unit": "pair-branch updates/s",
+                               "cores": threads, "kind": "oracle", "cpu_model": cpu_model(),
+                               "sample": f"the full matrix ({n_pairs} pairs x {B} branches), both methods",
+                               "seconds": round(t_all, 3),
+                               "one_thread": {"value": round(2 * updates / t_one, 1), "seconds": round(t_one, 3)}}
+        res["error_vs_oracle"] = errs
+    plan.close()
     return res
 
 
@@ -662,11 +765,40 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": src.numel() * 4, "dispatches": 3}))
         return
+    extras = set()
+    if args.workload == "striped" and args.extras != "none":
+        extras = {"mfma", "hbm", "binary_256", "full_oracle"} if args.extras == "all" \
+            else set(x for x in args.extras.split(",") if x)
+    args.full_oracle = "full_oracle" in extras and not args.no_cpu
     if args.workload.startswith("large"):
         res = bench_large(args, args.workload.split("-")[1])
     else:
-        res = {"striped": bench_striped, "mfma": bench_mfma, "batch": bench_batch,
-               "hbm": bench_hbm}[args.workload](args)
+        res = {"striped": bench_striped, "binary_256": bench_binary_256, "mfma": bench_mfma,
+               "batch": bench_batch, "hbm": bench_hbm}[args.workload](args)
+    if extras - {"full_oracle"}:
+        # the other targets, each on its default configuration with a few steps
+        res["targets"] = {}
+        runs = [("mfma", bench_mfma, ["--workload", "mfma", "--steps", "3", "--warmup", "1",
+                                      "--cpu-seconds", "10"]),
+                ("hbm", bench_hbm, ["--workload", "hbm", "--steps", "3", "--warmup", "1",
+                                    "--cpu-seconds", "5"]),
+                ("binary_256", bench_binary_256, ["--workload", "binary_256", "--steps", "20",
+                                                  "--warmup", "3"])]
+        for name, fn, argv in runs:
+            if name not in extras:
+                continue
+            sub = parse(argv + (["--no-cpu"] if args.no_cpu else []))
+            log(f"target {name}: {' '.join(argv)}")
+            t = time.time()
+            try:
+                rec = fn(sub)
+            except Exception as e:  # a failing extra must not lose the headline line
+                rec = {"error": f"{type(e).__name__}: {e}"}
+            for k in ("metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data"):
+                rec.pop(k, None)
+            rec["wall_s"] = round(time.time() - t, 1)
+            res["targets"][name] = rec
+            torch.cuda.empty_cache()
     print(json.dumps(res), flush=True)
 
 

@@ -18,8 +18,9 @@
  *    uf_last_error().
  *  - Ownership: the caller owns every input array; they are read during the call only and
  *    never retained, except that uf_plan_create copies what it needs into the plan.
- *    Output buffers are caller-owned too.  Contexts and plans are library-owned opaque
- *    objects released with their destroy function.
+ *    Output buffers are caller-owned too.  Contexts, plans and batches are library-owned
+ *    opaque objects released with their destroy function; plans and batches must be
+ *    destroyed before the context they were made on.
  *  - Pointers: tree and table arrays are HOST pointers.  Output pointers are host or device
  *    pointers as the `out_on_device` flag says (device = memory of the context's GPU).
  *  - Streams: `stream` is a hipStream_t passed as void* (NULL = the default stream).  All
@@ -104,9 +105,12 @@ typedef struct {
 typedef struct {
     int32_t emb_batch;  /* branches per embedding batch streamed through the striped kernel
                            (the batch depth of Section 3, Fig. 2)                            */
-    int32_t k_chunk;    /* matrix-core path: branches per FP32 accumulation chunk (rounded
-                           to an even number of 64-branch stages); chunk sums go to FP64 one
-                           by one (variant 1) or four at a time, added in FP32 (variant 0)  */
+    int32_t k_chunk;    /* matrix-core path: branches per FP32 accumulation chain (rounded
+                           to an even number of 64-branch stages; default 4096).  Variant 1
+                           adds every chain's sum into FP64.  Variant 0 adds four consecutive
+                           chain sums together in FP32 (three roundings) before one FP64 add,
+                           so each FP64 add takes 4 * k_chunk branches, while the FP32 error
+                           stays that of one k_chunk chain plus three roundings              */
     int32_t den_mode;   /* striped path: 0 = numerator and denominator stripes (default);
                            1 = numerator stripes only, denominator from per-sample sums
                            (weighted normalized: sum_b L_b p_ib + sum_b L_b p_jb)            */
@@ -114,10 +118,10 @@ typedef struct {
                            staging them and loops over every batch in one launch (default);
                            1 = separate transform launch into an embedding buffer and one
                            striped launch per batch (single plans only; batches ignore it).
-                           matrix-core path: 0 = each chunk's FP32 sums are added into the
-                           FP64 output after every chunk (two work-groups per CU, default);
-                           1 = chunk sums are kept in FP64 registers and written once (one
-                           work-group per CU)                                                */
+                           matrix-core path: 0 = four consecutive chunk sums are added
+                           together in FP32, then into the FP64 output (two work-groups per
+                           CU, default); 1 = every chunk sum goes into FP64 registers, written
+                           once at the end (one work-group per CU)                           */
     int32_t tile;       /* striped fused/queued kernels: per-lane tile shape (samples x
                            stripes), 0, 1 or 2; den_mode 0: FP64 4x8 | 2x12 | 2x8,
                            FP32 4x16 | 8x8 | 4x8; den_mode 1: FP64 4x16 | 2x24 | 4x8,
@@ -220,6 +224,20 @@ uf_status uf_plan_stripes(uf_plan *plan, uf_method method, uf_precision prec,
 /* Release the plan's cached device scratch (embeddings, stripes); inputs stay resident. */
 uf_status uf_plan_trim(uf_plan *plan);
 
+/* Device memory the plan may hold, in bytes, inputs included (0 = no limit but the
+ * device's).  When all embedding count rows (striped precisions) or presence bits
+ * (matrix-core precision) would not fit beside the inputs and the accumulators, the plan
+ * generates them batch by batch instead: each batch of branch rows is computed from the
+ * table on a second stream (the tips below a node form one range of a depth-first order,
+ * so a row is a difference of two prefix sums over the sample's entries) while the previous
+ * batch is accumulated, in two alternating buffers.  The same happens, without a limit,
+ * when allocating the full rows fails.  Generated rows equal the propagated ones exactly;
+ * striped results then run without branch splits (as with k_split = 1), and the
+ * matrix-core path takes its branches in chunks of a multiple of 4 * k_chunk.  Returns
+ * UF_E_ARG for a negative limit; a limit too small even for generated batches makes the
+ * distance calls fail with UF_E_OOM. */
+uf_status uf_plan_set_memory_limit(uf_plan *plan, int64_t max_device_bytes);
+
 /* Per-kernel timing with HIP events recorded on the launch stream around every device
  * launch of the plan, grouped by kernel class ("propagate", "transform", "stripe",
  * "rowdot", "condense", "bits_transpose", "mfma", "normalize").  enable != 0 turns it on
@@ -234,18 +252,21 @@ uf_status uf_plan_set_profiling(uf_plan *plan, int32_t enable);
 uf_status uf_plan_get_profile(uf_plan *plan, uf_kernel_stat *out, int32_t cap, int32_t *n_out);
 
 /* Autotuner for the grouping parameters (Section 3: tile and batch sizes decide the run
- * time).  Times candidate settings of `prec` on this plan's resident inputs with HIP events
- * (one warm-up, then `reps` calls each; reps <= 0 means 3): striped paths try the three
- * tile shapes with embedding-batch depths 128, 64, 256 and 512 (FP32) or 1024, 256 and 4096
- * (FP64) each; the matrix-core path tries variants 0 and 1 with k_chunk 4096 and 16384.
- * den_mode is taken from `base` (NULL = 0).  A candidate whose output differs from the first
- * candidate's by more than the path's tolerance (FP64 1e-12, else 1e-5) is rejected.  The
- * winner goes to *best (and its milliseconds per call to *best_ms if non-NULL).  With a
- * non-NULL cache_path the winner is appended to that text file under a key of device
- * architecture, method, precision, den_mode and log2 size buckets, and a later call with
- * the same key returns the cached entry without timing.  Uses the default stream. */
-uf_status uf_autotune(uf_plan *plan, uf_method method, uf_precision prec, const uf_tuning *base,
-                      int32_t reps, const char *cache_path, uf_tuning *best, double *best_ms);
+ * time), on one plan.  Times candidate settings of `prec` on this plan's resident inputs
+ * with HIP events (one warm-up, then `reps` calls each; reps <= 0 means 3): striped paths
+ * try the three tile shapes with embedding-batch depths 128, 64 and 32 (FP32; deeper FP32
+ * batches would loosen the worst-case bound of the in-batch FP32 sums, (E - 1) * 2^-24 of
+ * the distance, past 1e-5) or 1024, 256 and 4096 (FP64); the matrix-core path tries variants
+ * 0 and 1 with k_chunk 4096 and 16384.  den_mode is taken from `base` (NULL = 0).  A
+ * candidate whose output differs from the first candidate's by more than the path's
+ * tolerance (FP64 1e-12, else 1e-5) is rejected.  The winner goes to *best (and its
+ * milliseconds per call to *best_ms if non-NULL).  With a non-NULL cache_path the winner is
+ * appended to that text file under a key of device architecture, method, precision,
+ * den_mode and log2 size buckets, and a later call with the same key returns the cached
+ * entry without timing.  Uses the default stream. */
+uf_status uf_plan_autotune(uf_plan *plan, uf_method method, uf_precision prec,
+                           const uf_tuning *base, int32_t reps, const char *cache_path,
+                           uf_tuning *best, double *best_ms);
 
 /* Mantel test between two condensed matrices (the paper's fp32-vs-fp64 check, Section 4:
  * Mantel R^2 0.99999).  x, y: DEVICE arrays of n*(n-1)/2 FP64 values in condensed order
@@ -272,11 +293,16 @@ typedef struct {
     uf_method method;
     uf_precision prec;      /* FP64 / FP32 striped, or MFMA_BF16X2 (unweighted only)     */
     uf_dtype out_dtype;
-    void *out;              /* DEVICE pointer to n*(n-1)/2 elements of out_dtype; it must
-                               stay valid for the life of the batch (graphs replay it)   */
+    void *out;              /* n*(n-1)/2 elements of out_dtype.  A DEVICE pointer must stay
+                               valid for the life of the batch (graphs replay it); a HOST
+                               pointer is written by uf_batch_run after the device work,
+                               through a device staging buffer the batch owns             */
+    int32_t out_on_device;  /* 1: `out` is device memory of the context's GPU; 0: host     */
 } uf_job;
 typedef struct uf_batch uf_batch;
-/* tuning (may be NULL): emb_batch, den_mode and k_chunk apply to every job. */
+/* tuning: when non-NULL its knobs (emb_batch, den_mode, tile, count_width, k_chunk,
+ * variant) apply to every job; when NULL every job takes the knobs uf_autotune stored in the
+ * context for a problem of its kind and size, or the library defaults. */
 uf_status uf_batch_create(uf_context *ctx, const uf_job *jobs, int32_t n_jobs,
                           const uf_tuning *tuning, void *stream, uf_batch **out);
 /* Runs every job (replaying the captured graph if there is one) and waits for it. */
@@ -294,6 +320,34 @@ uf_status uf_distance_batch(uf_context *ctx, const uf_job *jobs, int32_t n_jobs,
 uf_status uf_distance(uf_context *ctx, const uf_tree *tree, const uf_table *table,
                       uf_method method, uf_precision prec, uf_dtype out_dtype, void *out,
                       int32_t out_on_device, void *stream);
+
+/* Embedding counts of every branch, for inspection (the per-branch input buffers of
+ * Section 3): out_counts[b][k] = reads of sample k on the tips at or below the b-th non-root
+ * node, nodes taken in ascending id order with the root skipped; [n_nodes - 1][n_samples]
+ * int32 row-major in HOST memory, owned by the caller.  Validates the inputs first (the
+ * status codes of uf_validate); computes on the context's GPU with the level-synchronous
+ * propagation of the distance path, on the default stream; blocks until done. */
+uf_status uf_debug_embedding_counts(uf_context *ctx, const uf_tree *tree, const uf_table *table,
+                                    int32_t *out_counts);
+
+/* Autotuner over representative jobs (Section 3: the grouping parameters "drastically"
+ * change the run time, so they are tuned per kind of problem).  For each of the n jobs the
+ * knobs of its (method, precision) are timed on its inputs (a temporary plan; tree, table,
+ * method and prec are read, out is ignored): striped precisions try tile shapes 0-2 x
+ * embedding-batch depths (FP32 32, 64, 128; FP64 256, 1024, 4096) x den_mode 0 and 1 (one
+ * warm-up and two timed calls each); the matrix-core precision tries variants 0-1 x k_chunk
+ * 4096 and 16384.  Candidates whose output differs from the first candidate's by more than
+ * the path's tolerance (FP64 1e-12, else 1e-5) are rejected.  The winner is stored in the
+ * context under (method, precision, log2 of the sample count, log2 of the node count); from
+ * then on uf_plan_distance, uf_plan_distance_stripes and uf_distance with a NULL tuning, and
+ * uf_batch_create with a NULL tuning, use the stored knobs for a problem in the same
+ * bucket.  A later tuning of the same bucket replaces the entry.  Blocks until done. */
+uf_status uf_autotune(uf_context *ctx, const uf_job *representative, int32_t n);
+
+/* The knobs uf_autotune stored for a problem of this kind and size: *found = 1 and *out =
+ * the knobs, or *found = 0 when the context has none (library defaults apply). */
+uf_status uf_autotune_lookup(const uf_context *ctx, uf_method method, uf_precision prec,
+                             int32_t n_samples, int32_t n_nodes, uf_tuning *out, int32_t *found);
 
 #ifdef __cplusplus
 }

@@ -12,6 +12,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -46,9 +47,11 @@ EXPORTED = ["uf_status_string", "uf_last_error", "uf_validate", "uf_context_crea
             "uf_context_destroy", "uf_plan_create", "uf_plan_destroy", "uf_plan_query",
             "uf_plan_embedding_counts", "uf_plan_embedding_counts16",
             "uf_plan_embedding_presence", "uf_plan_distance", "uf_plan_distance_stripes", "uf_plan_stripes", "uf_plan_trim", "uf_plan_set_profiling",
-            "uf_plan_get_profile", "uf_autotune", "uf_batch_create", "uf_batch_run", "uf_batch_capture",
+            "uf_plan_get_profile", "uf_plan_autotune", "uf_batch_create", "uf_batch_run", "uf_batch_capture",
             "uf_batch_set_profiling", "uf_batch_get_profile", "uf_batch_destroy",
-            "uf_distance_batch", "uf_mantel", "uf_distance"]
+            "uf_distance_batch", "uf_mantel", "uf_distance", "uf_debug_embedding_counts",
+            "uf_autotune", "uf_autotune_lookup",
+            "uf_plan_set_memory_limit"]
 
 
 class UfTree(ctypes.Structure):
@@ -72,7 +75,8 @@ class UfKernelStat(ctypes.Structure):
 
 class UfJob(ctypes.Structure):
     _fields_ = [("tree", UfTree), ("table", UfTable), ("method", ctypes.c_int),
-                ("prec", ctypes.c_int), ("out_dtype", ctypes.c_int), ("out", c_p)]
+                ("prec", ctypes.c_int), ("out_dtype", ctypes.c_int), ("out", c_p),
+                ("out_on_device", c_i32)]
 
 
 class UfPlanInfo(ctypes.Structure):
@@ -107,8 +111,13 @@ _lib.uf_plan_trim.argtypes = [c_p]
 _lib.uf_plan_set_profiling.argtypes = [c_p, c_i32]
 _lib.uf_plan_get_profile.argtypes = [c_p, ctypes.POINTER(UfKernelStat), c_i32,
                                      ctypes.POINTER(c_i32)]
-_lib.uf_autotune.argtypes = [c_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(UfTuning), c_i32,
-                             ctypes.c_char_p, ctypes.POINTER(UfTuning), ctypes.POINTER(ctypes.c_double)]
+_lib.uf_plan_autotune.argtypes = [c_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(UfTuning), c_i32,
+                                  ctypes.c_char_p, ctypes.POINTER(UfTuning), ctypes.POINTER(ctypes.c_double)]
+_lib.uf_autotune.argtypes = [c_p, ctypes.POINTER(UfJob), c_i32]
+_lib.uf_autotune_lookup.argtypes = [c_p, ctypes.c_int, ctypes.c_int, c_i32, c_i32, ctypes.POINTER(UfTuning),
+                                    ctypes.POINTER(c_i32)]
+_lib.uf_plan_set_memory_limit.argtypes = [c_p, c_i64]
+_lib.uf_debug_embedding_counts.argtypes = [c_p, ctypes.POINTER(UfTree), ctypes.POINTER(UfTable), c_p]
 _lib.uf_batch_create.argtypes = [c_p, ctypes.POINTER(UfJob), c_i32, ctypes.POINTER(UfTuning), c_p,
                                  ctypes.POINTER(c_p)]
 _lib.uf_batch_run.argtypes = [c_p, c_p]
@@ -126,7 +135,7 @@ _lib.uf_distance.argtypes = [c_p, ctypes.POINTER(UfTree), ctypes.POINTER(UfTable
 for _name in ("uf_validate", "uf_context_create", "uf_plan_create", "uf_plan_query",
               "uf_plan_embedding_counts", "uf_plan_embedding_counts16",
               "uf_plan_embedding_presence", "uf_plan_distance", "uf_plan_distance_stripes", "uf_plan_stripes", "uf_plan_trim", "uf_plan_set_profiling",
-              "uf_plan_get_profile", "uf_autotune", "uf_batch_create", "uf_batch_run", "uf_batch_capture",
+              "uf_plan_get_profile", "uf_plan_autotune", "uf_batch_create", "uf_batch_run", "uf_batch_capture",
               "uf_batch_set_profiling", "uf_batch_get_profile", "uf_distance_batch",
               "uf_distance"):
     getattr(_lib, _name).restype = ctypes.c_int
@@ -211,6 +220,9 @@ class Context:
             raise UniFracError(st, _lib.uf_last_error(None).decode())
         self._h = h
         self.device = device
+        # plans and batches made on this context: a context outlives them in the C ABI,
+        # so close() releases the ones still open first
+        self._children = weakref.WeakSet()
 
     @property
     def handle(self):
@@ -220,8 +232,35 @@ class Context:
         if st != UF_OK:
             raise UniFracError(st, _lib.uf_last_error(self._h).decode())
 
+    def autotune(self, jobs):
+        """uf_autotune over representative jobs: a list of (problem, method, precision).
+        The winners stay in this context for problems of the same kind and size."""
+        arr, keep = _job_array([dict(problem=p, method=m, precision=pr, out=None) for p, m, pr in jobs])
+        self._check(_lib.uf_autotune(self._h, arr, len(jobs)))
+        del keep
+
+    def tuned(self, method, precision, n_samples, n_nodes):
+        """The knobs uf_autotune stored for such a problem (dict), or None."""
+        t = UfTuning()
+        found = c_i32(0)
+        self._check(_lib.uf_autotune_lookup(self._h, METHODS[method], PRECISIONS[precision],
+                                            int(n_samples), int(n_nodes), ctypes.byref(t),
+                                            ctypes.byref(found)))
+        return {f: int(getattr(t, f)) for f, _ in UfTuning._fields_} if found.value else None
+
+    def debug_embedding_counts(self, prob) -> np.ndarray:
+        """uf_debug_embedding_counts: [n_nodes - 1][n_samples] int32, non-root nodes in
+        ascending id order."""
+        inp = _Inputs(*_problem_args(prob))
+        out = np.empty((max(inp.parent.shape[0] - 1, 0), inp.indptr.shape[0] - 1), np.int32)
+        self._check(_lib.uf_debug_embedding_counts(self._h, ctypes.byref(inp.tree),
+                                                   ctypes.byref(inp.table), _ptr(out)))
+        return out
+
     def close(self):
         if self._h:
+            for child in list(self._children):
+                child.close()
             _lib.uf_context_destroy(self._h)
             self._h = None
 
@@ -243,6 +282,7 @@ class Plan:
         ctx._check(_lib.uf_plan_create(ctx.handle, ctypes.byref(inp.tree), ctypes.byref(inp.table),
                                        _stream_handle(stream), ctypes.byref(h)))
         self._h = h
+        ctx._children.add(self)
         self.info = self.query()
 
     @classmethod
@@ -322,12 +362,17 @@ class Plan:
     def trim(self):
         self.ctx._check(_lib.uf_plan_trim(self._h))
 
+    def set_memory_limit(self, max_device_bytes: int):
+        """Device bytes the plan may hold (0: no limit); beyond it the count rows or
+        presence bits are generated batch by batch."""
+        self.ctx._check(_lib.uf_plan_set_memory_limit(self._h, int(max_device_bytes)))
+
     def autotune(self, method="unweighted", precision="fp64", base=None, reps=3, cache_path=None):
         """Fastest eligible knobs for this plan: (dict, milliseconds per call)."""
         best = UfTuning()
         ms = ctypes.c_double(0)
-        self.ctx._check(_lib.uf_autotune(self._h, METHODS[method], PRECISIONS[precision],
-                                         _tuning(base), int(reps),
+        self.ctx._check(_lib.uf_plan_autotune(self._h, METHODS[method], PRECISIONS[precision],
+                                              _tuning(base), int(reps),
                                          None if cache_path is None else str(cache_path).encode(),
                                          ctypes.byref(best), ctypes.byref(ms)))
         return ({f: int(getattr(best, f)) for f, _ in UfTuning._fields_}, float(ms.value))
@@ -367,28 +412,45 @@ def distance(ctx: Context, prob, method="unweighted", precision="fp64", out_dtyp
     return out
 
 
+def _job_array(jobs):
+    """ABI job array for a list of dicts (problem, method, precision, out, out_dtype); `out`
+    is a device tensor, a host numpy array, or None.  Returns the array and the objects that
+    must stay alive while the library reads it."""
+    arr = (UfJob * max(1, len(jobs)))()
+    keep = []
+    for i, j in enumerate(jobs):
+        inp = _Inputs(*_problem_args(j["problem"]))
+        keep.append(inp)
+        out = j.get("out")
+        if out is None:
+            ptr, on_dev = None, 0
+        elif isinstance(out, np.ndarray):
+            if not out.flags.c_contiguous:
+                raise ValueError("host outputs must be contiguous")
+            ptr, on_dev = _ptr(out), 0
+        else:
+            ptr, on_dev = c_p(out.data_ptr()), 1
+        arr[i] = UfJob(inp.tree, inp.table, METHODS[j["method"]], PRECISIONS[j["precision"]],
+                       DTYPES[j.get("out_dtype", "f64")], ptr, on_dev)
+    return arr, keep
+
+
 class Batch:
     """Many jobs computed together.  `jobs` is a list of dicts with keys problem, method,
-    precision, out (a contiguous device tensor of n*(n-1)/2 elements) and optionally
-    out_dtype ('f64' or 'f32'); the output tensors must outlive the batch."""
+    precision, out (a contiguous device tensor or host numpy array of n*(n-1)/2 elements)
+    and optionally out_dtype ('f64' or 'f32'); the outputs must outlive the batch.  With
+    tuning=None every job takes the context's tuned knobs for its kind (Context.autotune)."""
 
     def __init__(self, ctx: Context, jobs, tuning=None, stream=None):
         self.ctx = ctx
-        arr = (UfJob * max(1, len(jobs)))()
-        self._outs = []
-        for i, j in enumerate(jobs):
-            inp = _Inputs(*_problem_args(j["problem"]))
-            out = j["out"]
-            self._outs.append(out)
-            arr[i] = UfJob(inp.tree, inp.table, METHODS[j["method"]], PRECISIONS[j["precision"]],
-                           DTYPES[j.get("out_dtype", "f64")], c_p(out.data_ptr()))
-            j["_inputs"] = inp   # keep the host arrays alive until creation returns
+        self._outs = [j["out"] for j in jobs]
+        arr, keep = _job_array(jobs)
         h = c_p()
         ctx._check(_lib.uf_batch_create(ctx.handle, arr, len(jobs), _tuning(tuning),
                                         _stream_handle(stream), ctypes.byref(h)))
-        for j in jobs:
-            j.pop("_inputs", None)
+        del keep
         self._h = h
+        ctx._children.add(self)
 
     def run(self, stream=None):
         self.ctx._check(_lib.uf_batch_run(self._h, _stream_handle(stream)))

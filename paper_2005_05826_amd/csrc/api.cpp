@@ -41,9 +41,17 @@ uf_status propagate_counts(uf_plan *plan, hipStream_t st, int32_t cw)
     cw = resolve_count_width(hp, cw);
     if (cw < 0) return set_err(ctx, UF_E_ARG, "16-bit counts need every sample total <= 65535");
     plan->cw = cw;
+    UF_TRY(plan->counts.ensure((size_t)hp.n_nodes * plan->cstride * cw), "allocating embedding counts");
+    return propagate_counts_into(plan, plan->counts.p, cw, st);
+}
+
+// The same into caller-provided rows C ([n_nodes][cstride] counts of cw bytes); allocates
+// nothing.
+uf_status propagate_counts_into(uf_plan *plan, void *C, int32_t cw, hipStream_t st)
+{
+    uf_context *ctx = plan->ctx;
+    const HostPrep &hp = plan->hp;
     const int64_t words = plan->cstride * cw / 4;   // uint32 words per row
-    UF_TRY(plan->counts.ensure((size_t)hp.n_nodes * words * 4), "allocating embedding counts");
-    void *C = plan->counts.p;
     UF_TRY(launch_fill_u32(C, 0u, (size_t)hp.n_leaf * words, st), "clearing tip rows");
     UF_TRY(timed(plan, "propagate", st, [&] {
                hipError_t r = launch_scatter_counts(plan->indptr.as<int64_t>(),
@@ -127,11 +135,7 @@ uf_status plan_prepare(uf_context *ctx, const uf_tree *tree, const uf_table *tab
 
 }  // namespace ufmi
 
-namespace {
-
-struct Knobs {
-    int32_t emb_batch, k_chunk, den_mode, variant, tile, count_width, k_split;
-};
+namespace ufmi {
 
 Knobs resolve_knobs(const uf_tuning *t, uf_precision prec, int32_t n_branches)
 {
@@ -173,6 +177,185 @@ int32_t auto_k_split(const uf_context *ctx, const StripeGeom &g, int64_t tiles, 
     return (int32_t)std::max<int64_t>(kz, 1);
 }
 
+
+
+StripeGeom striped_geometry(const uf_plan *plan, uf_precision prec, const Knobs &kn)
+{
+    return stripe_geometry(plan->hp.n_samples, prec == UF_PREC_FP64, kn.den_mode, kn.variant == 0 ? kn.tile : 0);
+}
+
+// Stripe tiles [*t0, *t1) that cover stripes [s_begin, s_end) (-1, -1 = all) and the FP64
+// bytes of one copy of their state.
+size_t striped_state_bytes(const StripeGeom &g, int32_t s_begin, int32_t s_end, int32_t *t0, int32_t *t1)
+{
+    *t0 = 0;
+    *t1 = g.spad / g.tsw;
+    if (s_begin >= 0) {
+        *t0 = s_begin / g.tsw;
+        *t1 = (s_end + g.tsw - 1) / g.tsw;
+    }
+    return (size_t)(*t1 - *t0) * g.tsw * g.sstride * sizeof(double);
+}
+
+int32_t striped_k_split(const uf_plan *plan, const Knobs &kn, const StripeGeom &g, int32_t t0, int32_t t1,
+                        size_t state)
+{
+    const int32_t B = plan->hp.n_nodes - 1;
+    const int64_t tiles = (int64_t)(g.sstride / g.tkw) * (t1 - t0);
+    return kn.variant != 0 ? 1
+           : kn.k_split > 0 ? std::min(kn.k_split, std::max(B, 1))
+                            : auto_k_split(plan->ctx, g, tiles, B, kn.emb_batch,
+                                           kn.den_mode == 0 ? 2 * state : state);
+}
+
+// (a)-(b) of the fused form on caller-provided buffers, allocating nothing: propagation into
+// W.C, the fused striped kernel over stripe tiles [t0, t1) into kz state copies at W.num /
+// W.den (each `state` bytes), their reduction, and the per-sample sums into W.D (den_mode 1).
+uf_status striped_core(uf_plan *plan, uf_method method, uf_precision prec, const Knobs &kn,
+                       const StripeGeom &g, int32_t t0, int32_t t1, int32_t kz, size_t state,
+                       int32_t cw, const StripedWork &W, hipStream_t st)
+{
+    uf_context *ctx = plan->ctx;
+    const HostPrep &hp = plan->hp;
+    const bool fp64 = (prec == UF_PREC_FP64);
+    // the unnormalized variant accumulates the weighted-normalized numerator only
+    const bool unnorm = (method == UF_WEIGHTED_UNNORMALIZED);
+    if (unnorm) method = UF_WEIGHTED_NORMALIZED;
+    const int32_t B = hp.n_nodes - 1;
+    double *num = W.num, *den = kn.den_mode == 0 ? W.den : nullptr;
+    if (B == 0) {  // single-node tree: no branches, every distance is 0
+        UF_TRY(launch_fill_u32(num, 0u, state / 4, st), "clearing stripes");
+        if (den) UF_TRY(launch_fill_u32(den, 0u, state / 4, st), "clearing stripes");
+        UF_TRY(launch_fill_u32(W.D, 0u, (size_t)hp.n_samples * 2, st), "clearing sums");
+        return UF_OK;
+    }
+    uf_status s = propagate_counts_into(plan, W.C, cw, st);
+    if (s != UF_OK) return s;
+    // the stripe kernels add every batch into the state, so it starts at zero
+    UF_TRY(launch_fill_u32(num, 0u, state * kz / 4, st), "clearing stripes");
+    if (den) UF_TRY(launch_fill_u32(den, 0u, state * kz / 4, st), "clearing stripes");
+    const double *len = plan->len_slot.as<double>();
+    UF_TRY(launch_inv_totals(plan->totals.as<int32_t>(), hp.n_samples, W.inv_t, st), "reciprocal totals");
+    UF_TRY(timed(plan, "stripe", st, [&] {
+               hipError_t r = launch_stripe_fused(fp64, method, kn.den_mode, kn.tile, W.C, cw,
+                                                  plan->cstride, W.inv_t, len, B, kn.emb_batch, num,
+                                                  den, g, t0, t1, kz, (int64_t)(state / sizeof(double)), st);
+               if (r == hipSuccess)
+                   r = launch_reduce_z(num, (int64_t)(state / sizeof(double)), kz,
+                                       (int64_t)(state / sizeof(double)), st);
+               if (r == hipSuccess && den)
+                   r = launch_reduce_z(den, (int64_t)(state / sizeof(double)), kz,
+                                       (int64_t)(state / sizeof(double)), st);
+               return r;
+           }), "striped accumulation");
+    if (kn.den_mode != 0 && !unnorm)
+        UF_TRY(timed(plan, "rowdot", st, [&] {
+                   return launch_rowdot(method, W.C, cw, plan->cstride, 0, B, plan->totals.as<int32_t>(),
+                                        len, g.n, W.D, true, W.part, st);
+               }), "per-sample sums");
+    return UF_OK;
+}
+
+}  // namespace ufmi
+
+namespace {
+
+// Device bytes of the plan's resident inputs.
+size_t input_bytes(const uf_plan *plan)
+{
+    const HostPrep &hp = plan->hp;
+    return (size_t)(hp.n_samples + 1) * 8 + (size_t)hp.nnz * 8 + (size_t)hp.n_samples * 4 +
+           (size_t)hp.n_nodes * (4 + 4 + 8 + 4);
+}
+
+// The generated-rows tables (depth-first tip ranges, sorted entries), a second stream and
+// its events, made once per plan.
+uf_status gen_prepare(uf_plan *plan, hipStream_t st)
+{
+    uf_context *ctx = plan->ctx;
+    if (plan->gen_ready) return UF_OK;
+    RangeTables rt;
+    range_tables(plan->hp, &rt);
+    UF_TRY(upload(plan->gen_lo, rt.lo, st), "uploading tip ranges");
+    UF_TRY(upload(plan->gen_hi, rt.hi, st), "uploading tip ranges");
+    UF_TRY(upload(plan->gen_spos, rt.spos, st), "uploading sorted entries");
+    UF_TRY(upload(plan->gen_scum, rt.scum, st), "uploading sorted entries");
+    if (!plan->gen_stream)
+        UF_TRY(hipStreamCreateWithFlags(&plan->gen_stream, hipStreamNonBlocking), "creating the row stream");
+    for (hipEvent_t *e : {&plan->gen_start, &plan->gen_filled[0], &plan->gen_filled[1], &plan->gen_used[0],
+                          &plan->gen_used[1]})
+        if (!*e) UF_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming), "creating row events");
+    UF_TRY(hipStreamSynchronize(st), "synchronizing");   // the host tables go out of scope
+    plan->gen_ready = true;
+    return UF_OK;
+}
+
+size_t gen_table_bytes(const uf_plan *plan)
+{
+    return (size_t)plan->hp.nnz * 8 + (size_t)plan->hp.n_nodes * 8;
+}
+
+// (a)-(b) with generated rows: batch i of E branches is computed into buffer i % 2 on the
+// row stream while the striped kernel accumulates batch i - 1 from the other buffer; events
+// order each buffer's fill after its previous use.  One state copy (no branch split).
+uf_status striped_generated(uf_plan *plan, uf_method method, uf_precision prec, const Knobs &kn,
+                            const StripeGeom &g, int32_t t0, int32_t t1, size_t state, int32_t cw,
+                            hipStream_t st)
+{
+    uf_context *ctx = plan->ctx;
+    const HostPrep &hp = plan->hp;
+    const bool fp64 = (prec == UF_PREC_FP64);
+    const bool unnorm = (method == UF_WEIGHTED_UNNORMALIZED);
+    if (unnorm) method = UF_WEIGHTED_NORMALIZED;
+    const int32_t B = hp.n_nodes - 1, E = kn.emb_batch, n = hp.n_samples;
+    uf_status s = gen_prepare(plan, st);
+    if (s != UF_OK) return s;
+    const size_t rows = (size_t)E * plan->cstride * cw;
+    UF_TRY(plan->num.ensure(state), "allocating numerator stripes");
+    if (kn.den_mode == 0) UF_TRY(plan->den.ensure(state), "allocating denominator stripes");
+    UF_TRY(plan->D.ensure((size_t)n * sizeof(double)), "allocating per-sample sums");
+    UF_TRY(plan->inv_t.ensure((size_t)n * sizeof(double)), "allocating totals");
+    UF_TRY(plan->rowdot_part.ensure(rowdot_scratch_elems(n, E) * sizeof(double)), "allocating sum scratch");
+    UF_TRY(plan->gen_buf[0].ensure(rows), "allocating generated rows");
+    UF_TRY(plan->gen_buf[1].ensure(rows), "allocating generated rows");
+    double *num = plan->num.as<double>();
+    double *den = kn.den_mode == 0 ? plan->den.as<double>() : nullptr;
+    UF_TRY(launch_fill_u32(num, 0u, state / 4, st), "clearing stripes");
+    if (den) UF_TRY(launch_fill_u32(den, 0u, state / 4, st), "clearing stripes");
+    UF_TRY(launch_inv_totals(plan->totals.as<int32_t>(), n, plan->inv_t.as<double>(), st), "reciprocal totals");
+    const double *len = plan->len_slot.as<double>();
+    hipStream_t gs = plan->gen_stream;
+    UF_TRY(hipEventRecord(plan->gen_start, st), "ordering the row stream");
+    UF_TRY(hipStreamWaitEvent(gs, plan->gen_start, 0), "ordering the row stream");
+    int32_t i = 0;
+    for (int32_t b0 = 0; b0 < B; b0 += E, ++i) {
+        const int32_t eb = std::min(E, B - b0), x = i & 1;
+        void *buf = plan->gen_buf[x].p;
+        if (i >= 2) UF_TRY(hipStreamWaitEvent(gs, plan->gen_used[x], 0), "reusing a row buffer");
+        UF_TRY(timed(plan, "generate", gs, [&] {
+                   return launch_range_counts(plan->indptr.as<int64_t>(), plan->gen_spos.as<int32_t>(),
+                                              plan->gen_scum.as<int32_t>(), plan->gen_lo.as<int32_t>(),
+                                              plan->gen_hi.as<int32_t>(), b0, eb, n, buf, cw,
+                                              plan->cstride, gs);
+               }), "generating count rows");
+        UF_TRY(hipEventRecord(plan->gen_filled[x], gs), "ordering generated rows");
+        UF_TRY(hipStreamWaitEvent(st, plan->gen_filled[x], 0), "ordering generated rows");
+        UF_TRY(timed(plan, "stripe", st, [&] {
+                   return launch_stripe_fused(fp64, method, kn.den_mode, kn.tile, buf, cw, plan->cstride,
+                                              plan->inv_t.as<double>(), len + b0, eb, eb, num, den, g, t0,
+                                              t1, 1, (int64_t)(state / sizeof(double)), st);
+               }), "striped accumulation");
+        if (kn.den_mode != 0 && !unnorm)
+            UF_TRY(timed(plan, "rowdot", st, [&] {
+                       return launch_rowdot(method, buf, cw, plan->cstride, 0, eb, plan->totals.as<int32_t>(),
+                                            len + b0, n, plan->D.as<double>(), b0 == 0,
+                                            plan->rowdot_part.as<double>(), st);
+                   }), "per-sample sums");
+        UF_TRY(hipEventRecord(plan->gen_used[x], st), "releasing a row buffer");
+    }
+    return UF_OK;
+}
+
 // (a)-(b): fills plan->num / den (den_mode 0) or num / D (den_mode 1).
 // Stripes [s_begin, s_end) (-1, -1 = all): the state block covers the stripe tiles that
 // overlap the range and *s_base receives the stripe held by its first row.
@@ -183,31 +366,71 @@ uf_status run_striped(uf_plan *plan, uf_method method, uf_precision prec, const 
     uf_context *ctx = plan->ctx;
     const HostPrep &hp = plan->hp;
     const bool fp64 = (prec == UF_PREC_FP64);
-    // the unnormalized variant accumulates the weighted-normalized numerator only
-    const bool unnorm = (method == UF_WEIGHTED_UNNORMALIZED);
-    if (unnorm) method = UF_WEIGHTED_NORMALIZED;
-    const StripeGeom g = stripe_geometry(hp.n_samples, fp64, kn.den_mode, kn.variant == 0 ? kn.tile : 0);
+    const StripeGeom g = striped_geometry(plan, prec, kn);
     *geom = g;
-    int32_t tile_s0 = 0, tile_s1 = g.spad / g.tsw;
-    if (s_begin >= 0) {
-        tile_s0 = s_begin / g.tsw;
-        tile_s1 = (s_end + g.tsw - 1) / g.tsw;
-    }
+    int32_t tile_s0 = 0, tile_s1 = 0;
+    const size_t state = striped_state_bytes(g, s_begin, s_end, &tile_s0, &tile_s1);
     if (s_base) *s_base = tile_s0 * g.tsw;
     const int32_t B = hp.n_nodes - 1;
     const size_t tsz = fp64 ? sizeof(double) : sizeof(float);
-    const size_t state = (size_t)(tile_s1 - tile_s0) * g.tsw * g.sstride * sizeof(double);
-    const int64_t tiles = (int64_t)(g.sstride / g.tkw) * (tile_s1 - tile_s0);
-    const int32_t kz = kn.variant != 0 ? 1
-                       : kn.k_split > 0 ? std::min(kn.k_split, std::max(B, 1))
-                                        : auto_k_split(ctx, g, tiles, B, kn.emb_batch,
-                                                       kn.den_mode == 0 ? 2 * state : state);
+    const int32_t cw = resolve_count_width(hp, kn.count_width);
+    if (cw < 0) return set_err(ctx, UF_E_ARG, "16-bit counts need every sample total <= 65535");
+    int32_t kz = striped_k_split(plan, kn, g, tile_s0, tile_s1, state);
+    if (kn.variant == 0 && B > 0) {
+        // resident rows, or rows generated batch by batch when they would not fit
+        const size_t sums = (size_t)hp.n_samples * 16 + rowdot_scratch_elems(g.n, B) * sizeof(double);
+        const size_t resident = input_bytes(plan) + (size_t)hp.n_nodes * plan->cstride * cw +
+                                state * kz * (kn.den_mode == 0 ? 2 : 1) + sums;
+        bool gen = plan->mem_limit > 0 && resident > (size_t)plan->mem_limit;
+        if (gen) {
+            const size_t need = input_bytes(plan) + gen_table_bytes(plan) +
+                                2 * (size_t)kn.emb_batch * plan->cstride * cw +
+                                state * (kn.den_mode == 0 ? 2 : 1) + (size_t)hp.n_samples * 16 +
+                                rowdot_scratch_elems(g.n, kn.emb_batch) * sizeof(double);
+            if (need > (size_t)plan->mem_limit)
+                return set_err(ctx, UF_E_OOM, "even generated count rows need " + std::to_string(need) +
+                                                  " device bytes, above the plan's limit");
+        } else {
+            hipError_t e = plan->counts.ensure((size_t)hp.n_nodes * plan->cstride * cw);
+            if (e == hipErrorOutOfMemory) {   // the full rows do not fit: generate them
+                (void)hipGetLastError();
+                gen = true;
+            } else if (e != hipSuccess) {
+                return hip_fail(ctx, e, "allocating embedding counts");
+            }
+        }
+        if (gen) {
+            plan->counts.release();
+            return striped_generated(plan, method, prec, kn, g, tile_s0, tile_s1, state, cw, st);
+        }
+    }
     UF_TRY(plan->num.ensure(state * kz), "allocating numerator stripes");
     if (kn.den_mode == 0) UF_TRY(plan->den.ensure(state * kz), "allocating denominator stripes");
     UF_TRY(plan->D.ensure((size_t)hp.n_samples * sizeof(double)), "allocating per-sample sums");
     double *num = plan->num.as<double>();
     double *den = kn.den_mode == 0 ? plan->den.as<double>() : nullptr;
     double *D = plan->D.as<double>();
+    if (kn.variant == 0) {
+        StripedWork W{};
+        W.num = num;
+        W.den = den;
+        W.D = D;
+        if (B > 0) {
+            UF_TRY(plan->counts.ensure((size_t)hp.n_nodes * plan->cstride * cw), "allocating embedding counts");
+            UF_TRY(plan->inv_t.ensure((size_t)hp.n_samples * sizeof(double)), "allocating totals");
+            if (kn.den_mode != 0 && method != UF_WEIGHTED_UNNORMALIZED)
+                UF_TRY(plan->rowdot_part.ensure(rowdot_scratch_elems(g.n, B) * sizeof(double)),
+                       "allocating per-sample sum scratch");
+            W.C = plan->counts.p;
+            plan->cw = cw;
+            W.inv_t = plan->inv_t.as<double>();
+            W.part = plan->rowdot_part.as<double>();
+        }
+        return striped_core(plan, method, prec, kn, g, tile_s0, tile_s1, kz, state, cw, W, st);
+    }
+    // the unnormalized variant accumulates the weighted-normalized numerator only
+    const bool unnorm = (method == UF_WEIGHTED_UNNORMALIZED);
+    if (unnorm) method = UF_WEIGHTED_NORMALIZED;
     if (B == 0) {  // single-node tree: no branches, every distance is 0
         UF_TRY(launch_fill_u32(num, 0u, state / 4, st), "clearing stripes");
         if (den) UF_TRY(launch_fill_u32(den, 0u, state / 4, st), "clearing stripes");
@@ -216,41 +439,11 @@ uf_status run_striped(uf_plan *plan, uf_method method, uf_precision prec, const 
     }
     uf_status s = propagate_counts(plan, st, kn.count_width);
     if (s != UF_OK) return s;
-    const int32_t cw = plan->cw;
-    // the stripe kernels add every batch into the state, so it starts at zero
     UF_TRY(launch_fill_u32(num, 0u, state * kz / 4, st), "clearing stripes");
     if (den) UF_TRY(launch_fill_u32(den, 0u, state * kz / 4, st), "clearing stripes");
     const int32_t E = kn.emb_batch;
     const void *C = plan->counts.p;
     const double *len = plan->len_slot.as<double>();
-    if (kn.variant == 0) {
-        UF_TRY(plan->inv_t.ensure((size_t)hp.n_samples * sizeof(double)), "allocating totals");
-        UF_TRY(launch_inv_totals(plan->totals.as<int32_t>(), hp.n_samples, plan->inv_t.as<double>(), st),
-               "reciprocal totals");
-        UF_TRY(timed(plan, "stripe", st, [&] {
-                   hipError_t r = launch_stripe_fused(fp64, method, kn.den_mode, kn.tile, C, cw,
-                                                      plan->cstride, plan->inv_t.as<double>(), len, B,
-                                                      E, num, den, g, tile_s0, tile_s1, kz,
-                                                      (int64_t)(state / sizeof(double)), st);
-                   if (r == hipSuccess)
-                       r = launch_reduce_z(num, (int64_t)(state / sizeof(double)), kz,
-                                           (int64_t)(state / sizeof(double)), st);
-                   if (r == hipSuccess && den)
-                       r = launch_reduce_z(den, (int64_t)(state / sizeof(double)), kz,
-                                           (int64_t)(state / sizeof(double)), st);
-                   return r;
-               }), "striped accumulation");
-        if (kn.den_mode != 0 && !unnorm) {
-            UF_TRY(plan->rowdot_part.ensure(rowdot_scratch_elems(g.n, B) * sizeof(double)),
-                   "allocating per-sample sum scratch");
-            UF_TRY(timed(plan, "rowdot", st, [&] {
-                       return launch_rowdot(method, C, cw, plan->cstride, 0, B,
-                                            plan->totals.as<int32_t>(), len, g.n, D, true,
-                                            plan->rowdot_part.as<double>(), st);
-                   }), "per-sample sums");
-        }
-        return UF_OK;
-    }
     UF_TRY(plan->emb.ensure((size_t)E * g.estride * tsz), "allocating embedding batch");
     if (kn.den_mode != 0 && !unnorm)
         UF_TRY(plan->rowdot_part.ensure(rowdot_scratch_elems(g.n, E) * sizeof(double)),
@@ -276,6 +469,10 @@ uf_status run_striped(uf_plan *plan, uf_method method, uf_precision prec, const 
     return UF_OK;
 }
 
+}  // namespace
+
+namespace ufmi {
+
 uf_status check_enums(uf_context *ctx, uf_method method, uf_precision prec)
 {
     if (method != UF_UNWEIGHTED && method != UF_WEIGHTED_NORMALIZED &&
@@ -289,7 +486,7 @@ uf_status check_enums(uf_context *ctx, uf_method method, uf_precision prec)
     return UF_OK;
 }
 
-}  // namespace
+}  // namespace ufmi
 
 namespace {
 // Matrix-core form of the unweighted variant: fills `out_dev` with condensed distances.
@@ -304,35 +501,97 @@ uf_status run_mfma_unweighted(uf_plan *plan, int32_t k_chunk, int32_t variant, i
     const MfmaGeom g = mfma_geometry(n, B);
     const int64_t n_pairs = (int64_t)n * (n - 1) / 2;
     k_chunk = std::max(g.kstep, k_chunk / g.kstep * g.kstep);
-    uf_status s = propagate_bits(plan, st);
-    if (s != UF_OK) return s;
     DevMem &Pm = plan->mfma_scratch[0], &HL = plan->mfma_scratch[1];
     DevMem &TL = plan->mfma_scratch[2], &TS = plan->mfma_scratch[3];
-    UF_TRY(Pm.ensure((size_t)g.n_pad * (g.k_pad / 8)), "allocating presence bits");
-    UF_TRY(HL.ensure((size_t)2 * g.k_pad * sizeof(uint16_t)), "allocating length splits");
     std::vector<int32_t> xy;
     mfma_tile_list(n, &xy);
+    const bool s_in_out = !out_f32;   // FP64 output doubles as the S array
+    const size_t t_bytes = (size_t)g.n_pad * sizeof(double);
+    const size_t ts_bytes = t_bytes + (s_in_out ? 0 : (size_t)n_pairs * sizeof(double));
+    // resident presence bits, or bits generated chunk by chunk when they would not fit
+    const size_t fixed = input_bytes(plan) + xy.size() * sizeof(int32_t) + ts_bytes;
+    const size_t resident = fixed + (size_t)hp.n_nodes * plan->bstride * 4 + (size_t)g.n_pad * (g.k_pad / 8) +
+                            (size_t)4 * g.k_pad;
+    bool gen = plan->mem_limit > 0 && resident > (size_t)plan->mem_limit;
+    if (!gen) {
+        hipError_t e = plan->bits.ensure((size_t)hp.n_nodes * plan->bstride * sizeof(uint32_t));
+        if (e == hipSuccess) e = Pm.ensure((size_t)g.n_pad * (g.k_pad / 8));
+        if (e == hipErrorOutOfMemory) {   // the full bits do not fit: generate them
+            (void)hipGetLastError();
+            gen = true;
+        } else if (e != hipSuccess) {
+            return hip_fail(ctx, e, "allocating presence bits");
+        }
+    }
     UF_TRY(TL.ensure(xy.size() * sizeof(int32_t)), "allocating tile list");
     UF_TRY(hipMemcpyAsync(TL.p, xy.data(), xy.size() * sizeof(int32_t), hipMemcpyHostToDevice, st),
            "uploading tile list");
-    const bool s_in_out = !out_f32;   // FP64 output doubles as the S array
-    const size_t t_bytes = (size_t)g.n_pad * sizeof(double);
-    UF_TRY(TS.ensure(t_bytes + (s_in_out ? 0 : (size_t)n_pairs * sizeof(double))),
-           "allocating shared lengths");
+    UF_TRY(TS.ensure(ts_bytes), "allocating shared lengths");
     double *T = TS.as<double>();
     double *S = s_in_out ? static_cast<double *>(out_dev) : T + g.n_pad;
-    uint16_t *hi = HL.as<uint16_t>(), *lo = hi + g.k_pad;
-    UF_TRY(timed(plan, "bits_transpose", st, [&] {
-               hipError_t r = launch_split_lengths(plan->len_slot.as<double>(), B, g.k_pad, hi, lo, st);
-               if (r == hipSuccess)
-                   r = launch_bits_transpose(plan->bits.as<uint32_t>(), plan->bstride, g,
-                                            Pm.as<uint8_t>(), st);
-               return r;
-           }), "presence transpose");
-    UF_TRY(timed(plan, "mfma", st, [&] {
-               return launch_mfma_gemm(Pm.as<uint8_t>(), hi, lo, k_chunk, TL.as<int32_t>(), g, S,
-                                       T, variant, st);
-           }), "matrix-core product");
+    if (!gen) {
+        uf_status s = propagate_bits(plan, st);
+        if (s != UF_OK) return s;
+        UF_TRY(HL.ensure((size_t)2 * g.k_pad * sizeof(uint16_t)), "allocating length splits");
+        uint16_t *hi = HL.as<uint16_t>(), *lo = hi + g.k_pad;
+        UF_TRY(timed(plan, "bits_transpose", st, [&] {
+                   hipError_t r = launch_split_lengths(plan->len_slot.as<double>(), B, g.k_pad, hi, lo, st);
+                   if (r == hipSuccess)
+                       r = launch_bits_transpose(plan->bits.as<uint32_t>(), plan->bstride, g,
+                                                Pm.as<uint8_t>(), st);
+                   return r;
+               }), "presence transpose");
+        UF_TRY(timed(plan, "mfma", st, [&] {
+                   return launch_mfma_gemm(Pm.as<uint8_t>(), hi, lo, k_chunk, TL.as<int32_t>(), g, S,
+                                           T, variant, st);
+               }), "matrix-core product");
+    } else {
+        // chunks of Kc branches, a multiple of the FP64 flush group (four FP32 chains of the
+        // kernel's chunk), so the sums come out in the same order as one launch over all
+        plan->bits.release();
+        Pm.release();
+        uf_status s = gen_prepare(plan, st);
+        if (s != UF_OK) return s;
+        const int32_t cs = (std::max(1, k_chunk / g.kstep) + 1) & ~1;
+        const int64_t group = (int64_t)4 * cs * g.kstep;
+        const size_t row_bytes = (size_t)g.n_pad / 8;   // bytes per branch over all samples
+        int64_t avail = plan->mem_limit > 0
+                            ? (int64_t)plan->mem_limit - (int64_t)(fixed + gen_table_bytes(plan))
+                            : (int64_t)1 << 31;
+        int64_t Kc = avail / (int64_t)(2 * row_bytes + 4) / group * group;
+        Kc = std::min<int64_t>(std::max<int64_t>(Kc, group), (g.k_pad + group - 1) / group * group);
+        if (plan->mem_limit > 0 && (int64_t)(fixed + gen_table_bytes(plan) + Kc * (2 * row_bytes + 4)) > plan->mem_limit)
+            return set_err(ctx, UF_E_OOM, "even generated presence bits exceed the plan's limit");
+        UF_TRY(plan->gen_buf[0].ensure((size_t)Kc * row_bytes), "allocating generated bits");
+        UF_TRY(plan->gen_buf[1].ensure((size_t)Kc * row_bytes), "allocating generated bits");
+        UF_TRY(HL.ensure((size_t)2 * Kc * sizeof(uint16_t)), "allocating length splits");
+        const double *len = plan->len_slot.as<double>();
+        hipStream_t gs = plan->gen_stream;
+        UF_TRY(hipEventRecord(plan->gen_start, st), "ordering the row stream");
+        UF_TRY(hipStreamWaitEvent(gs, plan->gen_start, 0), "ordering the row stream");
+        int32_t i = 0;
+        for (int64_t c0 = 0; c0 < B; c0 += Kc, ++i) {
+            const int32_t bc = (int32_t)std::min<int64_t>(Kc, B - c0), x = i & 1;
+            const MfmaGeom gc = mfma_geometry(n, bc);
+            uint8_t *P = plan->gen_buf[x].as<uint8_t>();
+            if (i >= 2) UF_TRY(hipStreamWaitEvent(gs, plan->gen_used[x], 0), "reusing a bit buffer");
+            UF_TRY(timed(plan, "generate", gs, [&] {
+                       return launch_range_bits(plan->indptr.as<int64_t>(), plan->gen_spos.as<int32_t>(),
+                                                plan->gen_scum.as<int32_t>(), plan->gen_lo.as<int32_t>(),
+                                                plan->gen_hi.as<int32_t>(), (int32_t)c0, bc, gc.k_pad, n,
+                                                gc.n_pad, P, gs);
+                   }), "generating presence bits");
+            UF_TRY(hipEventRecord(plan->gen_filled[x], gs), "ordering generated bits");
+            UF_TRY(hipStreamWaitEvent(st, plan->gen_filled[x], 0), "ordering generated bits");
+            uint16_t *hi = HL.as<uint16_t>(), *lo = hi + gc.k_pad;
+            UF_TRY(launch_split_lengths(len + c0, bc, gc.k_pad, hi, lo, st), "length splits");
+            UF_TRY(timed(plan, "mfma", st, [&] {
+                       return launch_mfma_gemm(P, hi, lo, k_chunk, TL.as<int32_t>(), gc, S, T, variant, st,
+                                               c0 > 0 ? 1 : 0);
+                   }), "matrix-core product");
+            UF_TRY(hipEventRecord(plan->gen_used[x], st), "releasing a bit buffer");
+        }
+    }
     UF_TRY(timed(plan, "normalize", st, [&] {
                return launch_mfma_normalize(S, T, n, out_f32, out_dev, st);
            }), "normalize");
@@ -412,8 +671,24 @@ void uf_plan_destroy(uf_plan *plan)
                       &plan->inv_t, &plan->out_tmp, &plan->gather_tmp, &plan->rowdot_part})
         m->release();
     for (DevMem &m : plan->mfma_scratch) m.release();
+    for (DevMem *m : {&plan->gen_spos, &plan->gen_scum, &plan->gen_lo, &plan->gen_hi, &plan->gen_buf[0],
+                      &plan->gen_buf[1]})
+        m->release();
+    if (plan->gen_stream) (void)hipStreamDestroy(plan->gen_stream);
+    for (hipEvent_t e : {plan->gen_start, plan->gen_filled[0], plan->gen_filled[1], plan->gen_used[0],
+                         plan->gen_used[1]})
+        if (e) (void)hipEventDestroy(e);
     plan->prof.release();
     delete plan;
+    (void)hipGetLastError();   // leave no error of the release pending for the caller
+}
+
+uf_status uf_plan_set_memory_limit(uf_plan *plan, int64_t max_device_bytes)
+{
+    if (!plan) return set_err(nullptr, UF_E_ARG, "plan must not be NULL");
+    if (max_device_bytes < 0) return set_err(plan->ctx, UF_E_ARG, "the memory limit must be >= 0");
+    plan->mem_limit = max_device_bytes;
+    return UF_OK;
 }
 
 uf_status uf_plan_trim(uf_plan *plan)
@@ -421,7 +696,8 @@ uf_status uf_plan_trim(uf_plan *plan)
     if (!plan) return set_err(nullptr, UF_E_ARG, "plan must not be NULL");
     (void)enter_device(plan->ctx->device);
     for (DevMem *m : {&plan->counts, &plan->bits, &plan->emb, &plan->num, &plan->den, &plan->D,
-                      &plan->inv_t, &plan->out_tmp, &plan->gather_tmp, &plan->rowdot_part})
+                      &plan->inv_t, &plan->out_tmp, &plan->gather_tmp, &plan->rowdot_part,
+                      &plan->gen_buf[0], &plan->gen_buf[1]})
         m->release();
     for (DevMem &m : plan->mfma_scratch) m.release();
     return UF_OK;
@@ -511,6 +787,40 @@ uf_status uf_plan_embedding_presence(uf_plan *plan, uint32_t *out, int32_t out_o
                      out_on_device, st);
 }
 
+uf_status uf_debug_embedding_counts(uf_context *ctx, const uf_tree *tree, const uf_table *table,
+                                    int32_t *out_counts)
+{
+    if (!ctx || !out_counts) return set_err(ctx, UF_E_ARG, "ctx and out_counts must not be NULL");
+    uf_plan *plan = nullptr;
+    uf_status s = plan_prepare(ctx, tree, table, nullptr, &plan);
+    if (s != UF_OK) return s;
+    const HostPrep &hp = plan->hp;
+    const int32_t nb = hp.n_nodes - 1, n = hp.n_samples;
+    if (nb == 0) {
+        uf_plan_destroy(plan);
+        return UF_OK;
+    }
+    // slots of the non-root nodes in ascending node id
+    std::vector<int32_t> slots;
+    slots.reserve(nb);
+    for (int32_t v = 0; v < hp.n_nodes; ++v)
+        if (v != hp.root) slots.push_back(hp.slot_of_node[v]);
+    const size_t bytes = (size_t)nb * n * sizeof(int32_t);
+    DevMem sl;
+    hipError_t e = upload(sl, slots, nullptr);
+    if (e == hipSuccess) s = propagate_counts(plan, nullptr, 4);
+    if (e == hipSuccess && s == UF_OK) e = plan->gather_tmp.ensure(bytes);
+    if (e == hipSuccess && s == UF_OK)
+        e = launch_gather_rows_u32(plan->counts.as<uint32_t>(), plan->cstride, sl.as<int32_t>(), nb, n,
+                                   plan->gather_tmp.as<uint32_t>(), nullptr);
+    if (e == hipSuccess && s == UF_OK) e = hipMemcpy(out_counts, plan->gather_tmp.p, bytes, hipMemcpyDeviceToHost);
+    sl.release();
+    uf_plan_destroy(plan);
+    if (s != UF_OK) return s;
+    if (e != hipSuccess) return hip_fail(ctx, e, "embedding counts");
+    return UF_OK;
+}
+
 uf_status uf_plan_distance(uf_plan *plan, uf_method method, uf_precision prec,
                            const uf_tuning *tuning, uf_dtype out_dtype, void *out,
                            int32_t out_on_device, void *stream)
@@ -524,6 +834,7 @@ uf_status uf_plan_distance(uf_plan *plan, uf_method method, uf_precision prec,
     const int64_t n_pairs = (int64_t)hp.n_samples * (hp.n_samples - 1) / 2;
     if (n_pairs == 0) return UF_OK;
     if (!out) return set_err(ctx, UF_E_ARG, "out must not be NULL");
+    if (!tuning) tuning = tuned_knobs(ctx, method, prec, hp.n_samples, hp.n_nodes);
     Knobs kn = resolve_knobs(tuning, prec, hp.n_nodes - 1);
     if (kn.den_mode != 0 && kn.den_mode != 1) return set_err(ctx, UF_E_ARG, "den_mode must be 0 or 1");
     if (kn.variant != 0 && kn.variant != 1) return set_err(ctx, UF_E_ARG, "variant must be 0 or 1");
@@ -578,6 +889,7 @@ uf_status uf_plan_distance_stripes(uf_plan *plan, uf_method method, uf_precision
         return set_err(ctx, UF_E_ARG, "stripe range must satisfy 0 <= s_begin <= s_end <= n/2");
     if (s_begin == s_end) return UF_OK;
     if (!out) return set_err(ctx, UF_E_ARG, "out must not be NULL");
+    if (!tuning) tuning = tuned_knobs(ctx, method, prec, hp.n_samples, hp.n_nodes);
     Knobs kn = resolve_knobs(tuning, prec, hp.n_nodes - 1);
     if (kn.den_mode != 0 && kn.den_mode != 1) return set_err(ctx, UF_E_ARG, "den_mode must be 0 or 1");
     if (kn.tile < 0 || kn.tile > 2) return set_err(ctx, UF_E_ARG, "tile must be 0, 1 or 2");

@@ -3,10 +3,12 @@
 // Every job is validated and made resident like a single plan.  The batch then builds
 // device tables so that the device work for all jobs is a short, fixed sequence of
 // launches: one tip scatter and one gather per height level for all jobs together, one
-// persistent queue-driven striped launch per precision, one persistent queue-driven MFMA
-// launch for the matrix-core jobs, and per-job condense/normalize launches.  The queues are
-// ordered largest job first, so idle work-groups always pick the most expensive remaining
-// tile (a longest-processing-time-first schedule).  The whole sequence can be captured
+// persistent queue-driven striped launch per kernel form (precision, method, count width,
+// denominator mode, tile shape), one persistent queue-driven MFMA launch per accumulation
+// variant on a second stream beside them, and per-job condense/normalize launches.  Every
+// job carries its own knobs (batch depth, MFMA chunk), so one batch can mix tunings.  The
+// queues are ordered largest job first, so idle work-groups always pick the most expensive
+// remaining tile (a longest-processing-time-first schedule).  The whole sequence can be captured
 // once into a HIP graph and replayed; it allocates nothing and uses fill kernels (not
 // memset nodes) to clear counters and accumulators.
 #include <algorithm>
@@ -18,28 +20,36 @@
 
 using namespace ufmi;
 
+// Knobs of one job: from the batch's tuning, else from the context's tune cache, else the
+// library defaults.
+struct JobKnobs {
+    int32_t E, den_mode, tile, count_width, k_chunk, variant;
+};
+
 struct uf_batch {
     uf_context *ctx = nullptr;
     std::vector<uf_plan *> plans;
     std::vector<uf_job> jobs;
-    int32_t emb_batch = 0, den_mode = 0, k_chunk = 4096, tile = 0, count_width = 0;
-    int32_t mfma_variant = 0;             // uf_tuning.variant: matrix-core accumulation form
-    int32_t n_groups = 512;   // persistent matrix-core work-groups (two per CU)
+    std::vector<JobKnobs> knobs;
+    std::vector<void *> dev_out;          // device output of every job (its own or staging)
     int32_t n_cus = 256;
     // propagation tables
     DevMem prop_jobs, scatter_tasks, level_tasks;
     std::vector<int32_t> level_ptr;       // per height level, range of level_tasks
     std::vector<int32_t> level_max_vec;   // widest row (uint4 columns) of each level
     int32_t n_scatter = 0;
-    // striped tables, one queue per (precision, method, count width):
-    // q = 4 * (FP32) + 2 * (weighted) + (16-bit counts)
-    static constexpr int kQueues = 8;
+    // striped queues, one per kernel instantiation:
+    // q = ((FP32 * 2 + weighted) * 2 + 16-bit counts) * 6 + den_mode * 3 + tile
+    static constexpr int kQueues = 48;
     DevMem stripe_jobs[kQueues], stripe_items[kQueues];
     int32_t n_stripe_items[kQueues] = {};
-    // matrix-core tables
-    DevMem mfma_jobs, mfma_items, mfma_tiles;
-    int32_t n_mfma_items = 0;
-    DevMem counters;                      // [0, kQueues) striped queues, [kQueues] MFMA queue
+    // matrix-core queues, one per accumulation variant
+    DevMem mfma_jobs[2], mfma_items[2], mfma_tiles;
+    int32_t n_mfma_items[2] = {};
+    DevMem counters;                      // [0, kQueues) striped, then the two matrix-core queues
+    // the matrix-core queue runs on a second stream beside the striped queues
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // graph
     hipStream_t cap_stream = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -52,7 +62,14 @@ namespace {
 
 bool is_striped(const uf_job &j) { return j.prec == UF_PREC_FP64 || j.prec == UF_PREC_FP32; }
 
-// Enqueue the whole batch on `st` (no allocation, no host synchronisation).
+int queue_of(bool fp32, bool weighted, bool c16, int32_t den_mode, int32_t tile)
+{
+    return ((((fp32 ? 1 : 0) * 2 + (weighted ? 1 : 0)) * 2 + (c16 ? 1 : 0)) * 6) + den_mode * 3 + tile;
+}
+
+// Enqueue the whole batch on `st` (no allocation, no host synchronisation).  The matrix-core
+// jobs run on the batch's second stream, forked from and joined back into `st` with events,
+// so that their persistent queue fills the device when the striped queues drain.
 uf_status enqueue(uf_batch *b, hipStream_t st)
 {
     uf_context *ctx = b->ctx;
@@ -77,26 +94,73 @@ uf_status enqueue(uf_batch *b, hipStream_t st)
                }
                return r;
            }), "batched propagation");
+    UF_TRY(launch_fill_u32(b->counters.p, 0u, uf_batch::kQueues + 2, st), "clearing queue counters");
 
-    // (b) striped jobs: clear state and queue counters, one persistent launch per queue
-    UF_TRY(launch_fill_u32(b->counters.p, 0u, uf_batch::kQueues + 1, st), "clearing queue counters");
+    // (c) matrix-core jobs on the second stream: presence bits, persistent MFMA queues,
+    // normalize
+    const bool has_mfma = b->n_mfma_items[0] + b->n_mfma_items[1] > 0;
+    if (has_mfma) {
+        hipStream_t ss = b->side;
+        UF_TRY(hipEventRecord(b->ev_fork, st), "forking the matrix-core stream");
+        UF_TRY(hipStreamWaitEvent(ss, b->ev_fork, 0), "forking the matrix-core stream");
+        for (int32_t j = 0; j < nj; ++j) {
+            if (is_striped(b->jobs[j])) continue;
+            uf_plan *p = b->plans[j];
+            const MfmaGeom g = mfma_geometry(p->hp.n_samples, p->hp.n_nodes - 1);
+            uint16_t *hi = p->mfma_scratch[1].as<uint16_t>(), *lo = hi + g.k_pad;
+            UF_TRY(timed(b->prof, "bits_transpose", ss, [&] {
+                       hipError_t r = launch_split_lengths(p->len_slot.as<double>(), g.B, g.k_pad, hi, lo, ss);
+                       if (r == hipSuccess)
+                           r = launch_bits_transpose(p->bits.as<uint32_t>(), p->bstride, g,
+                                                    p->mfma_scratch[0].as<uint8_t>(), ss);
+                       return r;
+                   }), "presence transpose");
+        }
+        for (int v = 0; v < 2; ++v) {
+            if (b->n_mfma_items[v] == 0) continue;
+            // persistent work-groups: two per CU (variant 0) or one (variant 1)
+            const int32_t groups = std::min(b->n_cus * (v == 1 ? 1 : 2), b->n_mfma_items[v]);
+            UF_TRY(timed(b->prof, "mfma", ss, [&] {
+                       return launch_mfma_queue(b->mfma_jobs[v].as<MfmaArgs>(), b->mfma_items[v].as<int32_t>(),
+                                                b->n_mfma_items[v],
+                                                b->counters.as<int32_t>() + uf_batch::kQueues + v, groups, v, ss);
+                   }), "queued matrix-core product");
+        }
+        for (int32_t j = 0; j < nj; ++j) {
+            if (is_striped(b->jobs[j])) continue;
+            uf_plan *p = b->plans[j];
+            const uf_job &J = b->jobs[j];
+            const MfmaGeom g = mfma_geometry(p->hp.n_samples, p->hp.n_nodes - 1);
+            double *T = p->mfma_scratch[3].as<double>();
+            double *S = J.out_dtype == UF_F64 ? static_cast<double *>(b->dev_out[j]) : T + g.n_pad;
+            UF_TRY(timed(b->prof, "normalize", ss, [&] {
+                       return launch_mfma_normalize(S, T, g.n, J.out_dtype == UF_F32, b->dev_out[j], ss);
+                   }), "normalize");
+        }
+        UF_TRY(hipEventRecord(b->ev_join, ss), "joining the matrix-core stream");
+    }
+
+    // (b) striped jobs: clear state, one persistent launch per queue, then condense
     for (int32_t j = 0; j < nj; ++j) {
         if (!is_striped(b->jobs[j])) continue;
         uf_plan *p = b->plans[j];
-        const StripeGeom g = stripe_geometry(p->hp.n_samples, b->jobs[j].prec == UF_PREC_FP64, b->den_mode, b->tile);
+        const JobKnobs &K = b->knobs[j];
+        const StripeGeom g = stripe_geometry(p->hp.n_samples, b->jobs[j].prec == UF_PREC_FP64, K.den_mode, K.tile);
         const size_t words = (size_t)g.spad * g.sstride * 2;
         UF_TRY(launch_fill_u32(p->num.p, 0u, words, st), "clearing stripes");
-        if (b->den_mode == 0) UF_TRY(launch_fill_u32(p->den.p, 0u, words, st), "clearing stripes");
+        if (K.den_mode == 0) UF_TRY(launch_fill_u32(p->den.p, 0u, words, st), "clearing stripes");
         UF_TRY(launch_inv_totals(p->totals.as<int32_t>(), p->hp.n_samples, p->inv_t.as<double>(), st),
                "reciprocal totals");
     }
     for (int q = 0; q < uf_batch::kQueues; ++q) {
         if (b->n_stripe_items[q] == 0) continue;
-        // as many persistent work-groups as the tile shape keeps resident (2 or 3 per CU)
-        const int32_t groups = b->n_cus * stripe_geometry(256, (q & 4) == 0, b->den_mode, b->tile).occ;
+        const int32_t tile = q % 3, den_mode = (q / 3) % 2, c16 = (q / 6) % 2, wn = (q / 12) % 2;
+        const bool fp64 = q < 24;
+        // as many persistent work-groups as the tile shape keeps resident (2 to 4 per CU)
+        const int32_t groups = b->n_cus * stripe_geometry(256, fp64, den_mode, tile).occ;
         UF_TRY(timed(b->prof, "stripe", st, [&] {
-                   return launch_stripe_queue((q & 4) == 0, (q & 2) ? UF_WEIGHTED_NORMALIZED : UF_UNWEIGHTED,
-                                              (q & 1) ? 2 : 4, b->den_mode, b->tile,
+                   return launch_stripe_queue(fp64, wn ? UF_WEIGHTED_NORMALIZED : UF_UNWEIGHTED,
+                                              c16 ? 2 : 4, den_mode, tile,
                                               b->stripe_jobs[q].as<StripeArgs>(),
                                               b->stripe_items[q].as<int32_t>(), b->n_stripe_items[q],
                                               b->counters.as<int32_t>() + q,
@@ -107,54 +171,21 @@ uf_status enqueue(uf_batch *b, hipStream_t st)
         if (!is_striped(b->jobs[j])) continue;
         uf_plan *p = b->plans[j];
         const uf_job &J = b->jobs[j];
-        const StripeGeom g = stripe_geometry(p->hp.n_samples, J.prec == UF_PREC_FP64, b->den_mode, b->tile);
-        if (b->den_mode != 0 && J.method != UF_WEIGHTED_UNNORMALIZED)
+        const JobKnobs &K = b->knobs[j];
+        const StripeGeom g = stripe_geometry(p->hp.n_samples, J.prec == UF_PREC_FP64, K.den_mode, K.tile);
+        if (K.den_mode != 0 && J.method != UF_WEIGHTED_UNNORMALIZED)
             UF_TRY(launch_rowdot(J.method, p->counts.p, p->cw, p->cstride, 0, p->hp.n_nodes - 1,
                                  p->totals.as<int32_t>(), p->len_slot.as<double>(), g.n,
                                  p->D.as<double>(), true, p->rowdot_part.as<double>(), st),
                    "per-sample sums");
         UF_TRY(timed(b->prof, "condense", st, [&] {
                    return launch_condense(J.method, p->num.as<double>(),
-                                          b->den_mode == 0 ? p->den.as<double>() : nullptr,
-                                          b->den_mode == 0 ? nullptr : p->D.as<double>(), g.sstride,
-                                          g.n, g.S, J.out_dtype == UF_F32, J.out, st);
+                                          K.den_mode == 0 ? p->den.as<double>() : nullptr,
+                                          K.den_mode == 0 ? nullptr : p->D.as<double>(), g.sstride,
+                                          g.n, g.S, J.out_dtype == UF_F32, b->dev_out[j], st);
                }), "condense");
     }
-
-    // (c) matrix-core jobs: presence bits, one persistent MFMA launch, normalize
-    if (b->n_mfma_items > 0) {
-        for (int32_t j = 0; j < nj; ++j) {
-            if (is_striped(b->jobs[j])) continue;
-            uf_plan *p = b->plans[j];
-            const MfmaGeom g = mfma_geometry(p->hp.n_samples, p->hp.n_nodes - 1);
-            uint16_t *hi = p->mfma_scratch[1].as<uint16_t>(), *lo = hi + g.k_pad;
-            UF_TRY(timed(b->prof, "bits_transpose", st, [&] {
-                       hipError_t r = launch_split_lengths(p->len_slot.as<double>(), g.B, g.k_pad, hi, lo, st);
-                       if (r == hipSuccess)
-                           r = launch_bits_transpose(p->bits.as<uint32_t>(), p->bstride, g,
-                                                    p->mfma_scratch[0].as<uint8_t>(), st);
-                       return r;
-                   }), "presence transpose");
-        }
-        UF_TRY(timed(b->prof, "mfma", st, [&] {
-                   return launch_mfma_queue(b->mfma_jobs.as<MfmaArgs>(), b->mfma_items.as<int32_t>(),
-                                            b->n_mfma_items, b->counters.as<int32_t>() + uf_batch::kQueues,
-                                            std::min(b->mfma_variant == 1 ? b->n_groups / 2 : b->n_groups,
-                                                     b->n_mfma_items),
-                                            b->mfma_variant, st);
-               }), "queued matrix-core product");
-        for (int32_t j = 0; j < nj; ++j) {
-            if (is_striped(b->jobs[j])) continue;
-            uf_plan *p = b->plans[j];
-            const uf_job &J = b->jobs[j];
-            const MfmaGeom g = mfma_geometry(p->hp.n_samples, p->hp.n_nodes - 1);
-            double *T = p->mfma_scratch[3].as<double>();
-            double *S = J.out_dtype == UF_F64 ? static_cast<double *>(J.out) : T + g.n_pad;
-            UF_TRY(timed(b->prof, "normalize", st, [&] {
-                       return launch_mfma_normalize(S, T, g.n, J.out_dtype == UF_F32, J.out, st);
-                   }), "normalize");
-        }
-    }
+    if (has_mfma) UF_TRY(hipStreamWaitEvent(st, b->ev_join, 0), "joining the matrix-core stream");
     return UF_OK;
 }
 
@@ -165,7 +196,20 @@ uf_status build_tables(uf_batch *b, hipStream_t st)
     int dev_cus = 256;
     (void)hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, ctx->device);
     b->n_cus = std::max(dev_cus, 1);
-    b->n_groups = 2 * b->n_cus;
+
+    // outputs: the job's device pointer, or a staging buffer for a host output
+    b->dev_out.assign(nj, nullptr);
+    for (int32_t j = 0; j < nj; ++j) {
+        const uf_job &J = b->jobs[j];
+        uf_plan *p = b->plans[j];
+        const int64_t n_pairs = (int64_t)p->hp.n_samples * (p->hp.n_samples - 1) / 2;
+        if (J.out_on_device) {
+            b->dev_out[j] = J.out;
+        } else if (n_pairs > 0) {
+            UF_TRY(p->out_tmp.ensure((size_t)n_pairs * (J.out_dtype == UF_F32 ? 4 : 8)), "allocating output staging");
+            b->dev_out[j] = p->out_tmp.p;
+        }
+    }
 
     // propagation tables and per-job scratch
     std::vector<PropJob> pj(nj);
@@ -179,7 +223,7 @@ uf_status build_tables(uf_batch *b, hipStream_t st)
         const HostPrep &hp = p->hp;
         const bool striped = is_striped(b->jobs[j]);
         if (striped) {
-            p->cw = resolve_count_width(hp, b->count_width);
+            p->cw = resolve_count_width(hp, b->knobs[j].count_width);
             if (p->cw < 0) return set_err(ctx, UF_E_ARG, "16-bit counts need every sample total <= 65535");
             UF_TRY(p->counts.ensure((size_t)hp.n_nodes * p->cstride * p->cw), "allocating counts");
         } else
@@ -226,64 +270,67 @@ uf_status build_tables(uf_batch *b, hipStream_t st)
     std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
         return b->plans[x]->hp.n_nodes > b->plans[y]->hp.n_nodes;
     });
-    for (int q = 0; q < uf_batch::kQueues; ++q) {
-        const bool fp64 = (q & 4) == 0;
-        std::vector<StripeArgs> sj;
-        std::vector<int32_t> items;
-        for (int32_t j : order) {
-            const uf_job &J = b->jobs[j];
-            if (!is_striped(J) || (J.prec == UF_PREC_FP64) != fp64) continue;
-            // the unnormalized variant runs the weighted-normalized numerator
-            const int32_t km = J.method == UF_WEIGHTED_UNNORMALIZED ? UF_WEIGHTED_NORMALIZED : J.method;
-            uf_plan *p = b->plans[j];
-            if ((km == UF_WEIGHTED_NORMALIZED) != ((q & 2) != 0) || (p->cw == 2) != ((q & 1) != 0)) continue;
-            const HostPrep &hp = p->hp;
-            const StripeGeom g = stripe_geometry(hp.n_samples, fp64, b->den_mode, b->tile);
-            const size_t state = (size_t)g.spad * g.sstride * sizeof(double);
-            UF_TRY(p->num.ensure(state), "allocating stripes");
-            if (b->den_mode == 0) UF_TRY(p->den.ensure(state), "allocating stripes");
-            UF_TRY(p->D.ensure((size_t)hp.n_samples * sizeof(double)), "allocating sums");
-            if (b->den_mode != 0)
-                UF_TRY(p->rowdot_part.ensure(rowdot_scratch_elems(hp.n_samples, hp.n_nodes - 1) * sizeof(double)),
-                       "allocating sum scratch");
-            UF_TRY(p->inv_t.ensure((size_t)hp.n_samples * sizeof(double)), "allocating totals");
-            int32_t E = b->emb_batch > 0 ? b->emb_batch : (fp64 ? 1024 : 128);
-            E = std::max(1, std::min(E, std::max(1, hp.n_nodes - 1)));
-            const int32_t idx = (int32_t)sj.size();
-            sj.push_back(make_stripe_args(km, p->counts.p, p->cw, p->cstride,
-                                          p->inv_t.as<double>(), p->len_slot.as<double>(),
-                                          hp.n_nodes - 1, E, p->num.as<double>(),
-                                          b->den_mode == 0 ? p->den.as<double>() : nullptr, g));
-            if (hp.n_nodes - 1 <= 0 || g.S == 0) continue;  // nothing to accumulate
-            const int32_t n_tiles = sj.back().tiles_k * sj.back().tiles_s;
-            for (int32_t t = 0; t < n_tiles; ++t) {
-                items.push_back(idx);
-                items.push_back(t);
-            }
+    std::vector<std::vector<StripeArgs>> sj(uf_batch::kQueues);
+    std::vector<std::vector<int32_t>> items(uf_batch::kQueues);
+    for (int32_t j : order) {
+        const uf_job &J = b->jobs[j];
+        if (!is_striped(J)) continue;
+        const JobKnobs &K = b->knobs[j];
+        const bool fp64 = J.prec == UF_PREC_FP64;
+        // the unnormalized variant runs the weighted-normalized numerator
+        const int32_t km = J.method == UF_WEIGHTED_UNNORMALIZED ? UF_WEIGHTED_NORMALIZED : J.method;
+        uf_plan *p = b->plans[j];
+        const HostPrep &hp = p->hp;
+        const int q = queue_of(!fp64, km == UF_WEIGHTED_NORMALIZED, p->cw == 2, K.den_mode, K.tile);
+        const StripeGeom g = stripe_geometry(hp.n_samples, fp64, K.den_mode, K.tile);
+        const size_t state = (size_t)g.spad * g.sstride * sizeof(double);
+        UF_TRY(p->num.ensure(state), "allocating stripes");
+        if (K.den_mode == 0) UF_TRY(p->den.ensure(state), "allocating stripes");
+        UF_TRY(p->D.ensure((size_t)hp.n_samples * sizeof(double)), "allocating sums");
+        if (K.den_mode != 0)
+            UF_TRY(p->rowdot_part.ensure(rowdot_scratch_elems(hp.n_samples, hp.n_nodes - 1) * sizeof(double)),
+                   "allocating sum scratch");
+        UF_TRY(p->inv_t.ensure((size_t)hp.n_samples * sizeof(double)), "allocating totals");
+        const int32_t E = std::max(1, std::min(K.E, std::max(1, hp.n_nodes - 1)));
+        const int32_t idx = (int32_t)sj[q].size();
+        sj[q].push_back(make_stripe_args(km, p->counts.p, p->cw, p->cstride,
+                                         p->inv_t.as<double>(), p->len_slot.as<double>(),
+                                         hp.n_nodes - 1, E, p->num.as<double>(),
+                                         K.den_mode == 0 ? p->den.as<double>() : nullptr, g));
+        if (hp.n_nodes - 1 <= 0 || g.S == 0) continue;  // nothing to accumulate
+        const int32_t n_tiles = sj[q].back().tiles_k * sj[q].back().tiles_s;
+        for (int32_t t = 0; t < n_tiles; ++t) {
+            items[q].push_back(idx);
+            items[q].push_back(t);
         }
-        b->n_stripe_items[q] = (int32_t)(items.size() / 2);
-        UF_TRY(upload(b->stripe_jobs[q], sj, st), "uploading striped jobs");
-        UF_TRY(upload(b->stripe_items[q], items, st), "uploading striped items");
+    }
+    for (int q = 0; q < uf_batch::kQueues; ++q) {
+        b->n_stripe_items[q] = (int32_t)(items[q].size() / 2);
+        if (sj[q].empty()) continue;
+        UF_TRY(upload(b->stripe_jobs[q], sj[q], st), "uploading striped jobs");
+        UF_TRY(upload(b->stripe_items[q], items[q], st), "uploading striped items");
     }
 
     // matrix-core tables
-    std::vector<MfmaArgs> mj;
-    std::vector<int32_t> mitems, tiles_all;
-    std::vector<std::pair<int32_t, size_t>> tile_off;   // (job, offset into tiles_all)
+    std::vector<int32_t> tiles_all;
+    std::vector<size_t> tile_off(nj, 0);
     std::vector<int32_t> morder;
     for (int32_t j : order)
         if (!is_striped(b->jobs[j])) morder.push_back(j);
     for (int32_t j : morder) {
         std::vector<int32_t> xy;
         mfma_tile_list(b->plans[j]->hp.n_samples, &xy);
-        tile_off.push_back({j, tiles_all.size()});
+        tile_off[j] = tiles_all.size();
         tiles_all.insert(tiles_all.end(), xy.begin(), xy.end());
     }
-    UF_TRY(upload(b->mfma_tiles, tiles_all, st), "uploading tile lists");
-    for (size_t m = 0; m < morder.size(); ++m) {
-        const int32_t j = morder[m];
+    if (!tiles_all.empty()) UF_TRY(upload(b->mfma_tiles, tiles_all, st), "uploading tile lists");
+    std::vector<MfmaArgs> mj[2];
+    std::vector<int32_t> mitems[2];
+    for (int32_t j : morder) {
         uf_plan *p = b->plans[j];
         const uf_job &J = b->jobs[j];
+        const JobKnobs &K = b->knobs[j];
+        const int v = K.variant;
         const MfmaGeom g = mfma_geometry(p->hp.n_samples, p->hp.n_nodes - 1);
         const int64_t n_pairs = (int64_t)g.n * (g.n - 1) / 2;
         UF_TRY(p->bits.ensure((size_t)p->hp.n_nodes * p->bstride * sizeof(uint32_t)), "allocating bits");
@@ -294,20 +341,43 @@ uf_status build_tables(uf_batch *b, hipStream_t st)
                                          (s_in_out ? 0 : (size_t)n_pairs * sizeof(double))),
                "allocating shared lengths");
         double *T = p->mfma_scratch[3].as<double>();
-        double *S = s_in_out ? static_cast<double *>(J.out) : T + g.n_pad;
+        double *S = s_in_out ? static_cast<double *>(b->dev_out[j]) : T + g.n_pad;
         uint16_t *hi = p->mfma_scratch[1].as<uint16_t>();
-        mj.push_back(make_mfma_args(p->mfma_scratch[0].as<uint8_t>(), hi, hi + g.k_pad, b->k_chunk,
-                                    b->mfma_tiles.as<int32_t>() + tile_off[m].second, g, S, T));
+        const int32_t m = (int32_t)mj[v].size();
+        mj[v].push_back(make_mfma_args(p->mfma_scratch[0].as<uint8_t>(), hi, hi + g.k_pad, K.k_chunk,
+                                       b->mfma_tiles.as<int32_t>() + tile_off[j], g, S, T));
         for (int32_t t = 0; t < g.n_tiles; ++t) {
-            mitems.push_back((int32_t)m);
-            mitems.push_back(t);
+            mitems[v].push_back(m);
+            mitems[v].push_back(t);
         }
     }
-    b->n_mfma_items = (int32_t)(mitems.size() / 2);
-    UF_TRY(upload(b->mfma_jobs, mj, st), "uploading matrix-core jobs");
-    UF_TRY(upload(b->mfma_items, mitems, st), "uploading matrix-core items");
-    UF_TRY(b->counters.ensure((uf_batch::kQueues + 1) * sizeof(int32_t)), "allocating counters");
+    for (int v = 0; v < 2; ++v) {
+        b->n_mfma_items[v] = (int32_t)(mitems[v].size() / 2);
+        if (mj[v].empty()) continue;
+        UF_TRY(upload(b->mfma_jobs[v], mj[v], st), "uploading matrix-core jobs");
+        UF_TRY(upload(b->mfma_items[v], mitems[v], st), "uploading matrix-core items");
+    }
+    UF_TRY(b->counters.ensure((uf_batch::kQueues + 2) * sizeof(int32_t)), "allocating counters");
+    if (!morder.empty()) {
+        UF_TRY(hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking), "creating the matrix-core stream");
+        UF_TRY(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming), "creating event");
+        UF_TRY(hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming), "creating event");
+    }
     UF_TRY(hipStreamSynchronize(st), "synchronizing");
+    return UF_OK;
+}
+
+// Host outputs: copy every staged job output back after the device work on `st`.
+uf_status copy_out(uf_batch *b, hipStream_t st)
+{
+    uf_context *ctx = b->ctx;
+    for (size_t j = 0; j < b->jobs.size(); ++j) {
+        const uf_job &J = b->jobs[j];
+        if (J.out_on_device || !b->dev_out[j]) continue;
+        const int64_t n = b->plans[j]->hp.n_samples;
+        const size_t bytes = (size_t)(n * (n - 1) / 2) * (J.out_dtype == UF_F32 ? 4 : 8);
+        UF_TRY(hipMemcpyAsync(J.out, b->dev_out[j], bytes, hipMemcpyDeviceToHost, st), "copying distances out");
+    }
     return UF_OK;
 }
 
@@ -345,20 +415,6 @@ uf_status uf_batch_create(uf_context *ctx, const uf_job *jobs, int32_t n_jobs,
     uf_batch *b = new (std::nothrow) uf_batch;
     if (!b) return set_err(ctx, UF_E_OOM, "host allocation failed");
     b->ctx = ctx;
-    b->tile = 2;   // without knobs, the fastest measured shape for den_mode 0
-    if (tuning) {
-        b->emb_batch = tuning->emb_batch;
-        b->den_mode = tuning->den_mode;
-        b->tile = tuning->tile;
-        b->count_width = tuning->count_width;
-        b->mfma_variant = tuning->variant;
-        if (tuning->k_chunk > 0) b->k_chunk = tuning->k_chunk;
-    }
-    if ((b->den_mode != 0 && b->den_mode != 1) || (b->tile < 0 || b->tile > 2) ||
-        (b->mfma_variant != 0 && b->mfma_variant != 1)) {
-        delete b;
-        return set_err(ctx, UF_E_ARG, "den_mode and variant must be 0 or 1, tile 0, 1 or 2");
-    }
     hipStream_t st = static_cast<hipStream_t>(stream);
     b->jobs.assign(jobs, jobs + n_jobs);
     for (int32_t j = 0; j < n_jobs; ++j) {
@@ -370,6 +426,24 @@ uf_status uf_batch_create(uf_context *ctx, const uf_job *jobs, int32_t n_jobs,
             return set_err(ctx, s, msg);
         }
         b->plans.push_back(p);
+        // knobs: the batch's tuning, else what uf_autotune stored for this kind of problem
+        const uf_job &J = jobs[j];
+        const uf_tuning *t = tuning ? tuning
+                                    : tuned_knobs(ctx, J.method, J.prec, p->hp.n_samples, p->hp.n_nodes);
+        JobKnobs K;
+        K.E = (t && t->emb_batch > 0) ? t->emb_batch : (J.prec == UF_PREC_FP64 ? 1024 : 128);
+        K.den_mode = t ? t->den_mode : 0;
+        K.tile = t ? t->tile : 2;   // without knobs, the fastest measured shape for den_mode 0
+        K.count_width = t ? t->count_width : 0;
+        K.k_chunk = (t && t->k_chunk > 0) ? t->k_chunk : 4096;
+        K.variant = t ? t->variant : 0;
+        if ((K.den_mode != 0 && K.den_mode != 1) || K.tile < 0 || K.tile > 2 ||
+            (K.variant != 0 && K.variant != 1)) {
+            uf_batch_destroy(b);
+            return set_err(ctx, UF_E_ARG, "den_mode and variant must be 0 or 1, tile 0, 1 or 2");
+        }
+        if (J.method == UF_WEIGHTED_UNNORMALIZED) K.den_mode = 1;   // no denominator at all
+        b->knobs.push_back(K);
     }
     uf_status s = build_tables(b, st);
     if (s != UF_OK) {
@@ -400,6 +474,8 @@ uf_status uf_batch_run(uf_batch *b, void *stream)
         uf_status s = enqueue(b, st);
         if (s != UF_OK) return s;
     }
+    uf_status s = copy_out(b, st);
+    if (s != UF_OK) return s;
     UF_TRY(hipStreamSynchronize(st), "synchronizing");
     if (b->prof.on) b->prof.collect();
     return UF_OK;
@@ -470,16 +546,23 @@ void uf_batch_destroy(uf_batch *b)
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);
     if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    if (b->side) (void)hipStreamDestroy(b->side);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    if (b->ev_join) (void)hipEventDestroy(b->ev_join);
     for (uf_plan *p : b->plans) uf_plan_destroy(p);
     for (int q = 0; q < uf_batch::kQueues; ++q) {
         b->stripe_jobs[q].release();
         b->stripe_items[q].release();
     }
-    for (DevMem *m : {&b->prop_jobs, &b->scatter_tasks, &b->level_tasks, &b->mfma_jobs,
-                      &b->mfma_items, &b->mfma_tiles, &b->counters})
+    for (int v = 0; v < 2; ++v) {
+        b->mfma_jobs[v].release();
+        b->mfma_items[v].release();
+    }
+    for (DevMem *m : {&b->prop_jobs, &b->scatter_tasks, &b->level_tasks, &b->mfma_tiles, &b->counters})
         m->release();
     b->prof.release();
     delete b;
+    (void)hipGetLastError();   // leave no error of the release pending for the caller
 }
 
 uf_status uf_distance_batch(uf_context *ctx, const uf_job *jobs, int32_t n_jobs, void *stream)

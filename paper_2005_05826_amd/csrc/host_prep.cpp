@@ -4,9 +4,11 @@
 // a status code and never reaches a kernel.  The products are the level schedule used by
 // the level-synchronous embedding propagation (children of a node always sit in an earlier
 // level) and the leaf slot of every CSR entry.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <limits>
+#include <numeric>
 
 #include "uf_internal.h"
 
@@ -165,6 +167,64 @@ uf_status validate_and_prepare(const uf_tree *tree, const uf_table *table, HostP
         hp->totals[k] = (int32_t)tot;
     }
     return UF_OK;
+}
+
+// Euler-tour tables for generating count rows without the level propagation: tips are
+// numbered in depth-first order (children in node-id order), so the tips below any node form
+// one contiguous range [lo, hi) of that order, and a sample's reads below the node are the
+// difference of two prefix sums over its entries sorted by tip position.
+void range_tables(const HostPrep &hp, RangeTables *rt)
+{
+    const int32_t N = hp.n_nodes, n = hp.n_samples;
+    rt->lo.assign(N, 0);
+    rt->hi.assign(N, 0);
+    std::vector<int32_t> tip_pos(N, -1);
+    // iterative depth-first walk over slots from the root (the last slot)
+    std::vector<std::pair<int32_t, int32_t>> stack;   // (slot, next child index)
+    stack.reserve(64);
+    stack.push_back({N - 1, 0});
+    int32_t pos = 0;
+    while (!stack.empty()) {
+        auto &top = stack.back();
+        const int32_t s = top.first;
+        if (s < hp.n_leaf) {   // a tip
+            rt->lo[s] = pos;
+            tip_pos[s] = pos++;
+            rt->hi[s] = pos;
+            stack.pop_back();
+            continue;
+        }
+        const int32_t i = s - hp.n_leaf;
+        const int32_t q0 = hp.child_ptr[i], q1 = hp.child_ptr[i + 1];
+        if (top.second == 0) rt->lo[s] = pos;
+        if (q0 + top.second < q1) {
+            const int32_t c = hp.child_slot[q0 + top.second];
+            ++top.second;
+            stack.push_back({c, 0});
+        } else {
+            rt->hi[s] = pos;
+            stack.pop_back();
+        }
+    }
+    // entries of every sample sorted by tip position, with running sums of their counts
+    const int64_t nnz = hp.nnz;
+    rt->spos.resize(nnz);
+    rt->scum.resize(nnz);
+    std::vector<int64_t> idx;
+    for (int32_t k = 0; k < n; ++k) {
+        const int64_t a = hp.indptr[k], b = hp.indptr[k + 1];
+        idx.resize(b - a);
+        std::iota(idx.begin(), idx.end(), a);
+        std::sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) {
+            return tip_pos[hp.entry_slot[x]] < tip_pos[hp.entry_slot[y]];
+        });
+        int64_t run = 0;
+        for (int64_t t = 0; t < b - a; ++t) {
+            rt->spos[a + t] = tip_pos[hp.entry_slot[idx[t]]];
+            run += hp.entry_count[idx[t]];
+            rt->scum[a + t] = (int32_t)run;   // <= the sample total, which fits in int32
+        }
+    }
 }
 
 }  // namespace ufmi

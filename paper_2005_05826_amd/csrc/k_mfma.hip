@@ -252,7 +252,7 @@ __device__ void mfma_tile(const MfmaArgs &a, int32_t row0, int32_t col0, MfmaSme
                 for (int r = 0; r < (REG64 ? 1 : 16); ++r) acc2[x][y][r] = 0.f;
     }
     int32_t grouped = 0;
-    bool flushed = false;
+    bool flushed = a.accum != 0;   // accumulating launches add from their first flush on
     int32_t ks = 0;
     while (ks < n_kstep) {
         // FP32 accumulation inside a chunk of chunk_steps stages, then one FP64 flush
@@ -331,13 +331,15 @@ __device__ void mfma_tile(const MfmaArgs &a, int32_t row0, int32_t col0, MfmaSme
                 for (int r = 0; r < 16; ++r) {
                     const int32_t i = elem_row(mb, r);
                     const int32_t j = elem_col(nb);
-                    if (i < n && j < n && i <= j)
-                        *(i < j ? S + ((int64_t)n * i - (int64_t)i * (i + 1) / 2 + (j - i - 1)) : T + i) =
-                            acc64[REG64 ? mb : 0][REG64 ? nb : 0][REG64 ? r : 0];
+                    if (i < n && j < n && i <= j) {
+                        double *dst = i < j ? S + ((int64_t)n * i - (int64_t)i * (i + 1) / 2 + (j - i - 1)) : T + i;
+                        const double v = acc64[REG64 ? mb : 0][REG64 ? nb : 0][REG64 ? r : 0];
+                        *dst = a.accum ? *dst + v : v;
+                    }
                 }
         return;
     }
-    if (n_kstep == 0) {   // no branches: every shared length is 0
+    if (n_kstep == 0 && !a.accum) {   // no branches: every shared length is 0
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
@@ -475,6 +477,8 @@ MfmaArgs make_mfma_args(const uint8_t *P, const uint16_t *hi, const uint16_t *lo
     a.lo = lo;
     a.n = g.n;
     a.n_tiles = g.n_tiles;
+    a.accum = 0;
+    a.pad = 0;
     a.S = S;
     a.T = T;
     a.tiles = reinterpret_cast<const int2 *>(tiles_xy);
@@ -483,9 +487,10 @@ MfmaArgs make_mfma_args(const uint8_t *P, const uint16_t *hi, const uint16_t *lo
 
 hipError_t launch_mfma_gemm(const uint8_t *P, const uint16_t *hi, const uint16_t *lo,
                             int32_t k_chunk, const int32_t *tiles_xy, const MfmaGeom &g,
-                            double *S, double *T, int32_t variant, hipStream_t st)
+                            double *S, double *T, int32_t variant, hipStream_t st, int32_t accum)
 {
-    const MfmaArgs a = make_mfma_args(P, hi, lo, k_chunk, tiles_xy, g, S, T);
+    MfmaArgs a = make_mfma_args(P, hi, lo, k_chunk, tiles_xy, g, S, T);
+    a.accum = accum;
     const int32_t per = (g.n_tiles + 7) / 8;
     if (variant == 1)
         k_mfma_gemm<true><<<(unsigned)(8 * per), 256, 0, st>>>(a, a.tiles, g.n_tiles);

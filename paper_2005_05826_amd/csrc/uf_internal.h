@@ -35,6 +35,16 @@ struct HostPrep {
 uf_status validate_and_prepare(const uf_tree *tree, const uf_table *table, HostPrep *hp,
                                std::string *err);
 
+// Tip ranges of a depth-first order and per-sample sorted entries, for generating count
+// rows batch by batch: the tips below slot s are positions [lo[s], hi[s]); the entries of
+// sample k (CSR range of the table) sorted by tip position are spos, with running count
+// sums scum (each sample starting from zero).
+struct RangeTables {
+    std::vector<int32_t> lo, hi;     // per slot
+    std::vector<int32_t> spos, scum; // per CSR entry, sorted within each sample
+};
+void range_tables(const HostPrep &hp, RangeTables *rt);
+
 // ------------------------------------------------------------------ device launches
 
 // All launches are asynchronous on `st` and return the launch status.
@@ -148,6 +158,17 @@ hipError_t launch_condense(int32_t method, const double *num, const double *den,
                            int64_t sstride, int32_t n, int32_t S, int32_t out_f32, void *out,
                            hipStream_t st);
 
+// Count rows generated from the range tables (no propagation): out[e][k] = reads of sample
+// k below slot slot0 + e, for e < E, k < n, as cw-byte counts in rows of ostride elements.
+hipError_t launch_range_counts(const int64_t *indptr, const int32_t *spos, const int32_t *scum,
+                               const int32_t *lo, const int32_t *hi, int32_t slot0, int32_t E,
+                               int32_t n, void *out, int32_t cw, int64_t ostride, hipStream_t st);
+// Presence bits of branch slots [slot0, slot0 + Bc) in the matrix-core layout: P[k][b / 8]
+// bit b % 8 for k < n_pad (rows k >= n are zero), b < kpad (bits b >= Bc are zero).
+hipError_t launch_range_bits(const int64_t *indptr, const int32_t *spos, const int32_t *scum,
+                             const int32_t *lo, const int32_t *hi, int32_t slot0, int32_t Bc,
+                             int64_t kpad, int32_t n, int32_t n_pad, uint8_t *P, hipStream_t st);
+
 // Matrix-core path (unweighted).  Presence bits P[n_pad][k_pad / 8] (bit b % 8 of byte b / 8
 // per branch slot b), bf16 length splits hi/lo[k_pad], upper-triangular GM x GM output tiles.
 struct MfmaGeom {
@@ -163,9 +184,10 @@ hipError_t launch_split_lengths(const double *len, int32_t B, int64_t k_pad, uin
                                 uint16_t *lo, hipStream_t st);
 hipError_t launch_bits_transpose(const uint32_t *bits, int64_t bstride, const MfmaGeom &g,
                                  uint8_t *Pb, hipStream_t st);
+// accum != 0: the products of this launch are added into S and T (a later chunk of branches)
 hipError_t launch_mfma_gemm(const uint8_t *P, const uint16_t *hi, const uint16_t *lo,
                             int32_t k_chunk, const int32_t *tiles_xy, const MfmaGeom &g,
-                            double *S, double *T, int32_t variant, hipStream_t st);
+                            double *S, double *T, int32_t variant, hipStream_t st, int32_t accum = 0);
 hipError_t launch_mfma_normalize(const double *S, const double *T, int32_t n, int32_t out_f32,
                                  void *out, hipStream_t st);
 // One job of the matrix-core path, for the single-job and queued kernels.
@@ -175,6 +197,7 @@ struct MfmaArgs {
     int32_t n_kstep, chunk_steps;
     const uint16_t *hi, *lo;    // bf16 splits [k_pad]
     int32_t n, n_tiles;
+    int32_t accum, pad;         // accum != 0: add into S and T instead of storing first
     double *S, *T;              // condensed shared lengths, per-sample totals
     const int2 *tiles;          // (I, J) tile list of this job
 };

@@ -95,6 +95,8 @@ struct uf_context {
     int32_t device = 0;
     int32_t n_cu = 256;      // compute units of the device
     std::string err;
+    // knobs chosen by uf_autotune, by problem kind and size bucket (tune_key)
+    std::map<std::string, uf_tuning> tune;
 };
 
 struct uf_plan {
@@ -110,6 +112,13 @@ struct uf_plan {
     int64_t cstride = 0;  // count elements per row (multiple of 64)
     int32_t cw = 4;       // bytes per count of the last propagation: 4 (int32) or 2 (uint16)
     int64_t bstride = 0;  // uint32 words per presence row (multiple of 4)
+    // generated rows: when all count rows (or presence bits) would not fit, batches of them
+    // are computed from depth-first tip ranges on a second stream, double-buffered
+    int64_t mem_limit = 0;   // device bytes the plan may hold (0: whatever the device has)
+    bool gen_ready = false;
+    ufmi::DevMem gen_spos, gen_scum, gen_lo, gen_hi, gen_buf[2];
+    hipStream_t gen_stream = nullptr;
+    hipEvent_t gen_start = nullptr, gen_filled[2] = {}, gen_used[2] = {};
 };
 
 namespace ufmi {
@@ -174,5 +183,33 @@ int32_t resolve_count_width(const HostPrep &hp, int32_t requested);
 uf_status propagate_bits(uf_plan *plan, hipStream_t st);
 uf_status plan_prepare(uf_context *ctx, const uf_tree *tree, const uf_table *table,
                        hipStream_t st, uf_plan **out);
+
+// Resolved knobs of one distance call (uf_tuning with the defaults filled in).
+struct Knobs {
+    int32_t emb_batch, k_chunk, den_mode, variant, tile, count_width, k_split;
+};
+Knobs resolve_knobs(const uf_tuning *t, uf_precision prec, int32_t n_branches);
+uf_status check_enums(uf_context *ctx, uf_method method, uf_precision prec);
+
+// Device buffers of the fused striped path: count rows, reciprocal totals, stripe state
+// copies, per-sample sums and their partial-sum scratch.
+struct StripedWork {
+    void *C;
+    double *inv_t, *num, *den, *D, *part;
+};
+uf_status propagate_counts_into(uf_plan *plan, void *C, int32_t cw, hipStream_t st);
+StripeGeom striped_geometry(const uf_plan *plan, uf_precision prec, const Knobs &kn);
+size_t striped_state_bytes(const StripeGeom &g, int32_t s_begin, int32_t s_end, int32_t *t0, int32_t *t1);
+int32_t striped_k_split(const uf_plan *plan, const Knobs &kn, const StripeGeom &g, int32_t t0, int32_t t1,
+                        size_t state);
+uf_status striped_core(uf_plan *plan, uf_method method, uf_precision prec, const Knobs &kn,
+                       const StripeGeom &g, int32_t t0, int32_t t1, int32_t kz, size_t state,
+                       int32_t cw, const StripedWork &W, hipStream_t st);
+
+// Context tune cache: key of a (method, precision) problem with n samples and n_nodes nodes
+// (log2 buckets of both), and the stored knobs for it (nullptr when none).
+std::string tune_key(uf_method method, uf_precision prec, int32_t n_samples, int32_t n_nodes);
+const uf_tuning *tuned_knobs(const uf_context *ctx, uf_method method, uf_precision prec,
+                             int32_t n_samples, int32_t n_nodes);
 
 }  // namespace ufmi

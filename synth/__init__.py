@@ -21,5 +21,6 @@ from .generators import (  # noqa: F401
     batch_job_specs,
     WORKLOADS,
     build_job,
+    build_jobs,
     permutations,
 )

@@ -19,6 +19,7 @@ Representation shared by all consumers:
 """
 from __future__ import annotations
 
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -343,6 +344,26 @@ def batch_job_specs(n_jobs: int = 64, seed: int | None = None, n_range=(200, 800
 
 def build_job(spec: dict) -> Problem:
     return _build(spec, make_rng(spec["seed"]))
+
+
+def build_jobs(specs: list[dict], workers: int = 0) -> list[Problem]:
+    """build_job for every spec, in a pool of fresh interpreter processes (spawned, so no
+    state of the calling process, such as an open GPU, is inherited).  Every job comes from
+    its own seed, so the result does not depend on the number of workers.  workers <= 0:
+    one per CPU, at most 16; 1: in this process."""
+    if workers <= 0:
+        workers = min(16, os.cpu_count() or 1, len(specs))
+    if workers <= 1 or len(specs) <= 1:
+        return [build_job(s) for s in specs]
+    import multiprocessing as mp
+    # largest jobs first so the pool's tail is short; results go back in spec order
+    order = sorted(range(len(specs)), key=lambda j: -int(specs[j]["n"]) * int(specs[j]["tips"]))
+    with mp.get_context("spawn").Pool(workers) as pool:
+        built = pool.map(build_job, [specs[j] for j in order], chunksize=1)
+    out: list = [None] * len(specs)
+    for j, prob in zip(order, built):
+        out[j] = prob
+    return out
 
 
 def permutations(n: int, n_perm: int, seed: int) -> np.ndarray:

@@ -151,3 +151,52 @@ def test_autotune_picks_valid_knobs_and_caches(uf, ctx, tmp_path, method, prec):
     best2, ms2 = plan.autotune(method, prec, reps=2, cache_path=cache)   # served from the cache
     assert best2 == best and ms2 == pytest.approx(ms, rel=1e-5)
     assert len(cache.read_text().strip().splitlines()) == 1
+
+
+@pytest.mark.parametrize("tile", [0, 1, 2])
+@pytest.mark.parametrize("den_mode", [0, 1])
+def test_batch_dyadic_bit_identical(uf, ctx, den_mode, tile):
+    """The queue-driven kernels on dyadic inputs (lengths m/256, rarefaction depth 256):
+    every partial sum is exact, so every job equals the oracle bit for bit."""
+    import torch
+    probs = [workload_problem("binary_256", n=n, tips=t, p_nonzero=0.3, depth=256, dyadic=True, seed=s)
+             for n, t, s in ((170, 500, 301), (33, 900, 302), (260, 300, 303))]
+    kinds = [("weighted_normalized", "fp32"), ("unweighted", "fp64"), ("weighted_normalized", "fp64"),
+             ("unweighted", "fp32")]
+    jobs = [(p, m, pr) for p in probs for m, pr in kinds]
+    outs = _outs(jobs)
+    b = uf.Batch(ctx, [dict(problem=p, method=m, precision=pr, out=o) for (p, m, pr), o in zip(jobs, outs)],
+                 tuning=dict(den_mode=den_mode, tile=tile, emb_batch=64))
+    b.run()
+    torch.cuda.synchronize()
+    for (p, m, pr), o in zip(jobs, outs):
+        want = oracle.problem_condensed(p, oracle.UNWEIGHTED if m == "unweighted" else oracle.WEIGHTED_NORMALIZED)
+        np.testing.assert_array_equal(o.cpu().numpy(), want)
+    b.close()
+
+
+def test_batch_int32_counts_deep_batches_and_unnormalized(uf, ctx):
+    """Paths the small batch above does not reach: sample totals above 65,535 (the int32
+    count-row queue), FP32 batches of 512 branches, and weighted-unnormalized jobs."""
+    import torch
+    big = workload_problem("binary_256", n=150, tips=3000, p_nonzero=0.9, nb_mean=40.0, depth=70000, seed=305)
+    small = workload_problem("binary_256", n=120, tips=2500, p_nonzero=0.2, depth=500, seed=306)
+    kinds = [("weighted_normalized", "fp32"), ("unweighted", "fp32"), ("weighted_unnormalized", "fp64"),
+             ("weighted_unnormalized", "fp32"), ("unweighted", "fp64")]
+    jobs = [(p, m, pr) for p in (big, small) for m, pr in kinds]
+    outs = _outs(jobs)
+    b = uf.Batch(ctx, [dict(problem=p, method=m, precision=pr, out=o) for (p, m, pr), o in zip(jobs, outs)],
+                 tuning=dict(emb_batch=512, den_mode=1, tile=2))
+    b.run()
+    torch.cuda.synchronize()
+    om = {"unweighted": oracle.UNWEIGHTED, "weighted_normalized": oracle.WEIGHTED_NORMALIZED,
+          "weighted_unnormalized": oracle.WEIGHTED_UNNORMALIZED}
+    for (p, m, pr), o in zip(jobs, outs):
+        want = oracle.problem_condensed(p, om[m])
+        got = o.cpu().numpy()
+        err = np.abs(got - want).max()
+        # unnormalized values are branch lengths: the bar is relative to max(1, |d|)
+        tol = TOL[pr] * (max(1.0, float(np.abs(want).max())) if m == "weighted_unnormalized" else 1.0)
+        print(f"[int32/E512] n={p.n_samples} {m} {pr} max_abs_err={err:.3e} (tol {tol:.1e})", flush=True)
+        assert err <= tol, (p.n_samples, m, pr, err)
+    b.close()

@@ -413,3 +413,19 @@ def test_count_width_16_rejects_large_totals(uf, ctx):
     got = plan.distance(WN, "fp64")          # auto picks int32 rows here
     want = oracle.problem_condensed(big, oracle.WEIGHTED_NORMALIZED)
     assert np.abs(got - want).max() <= 1e-12
+
+
+@pytest.mark.parametrize("tile", [0, 1, 2])
+@pytest.mark.parametrize("den_mode", [0, 1])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("method", [UW, WN])
+def test_dyadic_bit_identical_every_form(uf, ctx, method, prec, den_mode, tile):
+    """Every tile shape and both denominator forms (numerator and denominator stripes, or
+    the per-sample denominator), with automatic branch splits: dyadic inputs leave nothing
+    to round, so each must equal the oracle bit for bit."""
+    prob = workload_problem("binary_256", n=300, tips=600, p_nonzero=0.3, depth=256, dyadic=True, seed=91)
+    plan = _plan(uf, ctx, prob)
+    want = oracle.problem_condensed(prob, OMETHOD[method])
+    for E in (64, 128):
+        got = plan.distance(method, prec, tuning=dict(den_mode=den_mode, tile=tile, emb_batch=E))
+        np.testing.assert_array_equal(got, want)
