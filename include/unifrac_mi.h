@@ -207,13 +207,34 @@ uf_status uf_plan_distance(uf_plan *plan, uf_method method, uf_precision prec,
  * (Section 1; Table 2 runs 128 and 4 chunks).  Computes only stripes [s_begin, s_end)
  * (0 <= s_begin <= s_end <= n/2) and writes the distances of the pairs those stripes hold
  * into `out`, a FULL condensed array of n*(n-1)/2 elements; all other entries are left
- * as they were (host outputs are staged through the device to keep them).  Ranges that
- * partition [0, n/2) fill the whole matrix with exactly the values of uf_plan_distance
- * (same per-element arithmetic).  Striped precisions only; tuning->variant is ignored. */
+ * as they were.  A host output receives only the range's pairs: they are laid out
+ * compactly in condensed order on the device, copied back once, and each condensed row's
+ * (at most two) runs copied into place.  Ranges that partition [0, n/2) fill the whole
+ * matrix with exactly the values of uf_plan_distance (same per-element arithmetic).
+ * Striped precisions only; tuning->variant is ignored. */
 uf_status uf_plan_distance_stripes(uf_plan *plan, uf_method method, uf_precision prec,
                                    const uf_tuning *tuning, int32_t s_begin, int32_t s_end,
                                    uf_dtype out_dtype, void *out, int32_t out_on_device,
                                    void *stream);
+
+/* The same stripe range as a compact block, the partial result one chunk job keeps or
+ * ships (Section 1, Table 2): out is [s_end - s_begin][n] values of out_dtype, row r,
+ * column k = distance of the pair (k, (k + s_begin + r + 1) mod n); for even n the last
+ * stripe's columns k >= n/2 repeat its first half.  Host or device output.  Blocks from
+ * independent plans, contexts or processes assemble into the full matrix with
+ * uf_merge_block. */
+uf_status uf_plan_distance_block(uf_plan *plan, uf_method method, uf_precision prec,
+                                 const uf_tuning *tuning, int32_t s_begin, int32_t s_end,
+                                 uf_dtype out_dtype, void *out, int32_t out_on_device, void *stream);
+
+/* Merge of a block of uf_plan_distance_block (stripes [s_begin, s_end) of an n-sample
+ * problem, [s_end - s_begin][n] values of dtype, host or device) into `condensed`, a DEVICE
+ * array of n*(n-1)/2 values of dtype: the block's pairs are written, every other entry is
+ * left as it was.  Blocks of ranges that partition [0, n/2) reproduce uf_plan_distance bit
+ * for bit.  A host block is staged through a device buffer allocated for the call.
+ * Blocks until done. */
+uf_status uf_merge_block(uf_context *ctx, int32_t n, int32_t s_begin, int32_t s_end, uf_dtype dtype,
+                         const void *block, int32_t block_on_device, void *condensed, void *stream);
 
 /* Raw stripe accumulators of the striped path (for inspection): num and den, each
  * [n_stripes][n_samples] FP64 row-major on the host, where row s, column k holds the sums

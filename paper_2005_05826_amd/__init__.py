@@ -16,6 +16,7 @@ from .binding import (  # noqa: F401
     distance,
     library,
     mantel,
+    merge_block,
     validate,
     validate_problem,
 )

@@ -51,7 +51,7 @@ EXPORTED = ["uf_status_string", "uf_last_error", "uf_validate", "uf_context_crea
             "uf_batch_set_profiling", "uf_batch_get_profile", "uf_batch_destroy",
             "uf_distance_batch", "uf_mantel", "uf_distance", "uf_debug_embedding_counts",
             "uf_autotune", "uf_autotune_lookup",
-            "uf_plan_set_memory_limit"]
+            "uf_plan_set_memory_limit", "uf_plan_distance_block", "uf_merge_block"]
 
 
 class UfTree(ctypes.Structure):
@@ -117,6 +117,9 @@ _lib.uf_autotune.argtypes = [c_p, ctypes.POINTER(UfJob), c_i32]
 _lib.uf_autotune_lookup.argtypes = [c_p, ctypes.c_int, ctypes.c_int, c_i32, c_i32, ctypes.POINTER(UfTuning),
                                     ctypes.POINTER(c_i32)]
 _lib.uf_plan_set_memory_limit.argtypes = [c_p, c_i64]
+_lib.uf_plan_distance_block.argtypes = [c_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(UfTuning),
+                                        c_i32, c_i32, ctypes.c_int, c_p, c_i32, c_p]
+_lib.uf_merge_block.argtypes = [c_p, c_i32, c_i32, c_i32, ctypes.c_int, c_p, c_i32, c_p, c_p]
 _lib.uf_debug_embedding_counts.argtypes = [c_p, ctypes.POINTER(UfTree), ctypes.POINTER(UfTable), c_p]
 _lib.uf_batch_create.argtypes = [c_p, ctypes.POINTER(UfJob), c_i32, ctypes.POINTER(UfTuning), c_p,
                                  ctypes.POINTER(c_p)]
@@ -137,7 +140,8 @@ for _name in ("uf_validate", "uf_context_create", "uf_plan_create", "uf_plan_que
               "uf_plan_embedding_presence", "uf_plan_distance", "uf_plan_distance_stripes", "uf_plan_stripes", "uf_plan_trim", "uf_plan_set_profiling",
               "uf_plan_get_profile", "uf_plan_autotune", "uf_batch_create", "uf_batch_run", "uf_batch_capture",
               "uf_batch_set_profiling", "uf_batch_get_profile", "uf_distance_batch",
-              "uf_distance"):
+              "uf_distance", "uf_debug_embedding_counts", "uf_autotune", "uf_autotune_lookup",
+              "uf_plan_set_memory_limit", "uf_plan_distance_block", "uf_merge_block"):
     getattr(_lib, _name).restype = ctypes.c_int
 
 
@@ -350,6 +354,27 @@ class Plan:
                                                       _stream_handle(stream)))
         return out
 
+    def distance_block(self, s_begin, s_end, method="unweighted", precision="fp64", out=None,
+                       out_dtype="f64", tuning=None, stream=None):
+        """Stripes [s_begin, s_end) as a dense [s_end - s_begin][n] block (numpy array, or
+        `out`: a numpy array or device tensor of that many elements)."""
+        n = self.info.n_samples
+        rows = int(s_end) - int(s_begin)
+        if out is None:
+            out = np.empty((rows, n), np.float64 if out_dtype == "f64" else np.float32)
+        if isinstance(out, np.ndarray):
+            if out.size != rows * n or not out.flags.c_contiguous:
+                raise ValueError("out must be a contiguous array of (s_end - s_begin) * n elements")
+            ptr, on_dev = _ptr(out), 0
+        else:
+            if out.numel() != rows * n or not out.is_contiguous():
+                raise ValueError("out must be a contiguous tensor of (s_end - s_begin) * n elements")
+            ptr, on_dev = c_p(out.data_ptr()), 1
+        self.ctx._check(_lib.uf_plan_distance_block(self._h, METHODS[method], PRECISIONS[precision],
+                                                    _tuning(tuning), int(s_begin), int(s_end),
+                                                    DTYPES[out_dtype], ptr, on_dev, _stream_handle(stream)))
+        return out
+
     def stripes(self, method="unweighted", precision="fp64", tuning=None, stream=None):
         S, n = self.info.n_stripes, self.info.n_samples
         num = np.empty((S, n), np.float64)
@@ -479,6 +504,19 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def merge_block(ctx: Context, n, s_begin, s_end, block, condensed, dtype="f64", stream=None):
+    """uf_merge_block: scatter a stripe block (numpy array or device tensor) into the
+    condensed device tensor `condensed`."""
+    if isinstance(block, np.ndarray):
+        bptr, on_dev = _ptr(np.ascontiguousarray(block)), 0
+        keep = block
+    else:
+        bptr, on_dev = c_p(block.data_ptr()), 1
+    ctx._check(_lib.uf_merge_block(ctx.handle, int(n), int(s_begin), int(s_end), DTYPES[dtype], bptr, on_dev,
+                                   c_p(condensed.data_ptr()), _stream_handle(stream)))
+    return condensed
 
 
 def mantel(ctx: Context, x, y, n: int, perms=None, stream=None):

@@ -24,6 +24,22 @@ using namespace ufmi;
 
 namespace ufmi {
 
+void range_row_runs(int32_t n, int32_t s_begin, int32_t s_end, std::vector<int32_t> *len_a,
+                    std::vector<int32_t> *len_b, std::vector<int64_t> *off)
+{
+    const int32_t S = n / 2;
+    len_a->assign(n, 0);
+    len_b->assign(n, 0);
+    off->assign((size_t)n + 1, 0);
+    const int32_t a_hi = std::min(s_end, S), b_lo = std::max(n - s_end, S + 1), b_hi = n - 1 - s_begin;
+    for (int32_t i = 0; i < n; ++i) {
+        const int32_t lim = n - 1 - i;   // largest distance j - i in row i
+        (*len_a)[i] = std::max(0, std::min(a_hi, lim) - s_begin);
+        (*len_b)[i] = std::max(0, std::min(b_hi, lim) - b_lo + 1);
+        (*off)[i + 1] = (*off)[i] + (*len_a)[i] + (*len_b)[i];
+    }
+}
+
 int32_t resolve_count_width(const HostPrep &hp, int32_t requested)
 {
     int32_t max_total = 0;
@@ -871,12 +887,10 @@ uf_status uf_plan_distance(uf_plan *plan, uf_method method, uf_precision prec,
     return UF_OK;
 }
 
-uf_status uf_plan_distance_stripes(uf_plan *plan, uf_method method, uf_precision prec,
-                                   const uf_tuning *tuning, int32_t s_begin, int32_t s_end,
-                                   uf_dtype out_dtype, void *out, int32_t out_on_device,
-                                   void *stream)
+// Checks and knobs shared by the stripe-range entry points.
+static uf_status range_setup(uf_plan *plan, uf_method method, uf_precision prec, const uf_tuning *tuning,
+                             int32_t s_begin, int32_t s_end, uf_dtype out_dtype, Knobs *kn)
 {
-    if (!plan) return set_err(nullptr, UF_E_ARG, "plan must not be NULL");
     uf_context *ctx = plan->ctx;
     uf_status s = check_enums(ctx, method, prec);
     if (s != UF_OK) return s;
@@ -884,28 +898,44 @@ uf_status uf_plan_distance_stripes(uf_plan *plan, uf_method method, uf_precision
         return set_err(ctx, UF_E_ARG, "stripe ranges exist for the striped precisions only");
     if (out_dtype != UF_F64 && out_dtype != UF_F32) return set_err(ctx, UF_E_ARG, "unknown dtype");
     const HostPrep &hp = plan->hp;
-    const int32_t S = hp.n_samples / 2;
-    if (s_begin < 0 || s_end > S || s_begin > s_end)
+    if (s_begin < 0 || s_end > hp.n_samples / 2 || s_begin > s_end)
         return set_err(ctx, UF_E_ARG, "stripe range must satisfy 0 <= s_begin <= s_end <= n/2");
+    if (!tuning) tuning = tuned_knobs(ctx, method, prec, hp.n_samples, hp.n_nodes);
+    *kn = resolve_knobs(tuning, prec, hp.n_nodes - 1);
+    if (kn->den_mode != 0 && kn->den_mode != 1) return set_err(ctx, UF_E_ARG, "den_mode must be 0 or 1");
+    if (kn->tile < 0 || kn->tile > 2) return set_err(ctx, UF_E_ARG, "tile must be 0, 1 or 2");
+    if (kn->k_split < 0 || kn->k_split > 64) return set_err(ctx, UF_E_ARG, "k_split must be in [0, 64]");
+    kn->variant = 0;
+    if (method == UF_WEIGHTED_UNNORMALIZED) kn->den_mode = 1;
+    return UF_OK;
+}
+
+uf_status uf_plan_distance_stripes(uf_plan *plan, uf_method method, uf_precision prec,
+                                   const uf_tuning *tuning, int32_t s_begin, int32_t s_end,
+                                   uf_dtype out_dtype, void *out, int32_t out_on_device,
+                                   void *stream)
+{
+    if (!plan) return set_err(nullptr, UF_E_ARG, "plan must not be NULL");
+    uf_context *ctx = plan->ctx;
+    Knobs kn;
+    uf_status s = range_setup(plan, method, prec, tuning, s_begin, s_end, out_dtype, &kn);
+    if (s != UF_OK) return s;
     if (s_begin == s_end) return UF_OK;
     if (!out) return set_err(ctx, UF_E_ARG, "out must not be NULL");
-    if (!tuning) tuning = tuned_knobs(ctx, method, prec, hp.n_samples, hp.n_nodes);
-    Knobs kn = resolve_knobs(tuning, prec, hp.n_nodes - 1);
-    if (kn.den_mode != 0 && kn.den_mode != 1) return set_err(ctx, UF_E_ARG, "den_mode must be 0 or 1");
-    if (kn.tile < 0 || kn.tile > 2) return set_err(ctx, UF_E_ARG, "tile must be 0, 1 or 2");
-    if (kn.k_split < 0 || kn.k_split > 64) return set_err(ctx, UF_E_ARG, "k_split must be in [0, 64]");
-    kn.variant = 0;
-    if (method == UF_WEIGHTED_UNNORMALIZED) kn.den_mode = 1;
+    const HostPrep &hp = plan->hp;
+    const int32_t n = hp.n_samples;
     UF_TRY(enter_device(ctx->device), "hipSetDevice");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const int64_t n_pairs = (int64_t)hp.n_samples * (hp.n_samples - 1) / 2;
     const size_t esz = out_dtype == UF_F32 ? sizeof(float) : sizeof(double);
-    void *dst = out;
-    if (!out_on_device) {   // staging keeps the entries this range does not write
-        UF_TRY(plan->out_tmp.ensure((size_t)n_pairs * esz), "allocating output staging");
-        dst = plan->out_tmp.p;
-        UF_TRY(hipMemcpyAsync(dst, out, (size_t)n_pairs * esz, hipMemcpyHostToDevice, st),
-               "staging output");
+    // host output: the range's pairs are written compactly in condensed order on the
+    // device, copied back once, and each row's (at most two) runs copied into place
+    std::vector<int32_t> len_a, len_b;
+    std::vector<int64_t> off;
+    DevMem row_off;
+    if (!out_on_device) {
+        range_row_runs(n, s_begin, s_end, &len_a, &len_b, &off);
+        UF_TRY(upload(row_off, off, st), "uploading row offsets");
+        UF_TRY(plan->out_tmp.ensure((size_t)std::max<int64_t>(off[n], 1) * esz), "allocating output staging");
     }
     StripeGeom g;
     int32_t s_base = 0;
@@ -914,15 +944,91 @@ uf_status uf_plan_distance_stripes(uf_plan *plan, uf_method method, uf_precision
     UF_TRY(timed(plan, "condense", st, [&] {
                return launch_condense_range(method, plan->num.as<double>(),
                                             kn.den_mode == 0 ? plan->den.as<double>() : nullptr,
-                                            kn.den_mode == 0 ? nullptr : plan->D.as<double>(),
-                                            g.sstride, g.n, g.S, s_base, s_begin, s_end,
-                                            out_dtype == UF_F32, dst, st);
+                                            kn.den_mode == 0 ? nullptr : plan->D.as<double>(), g.sstride, g.n,
+                                            g.S, s_base, s_begin, s_end, out_dtype == UF_F32,
+                                            out_on_device ? out : plan->out_tmp.p, st, out_on_device ? 0 : 2,
+                                            out_on_device ? nullptr : row_off.as<int64_t>());
            }), "condense");
-    if (!out_on_device)
-        UF_TRY(hipMemcpyAsync(out, dst, (size_t)n_pairs * esz, hipMemcpyDeviceToHost, st),
-               "copying distances out");
+    if (!out_on_device) {
+        std::vector<unsigned char> stage((size_t)off[n] * esz);
+        if (off[n] > 0)
+            UF_TRY(hipMemcpyAsync(stage.data(), plan->out_tmp.p, stage.size(), hipMemcpyDeviceToHost, st),
+                   "copying distances out");
+        UF_TRY(hipStreamSynchronize(st), "synchronizing");
+        unsigned char *dst = static_cast<unsigned char *>(out);
+        const int32_t S = n / 2, b_lo = std::max(n - s_end, S + 1);
+        for (int32_t i = 0; i < n; ++i) {
+            const int64_t row = (int64_t)n * i - (int64_t)i * (i + 1) / 2;   // condensed index of (i, i + 1)
+            if (len_a[i] > 0)
+                std::memcpy(dst + (size_t)(row + s_begin) * esz, stage.data() + (size_t)off[i] * esz,
+                            (size_t)len_a[i] * esz);
+            if (len_b[i] > 0)
+                std::memcpy(dst + (size_t)(row + b_lo - 1) * esz,
+                            stage.data() + (size_t)(off[i] + len_a[i]) * esz, (size_t)len_b[i] * esz);
+        }
+    }
     UF_TRY(hipStreamSynchronize(st), "synchronizing");
     if (plan->prof.on) plan->prof.collect();
+    return UF_OK;
+}
+
+uf_status uf_plan_distance_block(uf_plan *plan, uf_method method, uf_precision prec,
+                                 const uf_tuning *tuning, int32_t s_begin, int32_t s_end,
+                                 uf_dtype out_dtype, void *out, int32_t out_on_device, void *stream)
+{
+    if (!plan) return set_err(nullptr, UF_E_ARG, "plan must not be NULL");
+    uf_context *ctx = plan->ctx;
+    Knobs kn;
+    uf_status s = range_setup(plan, method, prec, tuning, s_begin, s_end, out_dtype, &kn);
+    if (s != UF_OK) return s;
+    const int32_t n = plan->hp.n_samples;
+    if (s_begin == s_end || n < 2) return UF_OK;
+    if (!out) return set_err(ctx, UF_E_ARG, "out must not be NULL");
+    UF_TRY(enter_device(ctx->device), "hipSetDevice");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t bytes = (size_t)(s_end - s_begin) * n * (out_dtype == UF_F32 ? sizeof(float) : sizeof(double));
+    void *dst = out;
+    if (!out_on_device) {
+        UF_TRY(plan->out_tmp.ensure(bytes), "allocating output staging");
+        dst = plan->out_tmp.p;
+    }
+    StripeGeom g;
+    int32_t s_base = 0;
+    s = run_striped(plan, method, prec, kn, &g, st, s_begin, s_end, &s_base);
+    if (s != UF_OK) return s;
+    UF_TRY(timed(plan, "condense", st, [&] {
+               return launch_condense_range(method, plan->num.as<double>(),
+                                            kn.den_mode == 0 ? plan->den.as<double>() : nullptr,
+                                            kn.den_mode == 0 ? nullptr : plan->D.as<double>(), g.sstride, g.n,
+                                            g.S, s_base, s_begin, s_end, out_dtype == UF_F32, dst, st, 1);
+           }), "condense");
+    if (!out_on_device) UF_TRY(hipMemcpyAsync(out, dst, bytes, hipMemcpyDeviceToHost, st), "copying the block out");
+    UF_TRY(hipStreamSynchronize(st), "synchronizing");
+    if (plan->prof.on) plan->prof.collect();
+    return UF_OK;
+}
+
+uf_status uf_merge_block(uf_context *ctx, int32_t n, int32_t s_begin, int32_t s_end, uf_dtype dtype,
+                         const void *block, int32_t block_on_device, void *condensed, void *stream)
+{
+    if (!ctx) return set_err(nullptr, UF_E_ARG, "ctx must not be NULL");
+    if (dtype != UF_F64 && dtype != UF_F32) return set_err(ctx, UF_E_ARG, "unknown dtype");
+    if (n < 0 || s_begin < 0 || s_end > n / 2 || s_begin > s_end)
+        return set_err(ctx, UF_E_ARG, "stripe range must satisfy 0 <= s_begin <= s_end <= n/2");
+    if (s_begin == s_end || n < 2) return UF_OK;
+    if (!block || !condensed) return set_err(ctx, UF_E_ARG, "block and condensed must not be NULL");
+    UF_TRY(enter_device(ctx->device), "hipSetDevice");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t bytes = (size_t)(s_end - s_begin) * n * (dtype == UF_F32 ? sizeof(float) : sizeof(double));
+    DevMem staged;
+    const void *src = block;
+    if (!block_on_device) {
+        UF_TRY(staged.ensure(bytes), "allocating block staging");
+        UF_TRY(hipMemcpyAsync(staged.p, block, bytes, hipMemcpyHostToDevice, st), "staging the block");
+        src = staged.p;
+    }
+    UF_TRY(launch_merge_block(src, n, s_begin, s_end, dtype == UF_F32, condensed, st), "merging the block");
+    UF_TRY(hipStreamSynchronize(st), "synchronizing");
     return UF_OK;
 }
 

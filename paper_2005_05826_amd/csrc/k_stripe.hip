@@ -508,16 +508,26 @@ __global__ void k_condense(const double *__restrict__ num, const double *__restr
 }
 
 // Condense of a stripe range [s_begin, s_end) held in a state block whose first row is
-// stripe s_base: each (s, k) writes the pair (k, (k + s + 1) mod n) into the condensed
-// output (for even n the last stripe writes only k < n/2, the first copy of each pair).
-template <int METHOD, typename OUT>
+// stripe s_base: each (s, k) computes the distance of the pair (k, (k + s + 1) mod n) and
+// writes it where the output layout puts it:
+//   RANGE_CONDENSED  the full condensed matrix (for even n the last stripe writes only
+//                    k < n/2, the first copy of each pair);
+//   RANGE_BLOCK      a dense [s_end - s_begin][n] block, every k (the duplicated half of an
+//                    even n's last stripe included);
+//   RANGE_COMPACT    the range's pairs only, in condensed order: row i's pairs start at
+//                    row_off[i], first those at distance j - i <= S (stripe j - i - 1), then
+//                    those beyond (stripe n - (j - i) - 1).
+enum { RANGE_CONDENSED = 0, RANGE_BLOCK = 1, RANGE_COMPACT = 2 };
+
+template <int METHOD, typename OUT, int LAYOUT>
 __global__ void k_condense_range(const double *__restrict__ num, const double *__restrict__ den,
                                  const double *__restrict__ D, int64_t sstride, int32_t n, int32_t S,
-                                 int32_t s_base, int32_t s_begin, OUT *__restrict__ out)
+                                 int32_t s_base, int32_t s_begin, int32_t s_end,
+                                 const int64_t *__restrict__ row_off, OUT *__restrict__ out)
 {
     const int32_t s = s_begin + blockIdx.y;
     const int32_t k = blockIdx.x * kBlock + threadIdx.x;
-    const int32_t kmax = (n % 2 == 0 && s == S - 1) ? n / 2 : n;
+    const int32_t kmax = (LAYOUT != RANGE_BLOCK && n % 2 == 0 && s == S - 1) ? n / 2 : n;
     if (k >= kmax) return;
     const int32_t j = (k + s + 1) % n;
     const int32_t lo = k < j ? k : j, hi = k < j ? j : k;
@@ -536,7 +546,37 @@ __global__ void k_condense_range(const double *__restrict__ num, const double *_
             b = 0.5 * (D[k] + D[j] + a);
         d = (b == 0.0) ? 0.0 : a / b;
     }
-    out[(int64_t)n * lo - (int64_t)lo * (lo + 1) / 2 + (hi - lo - 1)] = (OUT)d;
+    int64_t idx;
+    if (LAYOUT == RANGE_CONDENSED) {
+        idx = (int64_t)n * lo - (int64_t)lo * (lo + 1) / 2 + (hi - lo - 1);
+    } else if (LAYOUT == RANGE_BLOCK) {
+        idx = (int64_t)(s - s_begin) * n + k;
+    } else {
+        const int32_t dist = hi - lo;
+        if (dist <= S) {
+            idx = row_off[lo] + (dist - (s_begin + 1));
+        } else {
+            const int32_t a_end = (s_end < S ? s_end : S) < n - 1 - lo ? (s_end < S ? s_end : S) : n - 1 - lo;
+            const int32_t len_a = a_end - s_begin > 0 ? a_end - s_begin : 0;
+            const int32_t b0 = (n - s_end) > S + 1 ? (n - s_end) : S + 1;
+            idx = row_off[lo] + len_a + (dist - b0);
+        }
+    }
+    out[idx] = (OUT)d;
+}
+
+// Scatter of a dense stripe block (RANGE_BLOCK layout) into the condensed matrix.
+template <typename T>
+__global__ void k_merge_block(const T *__restrict__ block, int32_t n, int32_t S, int32_t s_begin,
+                              T *__restrict__ out)
+{
+    const int32_t s = s_begin + blockIdx.y;
+    const int32_t k = blockIdx.x * kBlock + threadIdx.x;
+    const int32_t kmax = (n % 2 == 0 && s == S - 1) ? n / 2 : n;
+    if (k >= kmax) return;
+    const int32_t j = (k + s + 1) % n;
+    const int32_t lo = k < j ? k : j, hi = k < j ? j : k;
+    out[(int64_t)n * lo - (int64_t)lo * (lo + 1) / 2 + (hi - lo - 1)] = block[(int64_t)(s - s_begin) * n + k];
 }
 
 inline unsigned grid1(int64_t n, int64_t per) { return (unsigned)((n + per - 1) / per); }
@@ -840,19 +880,40 @@ namespace ufmi {
 hipError_t launch_condense_range(int32_t method, const double *num, const double *den, const double *D,
                                  int64_t sstride, int32_t n, int32_t S, int32_t s_base,
                                  int32_t s_begin, int32_t s_end, int32_t out_f32, void *out,
-                                 hipStream_t st)
+                                 hipStream_t st, int32_t layout, const int64_t *row_off)
 {
     if (s_end <= s_begin || n < 2) return hipSuccess;
     dim3 grid(grid1(n, kBlock), (unsigned)(s_end - s_begin));
-#define UF_CR(M, O) k_condense_range<M, O><<<grid, kBlock, 0, st>>>(num, den, D, sstride, n, S, s_base, s_begin, (O *)out)
+#define UF_CR(M, O, L) k_condense_range<M, O, L><<<grid, kBlock, 0, st>>>(num, den, D, sstride, n, S, s_base, s_begin, s_end, row_off, (O *)out)
+#define UF_CRL(M, O)                                                   \
+    do {                                                               \
+        if (layout == RANGE_BLOCK) UF_CR(M, O, RANGE_BLOCK);           \
+        else if (layout == RANGE_COMPACT) UF_CR(M, O, RANGE_COMPACT);  \
+        else UF_CR(M, O, RANGE_CONDENSED);                             \
+    } while (0)
     if (method == UF_WEIGHTED_UNNORMALIZED) {
-        if (out_f32) UF_CR(UF_WEIGHTED_UNNORMALIZED, float); else UF_CR(UF_WEIGHTED_UNNORMALIZED, double);
+        if (out_f32) UF_CRL(UF_WEIGHTED_UNNORMALIZED, float); else UF_CRL(UF_WEIGHTED_UNNORMALIZED, double);
     } else if (method == UF_WEIGHTED_NORMALIZED) {
-        if (out_f32) UF_CR(UF_WEIGHTED_NORMALIZED, float); else UF_CR(UF_WEIGHTED_NORMALIZED, double);
+        if (out_f32) UF_CRL(UF_WEIGHTED_NORMALIZED, float); else UF_CRL(UF_WEIGHTED_NORMALIZED, double);
     } else {
-        if (out_f32) UF_CR(UF_UNWEIGHTED, float); else UF_CR(UF_UNWEIGHTED, double);
+        if (out_f32) UF_CRL(UF_UNWEIGHTED, float); else UF_CRL(UF_UNWEIGHTED, double);
     }
+#undef UF_CRL
 #undef UF_CR
+    return hipGetLastError();
+}
+
+hipError_t launch_merge_block(const void *block, int32_t n, int32_t s_begin, int32_t s_end, int32_t f32,
+                              void *condensed, hipStream_t st)
+{
+    if (s_end <= s_begin || n < 2) return hipSuccess;
+    dim3 grid(grid1(n, kBlock), (unsigned)(s_end - s_begin));
+    if (f32)
+        k_merge_block<float><<<grid, kBlock, 0, st>>>(static_cast<const float *>(block), n, n / 2, s_begin,
+                                                     static_cast<float *>(condensed));
+    else
+        k_merge_block<double><<<grid, kBlock, 0, st>>>(static_cast<const double *>(block), n, n / 2, s_begin,
+                                                      static_cast<double *>(condensed));
     return hipGetLastError();
 }
 

@@ -142,12 +142,22 @@ hipError_t launch_stripe_fused(bool fp64, int32_t method, int32_t den_mode, int3
                                int32_t kz, int64_t zstride, hipStream_t st);
 // x[i] = sum over z of x[z * zstride + i] (z in order), for i < count.
 hipError_t launch_reduce_z(double *x, int64_t zstride, int32_t kz, int64_t count, hipStream_t st);
-// Writes the pairs of stripes [s_begin, s_end) into a full condensed output; the state
-// block's row 0 holds stripe s_base.
+// Writes the pairs of stripes [s_begin, s_end) (the state block's row 0 holds stripe
+// s_base) in one of three layouts: 0 = into a full condensed output; 1 = a dense
+// [s_end - s_begin][n] block; 2 = the range's pairs only, in condensed order, row i's
+// pairs from row_off[i] (range_row_offsets).
 hipError_t launch_condense_range(int32_t method, const double *num, const double *den, const double *D,
                                  int64_t sstride, int32_t n, int32_t S, int32_t s_base,
                                  int32_t s_begin, int32_t s_end, int32_t out_f32, void *out,
-                                 hipStream_t st);
+                                 hipStream_t st, int32_t layout = 0, const int64_t *row_off = nullptr);
+// Scatter of a dense block (layout 1) into the condensed matrix.
+hipError_t launch_merge_block(const void *block, int32_t n, int32_t s_begin, int32_t s_end, int32_t f32,
+                              void *condensed, hipStream_t st);
+// Pairs of stripes [s_begin, s_end) in condensed row i: a run at distances j - i in
+// [s_begin + 1, min(s_end, S)] and a run at distances in [max(n - s_end, S + 1), n - 1 - s_begin],
+// both clipped to j < n.  Fills len_a, len_b (n each) and off (n + 1, prefix sums).
+void range_row_runs(int32_t n, int32_t s_begin, int32_t s_end, std::vector<int32_t> *len_a,
+                    std::vector<int32_t> *len_b, std::vector<int64_t> *off);
 // Per-sample sums D_k = sum_b L_b u_kb over a batch of E branches (separable denominator);
 // `part` holds rowdot_scratch_elems(n, E) doubles of scratch.
 size_t rowdot_scratch_elems(int32_t n, int32_t E);
