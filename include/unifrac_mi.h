@@ -370,6 +370,28 @@ uf_status uf_autotune(uf_context *ctx, const uf_job *representative, int32_t n);
 uf_status uf_autotune_lookup(const uf_context *ctx, uf_method method, uf_precision prec,
                              int32_t n_samples, int32_t n_nodes, uf_tuning *out, int32_t *found);
 
+/* ---- Without device allocation ------------------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  The library holds one fixed scratch
+ * array of UF_NOALLOC_SCRATCH_BYTES on every GPU it runs on (until the process ends); its
+ * address is resolved per device when a context is created there. */
+#define UF_NOALLOC_SCRATCH_BYTES (128u << 20)
+
+/* uf_plan_distance for the striped precisions (UF_PREC_FP64, UF_PREC_FP32) with every
+ * scratch buffer (count rows, reciprocal totals, per-sample sums, stripe state) taken from
+ * that array: no hipMalloc, hipFree, memset node or other allocating call.  `out` is a
+ * DEVICE pointer of n*(n-1)/2 elements of out_dtype.  The knobs are uf_plan_distance's
+ * (fused kernel only; tuning->variant is ignored); the automatic branch split is lowered
+ * until the state copies fit.  Returns UF_E_ARG when the problem needs more scratch than the
+ * array holds (the message gives the size), UF_E_UNSUPPORTED for UF_PREC_MFMA_BF16X2.
+ * Asynchronous: the work is enqueued on `stream` and `out` is complete when the stream's
+ * work is.  Every call on one GPU shares its array and leaves its contents behind (each
+ * call clears what must start at zero), so calls that overlap on one GPU, from several
+ * streams or threads, race: serialize them. */
+uf_status uf_plan_distance_noalloc(uf_plan *plan, uf_method method, uf_precision prec,
+                                   const uf_tuning *tuning, uf_dtype out_dtype, void *out,
+                                   void *stream);
+
 #ifdef __cplusplus
 }
 #endif

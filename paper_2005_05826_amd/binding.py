@@ -50,7 +50,7 @@ EXPORTED = ["uf_status_string", "uf_last_error", "uf_validate", "uf_context_crea
             "uf_plan_get_profile", "uf_plan_autotune", "uf_batch_create", "uf_batch_run", "uf_batch_capture",
             "uf_batch_set_profiling", "uf_batch_get_profile", "uf_batch_destroy",
             "uf_distance_batch", "uf_mantel", "uf_distance", "uf_debug_embedding_counts",
-            "uf_autotune", "uf_autotune_lookup",
+            "uf_autotune", "uf_autotune_lookup", "uf_plan_distance_noalloc",
             "uf_plan_set_memory_limit", "uf_plan_distance_block", "uf_merge_block"]
 
 
@@ -116,6 +116,8 @@ _lib.uf_plan_autotune.argtypes = [c_p, ctypes.c_int, ctypes.c_int, ctypes.POINTE
 _lib.uf_autotune.argtypes = [c_p, ctypes.POINTER(UfJob), c_i32]
 _lib.uf_autotune_lookup.argtypes = [c_p, ctypes.c_int, ctypes.c_int, c_i32, c_i32, ctypes.POINTER(UfTuning),
                                     ctypes.POINTER(c_i32)]
+_lib.uf_plan_distance_noalloc.argtypes = [c_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(UfTuning),
+                                          ctypes.c_int, c_p, c_p]
 _lib.uf_plan_set_memory_limit.argtypes = [c_p, c_i64]
 _lib.uf_plan_distance_block.argtypes = [c_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(UfTuning),
                                         c_i32, c_i32, ctypes.c_int, c_p, c_i32, c_p]
@@ -141,7 +143,8 @@ for _name in ("uf_validate", "uf_context_create", "uf_plan_create", "uf_plan_que
               "uf_plan_get_profile", "uf_plan_autotune", "uf_batch_create", "uf_batch_run", "uf_batch_capture",
               "uf_batch_set_profiling", "uf_batch_get_profile", "uf_distance_batch",
               "uf_distance", "uf_debug_embedding_counts", "uf_autotune", "uf_autotune_lookup",
-              "uf_plan_set_memory_limit", "uf_plan_distance_block", "uf_merge_block"):
+              "uf_plan_set_memory_limit", "uf_plan_distance_block", "uf_merge_block",
+              "uf_plan_distance_noalloc"):
     getattr(_lib, _name).restype = ctypes.c_int
 
 
@@ -339,6 +342,19 @@ class Plan:
         self.ctx._check(_lib.uf_plan_distance(self._h, METHODS[method], PRECISIONS[precision],
                                               _tuning(tuning), DTYPES[out_dtype], ptr, on_dev,
                                               _stream_handle(stream)))
+        return out
+
+    def distance_noalloc(self, out, method="unweighted", precision="fp64", out_dtype="f64",
+                         tuning=None, stream=None):
+        """uf_plan_distance_noalloc into a contiguous device tensor `out` of n*(n-1)/2
+        elements; asynchronous on `stream` (torch's current stream by default)."""
+        import torch
+        want = torch.float64 if out_dtype == "f64" else torch.float32
+        if out.numel() != self.info.n_pairs or not out.is_contiguous() or out.dtype != want:
+            raise ValueError("out must be a contiguous device tensor of n*(n-1)/2 elements of out_dtype")
+        self.ctx._check(_lib.uf_plan_distance_noalloc(self._h, METHODS[method], PRECISIONS[precision],
+                                                      _tuning(tuning), DTYPES[out_dtype],
+                                                      c_p(out.data_ptr()), _stream_handle(stream)))
         return out
 
     def distance_stripes(self, s_begin, s_end, out, method="unweighted", precision="fp64",

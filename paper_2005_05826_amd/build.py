@@ -18,7 +18,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libunifrac_mi.so")
 ARCH = os.environ.get("UFMI_ARCH", "gfx950")
 
-SOURCES = ["host_prep.cpp", "api.cpp", "batch.cpp", "autotune.cpp", "k_propagate.hip", "k_generate.hip", "k_stripe.hip", "k_mfma.hip", "k_mantel.hip"]
+SOURCES = ["host_prep.cpp", "api.cpp", "batch.cpp", "autotune.cpp", "noalloc.cpp", "k_propagate.hip", "k_generate.hip", "k_stripe.hip", "k_mfma.hip", "k_mantel.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CFLAGS = ["-x", "hip", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

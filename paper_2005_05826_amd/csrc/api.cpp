@@ -661,6 +661,11 @@ uf_status uf_context_create(int32_t device, uf_context **out)
     uf_context *ctx = new (std::nothrow) uf_context;
     if (!ctx) return set_err(nullptr, UF_E_OOM, "host allocation failed");
     ctx->device = device;
+    e = noalloc_scratch_init(device);   // this device's copy of the fixed scratch array
+    if (e != hipSuccess) {
+        delete ctx;
+        return set_err(nullptr, UF_E_DEVICE, std::string("resolving the device scratch: ") + hipGetErrorString(e));
+    }
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
         ctx->n_cu = cus;

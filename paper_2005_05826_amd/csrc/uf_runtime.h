@@ -206,6 +206,10 @@ uf_status striped_core(uf_plan *plan, uf_method method, uf_precision prec, const
                        const StripeGeom &g, int32_t t0, int32_t t1, int32_t kz, size_t state,
                        int32_t cw, const StripedWork &W, hipStream_t st);
 
+// Resolves this device's copy of the fixed scratch array of uf_plan_distance_noalloc
+// (once per device; the device must be current).
+hipError_t noalloc_scratch_init(int device);
+
 // Context tune cache: key of a (method, precision) problem with n samples and n_nodes nodes
 // (log2 buckets of both), and the stored knobs for it (nullptr when none).
 std::string tune_key(uf_method method, uf_precision prec, int32_t n_samples, int32_t n_nodes);
