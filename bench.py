@@ -123,6 +123,9 @@ def parse(argv=None):
                     help="large-wn: compute 1/share of the stripes (one GPU's share)")
     ap.add_argument("--k-split", type=int, default=0,
                     help="striped: branch ranges over grid z (0 = automatic)")
+    ap.add_argument("--count-width", type=int, default=2,
+                    help="large-wn: bytes per embedding count (2 = 16-bit rows, resident; 4 = "
+                         "int32 rows, 452 GB, generated batch by batch on the device)")
     ap.add_argument("--all-shares", action="store_true",
                     help="large-wn: compute every share in turn, i.e. the full matrix")
     ap.add_argument("--method", default=None)
@@ -631,7 +634,7 @@ def bench_large(args, part):
         out = torch.empty(n_pairs, dtype=torch.float32, device="cuda:0")
         den_mode = 1 if args.den_mode is None else args.den_mode
         tuning = dict(emb_batch=args.emb_batch, den_mode=den_mode,
-                      tile=2 if args.tile is None else args.tile, count_width=2)
+                      tile=2 if args.tile is None else args.tile, count_width=args.count_width)
 
         def step():
             for a, b in ranges:
@@ -664,7 +667,8 @@ def bench_large(args, part):
                                           if len(ranges) > 1 else
                                           f"stripes [{s0}, {s1}) = 1/{args.share} of {S}"),
                            "n_samples": n, "branches": B, "stripes": [s0, s1],
-                           "precision": "fp32", "count_width": 2})
+                           "precision": "fp32", "count_width": args.count_width,
+                           "count_rows": "generated per batch" if prof.get("generate") else "resident"})
         res["roofline"] = {"kernel": "k_stripe_fused", "bound": "alu", "achieved": round(achieved, 3),
                            "peak": round(VALU_PEAK_TOPS["fp32"], 2), "unit": "Tops/s",
                            "frac": round(achieved / VALU_PEAK_TOPS["fp32"], 4), "traffic": None}

@@ -74,12 +74,16 @@ uf_status propagate_counts_into(uf_plan *plan, void *C, int32_t cw, hipStream_t 
                                                     plan->entry_slot.as<int32_t>(),
                                                     plan->entry_count.as<int32_t>(), C, cw,
                                                     plan->cstride, hp.n_samples, st);
-               for (int32_t h = 1; h < hp.n_levels && r == hipSuccess; ++h) {
+               for (int32_t h = 1; h < plan->tail_level && r == hipSuccess; ++h) {
                    const int32_t b = hp.level_ptr[h], e = hp.level_ptr[h + 1];
                    r = launch_level_sum(C, words, b, e - b, hp.n_leaf,
                                         plan->child_ptr.as<int32_t>(),
                                         plan->child_slot.as<int32_t>(), st);
                }
+               if (r == hipSuccess)
+                   r = launch_level_tail(false, static_cast<uint32_t *>(C), words, plan->level_ptr.as<int32_t>(),
+                                         std::max(plan->tail_level, 1), hp.n_levels, hp.n_leaf,
+                                         plan->child_ptr.as<int32_t>(), plan->child_slot.as<int32_t>(), st);
                return r;
            }), "propagating counts");
     return UF_OK;
@@ -99,12 +103,16 @@ uf_status propagate_bits(uf_plan *plan, hipStream_t st)
                                                   plan->entry_slot.as<int32_t>(),
                                                   plan->entry_count.as<int32_t>(), B,
                                                   plan->bstride, hp.n_samples, st);
-               for (int32_t h = 1; h < hp.n_levels && r == hipSuccess; ++h) {
+               for (int32_t h = 1; h < plan->tail_level && r == hipSuccess; ++h) {
                    const int32_t b = hp.level_ptr[h], e = hp.level_ptr[h + 1];
                    r = launch_level_or(B, plan->bstride, b, e - b, hp.n_leaf,
                                        plan->child_ptr.as<int32_t>(),
                                        plan->child_slot.as<int32_t>(), st);
                }
+               if (r == hipSuccess)
+                   r = launch_level_tail(true, B, plan->bstride, plan->level_ptr.as<int32_t>(),
+                                         std::max(plan->tail_level, 1), hp.n_levels, hp.n_leaf,
+                                         plan->child_ptr.as<int32_t>(), plan->child_slot.as<int32_t>(), st);
                return r;
            }), "propagating presence");
     return UF_OK;
@@ -140,6 +148,11 @@ uf_status plan_prepare(uf_context *ctx, const uf_tree *tree, const uf_table *tab
     if (r == hipSuccess) r = upload(plan->child_slot, hp.child_slot, st);
     if (r == hipSuccess) r = upload(plan->len_slot, hp.length_slot, st);
     if (r == hipSuccess) r = upload(plan->slot_of_node, hp.slot_of_node, st);
+    if (r == hipSuccess) r = upload(plan->level_ptr, hp.level_ptr, st);
+    // the narrow top of a deep tree (levels of at most 64 nodes) runs as one launch; a short
+    // narrow top (under eight levels) keeps one launch per level
+    plan->tail_level = narrow_tail_level(hp, 64);
+    if (hp.n_levels - plan->tail_level < 8) plan->tail_level = hp.n_levels;
     if (r == hipSuccess) r = hipStreamSynchronize(st);
     if (r != hipSuccess) {
         uf_plan_destroy(plan);
@@ -688,6 +701,7 @@ void uf_plan_destroy(uf_plan *plan)
     (void)enter_device(plan->ctx->device);
     for (DevMem *m : {&plan->indptr, &plan->entry_slot, &plan->entry_count, &plan->totals,
                       &plan->child_ptr, &plan->child_slot, &plan->len_slot, &plan->slot_of_node,
+                      &plan->level_ptr,
                       &plan->counts, &plan->bits, &plan->emb, &plan->num, &plan->den, &plan->D,
                       &plan->inv_t, &plan->out_tmp, &plan->gather_tmp, &plan->rowdot_part})
         m->release();

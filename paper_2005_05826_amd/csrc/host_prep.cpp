@@ -169,6 +169,13 @@ uf_status validate_and_prepare(const uf_tree *tree, const uf_table *table, HostP
     return UF_OK;
 }
 
+int32_t narrow_tail_level(const HostPrep &hp, int32_t max_nodes)
+{
+    int32_t h = hp.n_levels;
+    while (h > 1 && hp.level_ptr[h] - hp.level_ptr[h - 1] <= max_nodes) --h;
+    return h;
+}
+
 // Euler-tour tables for generating count rows without the level propagation: tips are
 // numbered in depth-first order (children in node-id order), so the tips below any node form
 // one contiguous range [lo, hi) of that order, and a sample's reads below the node are the

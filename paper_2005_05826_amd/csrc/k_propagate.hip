@@ -85,6 +85,43 @@ __global__ void k_level(uint32_t *__restrict__ X, int64_t stride, int32_t n_vec,
     }
 }
 
+// The narrow top of a deep tree, levels [h0, h1) (each with few nodes), in one launch:
+// work-group g owns uint4 columns [g * kTailCols, (g + 1) * kTailCols) of every row and walks
+// the levels in order with a barrier between them.  A node's children sit in lower levels,
+// computed either by earlier launches or by this same work-group for these same columns, so
+// no other work-group is ever waited for; the barrier's workgroup-scope fence makes a
+// level's stores visible to the next level's loads (one CU, one L1).
+constexpr int kTailCols = 16;
+template <bool OR>
+__global__ void k_level_tail(uint32_t *__restrict__ X, int64_t stride, int32_t n_vec,
+                             const int32_t *__restrict__ level_ptr, int32_t h0, int32_t h1, int32_t n_leaf,
+                             const int32_t *__restrict__ child_ptr, const int32_t *__restrict__ child_slot)
+{
+    const int32_t c = blockIdx.x * kTailCols + (int32_t)(threadIdx.x % kTailCols);
+    const int32_t lane = (int32_t)(threadIdx.x / kTailCols);
+    constexpr int32_t kLanes = kBlock / kTailCols;
+    for (int32_t h = h0; h < h1; ++h) {
+        const int32_t b = level_ptr[h], e = level_ptr[h + 1];
+        if (c < n_vec) {
+            for (int32_t slot = b + lane; slot < e; slot += kLanes) {
+                const int32_t i = slot - n_leaf;
+                const int32_t q0 = child_ptr[i], q1 = child_ptr[i + 1];
+                uint4 acc = make_uint4(0u, 0u, 0u, 0u);
+                for (int32_t q = q0; q < q1; ++q) {
+                    const uint4 v = reinterpret_cast<const uint4 *>(X + (int64_t)child_slot[q] * stride)[c];
+                    if (OR) {
+                        acc.x |= v.x; acc.y |= v.y; acc.z |= v.z; acc.w |= v.w;
+                    } else {
+                        acc.x += v.x; acc.y += v.y; acc.z += v.z; acc.w += v.w;
+                    }
+                }
+                reinterpret_cast<uint4 *>(X + (int64_t)slot * stride)[c] = acc;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 __global__ void k_gather_rows_u16(const uint16_t *__restrict__ src, int64_t sstride,
                                   const int32_t *__restrict__ slot_of_node, int32_t n_nodes,
                                   int32_t width, int32_t *__restrict__ out)
@@ -244,6 +281,22 @@ static hipError_t launch_level(bool is_or, uint32_t *X, int64_t stride, int32_t 
     else
         k_level<false><<<grid, kBlock, 0, st>>>(X, stride, n_vec, slot_begin, n_rows, n_leaf,
                                                 child_ptr, child_slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_level_tail(bool is_or, uint32_t *X, int64_t stride_words, const int32_t *level_ptr,
+                             int32_t h0, int32_t h1, int32_t n_leaf, const int32_t *child_ptr,
+                             const int32_t *child_slot, hipStream_t st)
+{
+    if (h1 <= h0) return hipSuccess;
+    const int32_t n_vec = (int32_t)(stride_words / 4);
+    const unsigned groups = grid1(n_vec, kTailCols);
+    if (is_or)
+        k_level_tail<true><<<groups, kBlock, 0, st>>>(X, stride_words, n_vec, level_ptr, h0, h1, n_leaf,
+                                                      child_ptr, child_slot);
+    else
+        k_level_tail<false><<<groups, kBlock, 0, st>>>(X, stride_words, n_vec, level_ptr, h0, h1, n_leaf,
+                                                       child_ptr, child_slot);
     return hipGetLastError();
 }
 

@@ -62,6 +62,15 @@ hipError_t launch_scatter_counts(const int64_t *indptr, const int32_t *entry_slo
 hipError_t launch_level_sum(void *C, int64_t stride_words, int32_t slot_begin, int32_t n_rows,
                             int32_t n_leaf, const int32_t *child_ptr, const int32_t *child_slot,
                             hipStream_t st);
+// Levels [h0, h1) in one launch (sum or OR of the children's rows); every level should be
+// narrow (few nodes), since one work-group walks all of them for its slice of columns.
+// level_ptr: the device copy of HostPrep::level_ptr.
+hipError_t launch_level_tail(bool is_or, uint32_t *X, int64_t stride_words, const int32_t *level_ptr,
+                             int32_t h0, int32_t h1, int32_t n_leaf, const int32_t *child_ptr,
+                             const int32_t *child_slot, hipStream_t st);
+// First level of the narrow top of the tree: every level from it on holds at most
+// `max_nodes` nodes (n_levels when the top level itself is wider).
+int32_t narrow_tail_level(const HostPrep &hp, int32_t max_nodes);
 // out[v][0..width) = (int32) src16[slot_of_node[v]][0..width)
 hipError_t launch_gather_rows_u16(const uint16_t *src, int64_t sstride, const int32_t *slot_of_node,
                                   int32_t n_nodes, int32_t width, int32_t *out, hipStream_t st);

@@ -104,7 +104,8 @@ struct uf_plan {
     ufmi::HostPrep hp;
     // resident inputs
     ufmi::DevMem indptr, entry_slot, entry_count, totals, child_ptr, child_slot, len_slot,
-        slot_of_node;
+        slot_of_node, level_ptr;
+    int32_t tail_level = 0;   // levels from here up run as one launch (narrow_tail_level)
     // scratch, allocated on first use
     ufmi::DevMem counts, bits, emb, num, den, D, inv_t, out_tmp, gather_tmp, rowdot_part;
     ufmi::DevMem mfma_scratch[4];
