@@ -81,9 +81,7 @@ uf_status propagate_counts_into(uf_plan *plan, void *C, int32_t cw, hipStream_t 
                                         plan->child_slot.as<int32_t>(), st);
                }
                if (r == hipSuccess)
-                   r = launch_level_tail(false, static_cast<uint32_t *>(C), words, plan->level_ptr.as<int32_t>(),
-                                         std::max(plan->tail_level, 1), hp.n_levels, hp.n_leaf,
-                                         plan->child_ptr.as<int32_t>(), plan->child_slot.as<int32_t>(), st);
+                   r = launch_level_tail(false, static_cast<uint32_t *>(C), words, plan->tail, st);
                return r;
            }), "propagating counts");
     return UF_OK;
@@ -110,9 +108,7 @@ uf_status propagate_bits(uf_plan *plan, hipStream_t st)
                                        plan->child_slot.as<int32_t>(), st);
                }
                if (r == hipSuccess)
-                   r = launch_level_tail(true, B, plan->bstride, plan->level_ptr.as<int32_t>(),
-                                         std::max(plan->tail_level, 1), hp.n_levels, hp.n_leaf,
-                                         plan->child_ptr.as<int32_t>(), plan->child_slot.as<int32_t>(), st);
+                   r = launch_level_tail(true, B, plan->bstride, plan->tail, st);
                return r;
            }), "propagating presence");
     return UF_OK;
@@ -148,11 +144,23 @@ uf_status plan_prepare(uf_context *ctx, const uf_tree *tree, const uf_table *tab
     if (r == hipSuccess) r = upload(plan->child_slot, hp.child_slot, st);
     if (r == hipSuccess) r = upload(plan->len_slot, hp.length_slot, st);
     if (r == hipSuccess) r = upload(plan->slot_of_node, hp.slot_of_node, st);
-    if (r == hipSuccess) r = upload(plan->level_ptr, hp.level_ptr, st);
     // the narrow top of a deep tree (levels of at most 64 nodes) runs as one launch; a short
     // narrow top (under eight levels) keeps one launch per level
-    plan->tail_level = narrow_tail_level(hp, 64);
-    if (hp.n_levels - plan->tail_level < 8) plan->tail_level = hp.n_levels;
+    plan->tail_level = std::max(narrow_tail_level(hp, 64), 1);
+    TailProgramHost tph;
+    if (hp.n_levels - plan->tail_level < 8 || !tail_program(hp, plan->tail_level, &tph))
+        plan->tail_level = hp.n_levels;
+    if (plan->tail_level < hp.n_levels) {
+        if (r == hipSuccess) r = upload(plan->tail_lvl, tph.lvl, st);
+        if (r == hipSuccess) r = upload(plan->tail_rec, tph.rec, st);
+        if (r == hipSuccess) r = upload(plan->tail_kid, tph.kid, st);
+        if (r == hipSuccess) r = upload(plan->tail_chunks, tph.chunks, st);
+        plan->tail.lvl = plan->tail_lvl.as<int32_t>();
+        plan->tail.rec = plan->tail_rec.as<int4>();
+        plan->tail.kid = plan->tail_kid.as<int32_t>();
+        plan->tail.chunks = plan->tail_chunks.as<int2>();
+        plan->tail.n_chunks = (int32_t)(tph.chunks.size() / 2);
+    }
     if (r == hipSuccess) r = hipStreamSynchronize(st);
     if (r != hipSuccess) {
         uf_plan_destroy(plan);
@@ -173,6 +181,7 @@ Knobs resolve_knobs(const uf_tuning *t, uf_precision prec, int32_t n_branches)
     // so the FP32 default batch is kept at 128 (< 1e-5); FP64 batches only trade stripe
     // traffic against embedding-buffer size.
     k.emb_batch = (t && t->emb_batch > 0) ? t->emb_batch : (prec == UF_PREC_FP32 ? 128 : 1024);
+    k.e_free = (t && t->emb_batch > 0) || prec != UF_PREC_FP64 ? 0 : 1;
     k.emb_batch = std::min(k.emb_batch, 4096);
     if (n_branches > 0) k.emb_batch = std::min(k.emb_batch, n_branches);
     k.emb_batch = std::max(k.emb_batch, 1);
@@ -192,21 +201,23 @@ Knobs resolve_knobs(const uf_tuning *t, uf_precision prec, int32_t n_branches)
 // left a measured 5 % behind), at most 16 splits, at least two batches per split, and the
 // copies of the stripe state within 4 GB.  No split when the stripe tiles alone give ten
 // rounds.
-int32_t auto_k_split(const uf_context *ctx, const StripeGeom &g, int64_t tiles, int32_t B, int32_t E,
-                     size_t state_bytes)
+int32_t auto_k_split(const uf_context *ctx, const StripeGeom &g, int64_t tiles, int32_t B, int32_t *E,
+                     bool e_free, size_t state_bytes)
 {
     const int64_t slots = (int64_t)std::max(ctx->n_cu, 1) * std::max(g.occ, 1);
     constexpr int64_t kRounds = 10;
     if (tiles <= 0 || tiles >= kRounds * slots) return 1;
     int64_t kz = (kRounds * slots + tiles - 1) / tiles;
-    kz = std::min<int64_t>(kz, 16);
-    kz = std::min<int64_t>(kz, std::max<int64_t>(1, B / std::max(2 * E, 1)));   // >= 2 batches each
+    // up to 16 splits; up to 64 when even 16 would not give the device one round
+    kz = std::min<int64_t>(kz, tiles * 16 < slots ? 64 : 16);
+    // >= 2 batches per split; a batch depth the caller left free (FP64, where it only
+    // trades state traffic) shrinks, down to 64 branches, to allow the splits
+    if (e_free && B / std::max(2 * *E, 1) < kz) *E = (int32_t)std::max<int64_t>(64, std::min<int64_t>(*E, B / (2 * kz)));
+    kz = std::min<int64_t>(kz, std::max<int64_t>(1, B / std::max(2 * *E, 1)));
     const size_t budget = (size_t)4 << 30;
     if (state_bytes > 0) kz = std::min<int64_t>(kz, std::max<int64_t>(1, (int64_t)(budget / state_bytes)));
     return (int32_t)std::max<int64_t>(kz, 1);
 }
-
-
 
 StripeGeom striped_geometry(const uf_plan *plan, uf_precision prec, const Knobs &kn)
 {
@@ -226,14 +237,16 @@ size_t striped_state_bytes(const StripeGeom &g, int32_t s_begin, int32_t s_end, 
     return (size_t)(*t1 - *t0) * g.tsw * g.sstride * sizeof(double);
 }
 
-int32_t striped_k_split(const uf_plan *plan, const Knobs &kn, const StripeGeom &g, int32_t t0, int32_t t1,
-                        size_t state)
+// Branch splits (and, when the caller left it free, the FP64 batch depth) of the fused
+// kernel.  Both follow from the whole problem's stripe tiles, not the range being computed,
+// so that stripe ranges repeat the per-element arithmetic of the full computation.
+int32_t striped_k_split(const uf_plan *plan, Knobs &kn, const StripeGeom &g, size_t state)
 {
     const int32_t B = plan->hp.n_nodes - 1;
-    const int64_t tiles = (int64_t)(g.sstride / g.tkw) * (t1 - t0);
+    const int64_t tiles = (int64_t)(g.sstride / g.tkw) * (g.spad / g.tsw);
     return kn.variant != 0 ? 1
            : kn.k_split > 0 ? std::min(kn.k_split, std::max(B, 1))
-                            : auto_k_split(plan->ctx, g, tiles, B, kn.emb_batch,
+                            : auto_k_split(plan->ctx, g, tiles, B, &kn.emb_batch, kn.e_free != 0,
                                            kn.den_mode == 0 ? 2 * state : state);
 }
 
@@ -388,7 +401,7 @@ uf_status striped_generated(uf_plan *plan, uf_method method, uf_precision prec, 
 // (a)-(b): fills plan->num / den (den_mode 0) or num / D (den_mode 1).
 // Stripes [s_begin, s_end) (-1, -1 = all): the state block covers the stripe tiles that
 // overlap the range and *s_base receives the stripe held by its first row.
-uf_status run_striped(uf_plan *plan, uf_method method, uf_precision prec, const Knobs &kn,
+uf_status run_striped(uf_plan *plan, uf_method method, uf_precision prec, Knobs kn,
                       StripeGeom *geom, hipStream_t st, int32_t s_begin = -1, int32_t s_end = -1,
                       int32_t *s_base = nullptr)
 {
@@ -404,7 +417,7 @@ uf_status run_striped(uf_plan *plan, uf_method method, uf_precision prec, const 
     const size_t tsz = fp64 ? sizeof(double) : sizeof(float);
     const int32_t cw = resolve_count_width(hp, kn.count_width);
     if (cw < 0) return set_err(ctx, UF_E_ARG, "16-bit counts need every sample total <= 65535");
-    int32_t kz = striped_k_split(plan, kn, g, tile_s0, tile_s1, state);
+    int32_t kz = striped_k_split(plan, kn, g, state);
     if (kn.variant == 0 && B > 0) {
         // resident rows, or rows generated batch by batch when they would not fit
         const size_t sums = (size_t)hp.n_samples * 16 + rowdot_scratch_elems(g.n, B) * sizeof(double);
@@ -701,7 +714,7 @@ void uf_plan_destroy(uf_plan *plan)
     (void)enter_device(plan->ctx->device);
     for (DevMem *m : {&plan->indptr, &plan->entry_slot, &plan->entry_count, &plan->totals,
                       &plan->child_ptr, &plan->child_slot, &plan->len_slot, &plan->slot_of_node,
-                      &plan->level_ptr,
+                      &plan->tail_lvl, &plan->tail_rec, &plan->tail_kid, &plan->tail_chunks,
                       &plan->counts, &plan->bits, &plan->emb, &plan->num, &plan->den, &plan->D,
                       &plan->inv_t, &plan->out_tmp, &plan->gather_tmp, &plan->rowdot_part})
         m->release();

@@ -176,6 +176,46 @@ int32_t narrow_tail_level(const HostPrep &hp, int32_t max_nodes)
     return h;
 }
 
+bool tail_program(const HostPrep &hp, int32_t h0, TailProgramHost *tp)
+{
+    tp->lvl.clear();
+    tp->kid.clear();
+    tp->rec.clear();
+    tp->chunks.clear();
+    int32_t chunk_first = 0, chunk_recs = 0, chunk_kids = 0;
+    for (int32_t h = h0; h < hp.n_levels; ++h) {
+        const int32_t nodes = hp.level_ptr[h + 1] - hp.level_ptr[h];
+        int32_t kids = 0;
+        for (int32_t s = hp.level_ptr[h]; s < hp.level_ptr[h + 1]; ++s)
+            kids += hp.child_ptr[s - hp.n_leaf + 1] - hp.child_ptr[s - hp.n_leaf];
+        if (nodes > kTailMaxNodes || kids > kTailMaxKids) return false;
+        const int32_t lv = h - h0;
+        if (chunk_recs + nodes > kTailMaxNodes || chunk_kids + kids > kTailMaxKids ||
+            lv - chunk_first >= kTailMaxLevels) {
+            tp->chunks.push_back(chunk_first);
+            tp->chunks.push_back(lv);
+            chunk_first = lv;
+            chunk_recs = chunk_kids = 0;
+        }
+        tp->lvl.push_back((int32_t)(tp->rec.size() / 4));
+        for (int32_t s = hp.level_ptr[h]; s < hp.level_ptr[h + 1]; ++s) {
+            const int32_t i = s - hp.n_leaf;
+            const int32_t k0 = (int32_t)tp->kid.size();
+            for (int32_t q = hp.child_ptr[i]; q < hp.child_ptr[i + 1]; ++q) tp->kid.push_back(hp.child_slot[q]);
+            tp->rec.insert(tp->rec.end(), {s, k0, (int32_t)tp->kid.size(), 0});
+        }
+        chunk_recs += nodes;
+        chunk_kids += kids;
+    }
+    const int32_t n_lv = hp.n_levels - h0;
+    tp->lvl.push_back((int32_t)(tp->rec.size() / 4));
+    if (n_lv > chunk_first) {
+        tp->chunks.push_back(chunk_first);
+        tp->chunks.push_back(n_lv);
+    }
+    return true;
+}
+
 // Euler-tour tables for generating count rows without the level propagation: tips are
 // numbered in depth-first order (children in node-id order), so the tips below any node form
 // one contiguous range [lo, hi) of that order, and a sample's reads below the node are the

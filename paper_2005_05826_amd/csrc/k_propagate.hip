@@ -85,40 +85,55 @@ __global__ void k_level(uint32_t *__restrict__ X, int64_t stride, int32_t n_vec,
     }
 }
 
-// The narrow top of a deep tree, levels [h0, h1) (each with few nodes), in one launch:
-// work-group g owns uint4 columns [g * kTailCols, (g + 1) * kTailCols) of every row and walks
-// the levels in order with a barrier between them.  A node's children sit in lower levels,
-// computed either by earlier launches or by this same work-group for these same columns, so
-// no other work-group is ever waited for; the barrier's workgroup-scope fence makes a
-// level's stores visible to the next level's loads (one CU, one L1).
+// The narrow top of a deep tree in one launch: work-group g owns uint4 columns
+// [g * kTailCols, (g + 1) * kTailCols) of every row and walks the tail's levels in order with
+// a barrier between them.  A node's children sit in lower levels, computed either by earlier
+// launches or by this same work-group for these same columns, so no other work-group is ever
+// waited for; the barrier's workgroup-scope fence makes a level's stores visible to the next
+// level's loads (one CU, one L1).  The tail's topology (TailProgram) is staged into LDS a
+// chunk of levels at a time, so that a level waits only on its row loads.
 constexpr int kTailCols = 16;
 template <bool OR>
-__global__ void k_level_tail(uint32_t *__restrict__ X, int64_t stride, int32_t n_vec,
-                             const int32_t *__restrict__ level_ptr, int32_t h0, int32_t h1, int32_t n_leaf,
-                             const int32_t *__restrict__ child_ptr, const int32_t *__restrict__ child_slot)
+__global__ void k_level_tail(uint32_t *__restrict__ X, int64_t stride, int32_t n_vec, TailProgram tp)
 {
+    __shared__ int32_t s_lvl[kTailMaxLevels + 1];
+    __shared__ int4 s_rec[kTailMaxNodes];     // (slot, first kid, end kid, 0), kids chunk-relative
+    __shared__ int32_t s_kid[kTailMaxKids];
     const int32_t c = blockIdx.x * kTailCols + (int32_t)(threadIdx.x % kTailCols);
     const int32_t lane = (int32_t)(threadIdx.x / kTailCols);
     constexpr int32_t kLanes = kBlock / kTailCols;
-    for (int32_t h = h0; h < h1; ++h) {
-        const int32_t b = level_ptr[h], e = level_ptr[h + 1];
-        if (c < n_vec) {
-            for (int32_t slot = b + lane; slot < e; slot += kLanes) {
-                const int32_t i = slot - n_leaf;
-                const int32_t q0 = child_ptr[i], q1 = child_ptr[i + 1];
-                uint4 acc = make_uint4(0u, 0u, 0u, 0u);
-                for (int32_t q = q0; q < q1; ++q) {
-                    const uint4 v = reinterpret_cast<const uint4 *>(X + (int64_t)child_slot[q] * stride)[c];
-                    if (OR) {
-                        acc.x |= v.x; acc.y |= v.y; acc.z |= v.z; acc.w |= v.w;
-                    } else {
-                        acc.x += v.x; acc.y += v.y; acc.z += v.z; acc.w += v.w;
-                    }
-                }
-                reinterpret_cast<uint4 *>(X + (int64_t)slot * stride)[c] = acc;
-            }
+    for (int32_t ch = 0; ch < tp.n_chunks; ++ch) {
+        const int2 lv = tp.chunks[ch];                     // levels [lv.x, lv.y) of the tail
+        const int32_t r0 = tp.lvl[lv.x], r1 = tp.lvl[lv.y];
+        const int32_t k0 = tp.rec[r0].y, k1 = tp.rec[r1 - 1].z;
+        for (int32_t i = threadIdx.x; i <= lv.y - lv.x; i += kBlock) s_lvl[i] = tp.lvl[lv.x + i] - r0;
+        for (int32_t i = threadIdx.x; i < r1 - r0; i += kBlock) {
+            int4 r = tp.rec[r0 + i];
+            r.y -= k0;
+            r.z -= k0;
+            s_rec[i] = r;
         }
+        for (int32_t i = threadIdx.x; i < k1 - k0; i += kBlock) s_kid[i] = tp.kid[k0 + i];
         __syncthreads();
+        for (int32_t h = 0; h < lv.y - lv.x; ++h) {
+            const int32_t b = s_lvl[h], e = s_lvl[h + 1];
+            if (c < n_vec) {
+                for (int32_t i = b + lane; i < e; i += kLanes) {
+                    const int4 r = s_rec[i];
+                    uint4 acc = make_uint4(0u, 0u, 0u, 0u);
+                    for (int32_t q = r.y; q < r.z; ++q) {
+                        const uint4 v = reinterpret_cast<const uint4 *>(X + (int64_t)s_kid[q] * stride)[c];
+                        if (OR) {
+                            acc.x |= v.x; acc.y |= v.y; acc.z |= v.z; acc.w |= v.w;
+                        } else {
+                            acc.x += v.x; acc.y += v.y; acc.z += v.z; acc.w += v.w;
+                        }
+                    }
+                    reinterpret_cast<uint4 *>(X + (int64_t)r.x * stride)[c] = acc;
+                }
+            }
+            __syncthreads();
+        }
     }
 }
 
@@ -284,19 +299,16 @@ static hipError_t launch_level(bool is_or, uint32_t *X, int64_t stride, int32_t 
     return hipGetLastError();
 }
 
-hipError_t launch_level_tail(bool is_or, uint32_t *X, int64_t stride_words, const int32_t *level_ptr,
-                             int32_t h0, int32_t h1, int32_t n_leaf, const int32_t *child_ptr,
-                             const int32_t *child_slot, hipStream_t st)
+hipError_t launch_level_tail(bool is_or, uint32_t *X, int64_t stride_words, const TailProgram &tp,
+                             hipStream_t st)
 {
-    if (h1 <= h0) return hipSuccess;
+    if (tp.n_chunks <= 0) return hipSuccess;
     const int32_t n_vec = (int32_t)(stride_words / 4);
     const unsigned groups = grid1(n_vec, kTailCols);
     if (is_or)
-        k_level_tail<true><<<groups, kBlock, 0, st>>>(X, stride_words, n_vec, level_ptr, h0, h1, n_leaf,
-                                                      child_ptr, child_slot);
+        k_level_tail<true><<<groups, kBlock, 0, st>>>(X, stride_words, n_vec, tp);
     else
-        k_level_tail<false><<<groups, kBlock, 0, st>>>(X, stride_words, n_vec, level_ptr, h0, h1, n_leaf,
-                                                       child_ptr, child_slot);
+        k_level_tail<false><<<groups, kBlock, 0, st>>>(X, stride_words, n_vec, tp);
     return hipGetLastError();
 }
 

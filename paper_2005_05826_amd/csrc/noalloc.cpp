@@ -87,7 +87,7 @@ extern "C" uf_status uf_plan_distance_noalloc(uf_plan *plan, uf_method method, u
         return set_err(ctx, UF_E_ARG,
                        "problem needs " + std::to_string(fixed + per_copy) + " bytes of device scratch, more than the " +
                            std::to_string(kScratchBytes) + " the no-allocation entry point holds");
-    int32_t kz = striped_k_split(plan, kn, g, t0, t1, state);
+    int32_t kz = striped_k_split(plan, kn, g, state);
     kz = (int32_t)std::min<size_t>((size_t)kz, (kScratchBytes - fixed) / per_copy);
     StripedWork W{};
     size_t off = 0;

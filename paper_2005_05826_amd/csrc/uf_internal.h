@@ -62,12 +62,27 @@ hipError_t launch_scatter_counts(const int64_t *indptr, const int32_t *entry_slo
 hipError_t launch_level_sum(void *C, int64_t stride_words, int32_t slot_begin, int32_t n_rows,
                             int32_t n_leaf, const int32_t *child_ptr, const int32_t *child_slot,
                             hipStream_t st);
-// Levels [h0, h1) in one launch (sum or OR of the children's rows); every level should be
-// narrow (few nodes), since one work-group walks all of them for its slice of columns.
-// level_ptr: the device copy of HostPrep::level_ptr.
-hipError_t launch_level_tail(bool is_or, uint32_t *X, int64_t stride_words, const int32_t *level_ptr,
-                             int32_t h0, int32_t h1, int32_t n_leaf, const int32_t *child_ptr,
-                             const int32_t *child_slot, hipStream_t st);
+// The narrow top of the tree (levels from HostPrep-derived tail_level up, each with few
+// nodes) as one launch.  Its topology, level by level: node records (slot, first kid, end
+// kid, 0) indexing the child slots `kid`, record boundaries per tail level `lvl`, and chunks of
+// whole levels whose records and kids fit the kernel's LDS staging.
+constexpr int kTailMaxLevels = 1024, kTailMaxNodes = 1024, kTailMaxKids = 2048;
+struct TailProgram {
+    const int32_t *lvl;      // tail levels + 1 record boundaries
+    const int4 *rec;
+    const int32_t *kid;
+    const int2 *chunks;      // [first level, end level) of each chunk, tail-relative
+    int32_t n_chunks, pad;
+};
+struct TailProgramHost {
+    std::vector<int32_t> lvl, kid;
+    std::vector<int32_t> rec;      // 4 ints per node
+    std::vector<int32_t> chunks;   // 2 ints per chunk
+};
+// Builds the program of levels [h0, n_levels); false when a level alone exceeds the limits.
+bool tail_program(const HostPrep &hp, int32_t h0, TailProgramHost *tp);
+hipError_t launch_level_tail(bool is_or, uint32_t *X, int64_t stride_words, const TailProgram &tp,
+                             hipStream_t st);
 // First level of the narrow top of the tree: every level from it on holds at most
 // `max_nodes` nodes (n_levels when the top level itself is wider).
 int32_t narrow_tail_level(const HostPrep &hp, int32_t max_nodes);

@@ -104,8 +104,9 @@ struct uf_plan {
     ufmi::HostPrep hp;
     // resident inputs
     ufmi::DevMem indptr, entry_slot, entry_count, totals, child_ptr, child_slot, len_slot,
-        slot_of_node, level_ptr;
-    int32_t tail_level = 0;   // levels from here up run as one launch (narrow_tail_level)
+        slot_of_node, tail_lvl, tail_rec, tail_kid, tail_chunks;
+    ufmi::TailProgram tail{};   // the narrow top of the tree as one launch (n_chunks 0: none)
+    int32_t tail_level = 0;     // first level of that top; lower levels run one launch each
     // scratch, allocated on first use
     ufmi::DevMem counts, bits, emb, num, den, D, inv_t, out_tmp, gather_tmp, rowdot_part;
     ufmi::DevMem mfma_scratch[4];
@@ -188,6 +189,7 @@ uf_status plan_prepare(uf_context *ctx, const uf_tree *tree, const uf_table *tab
 // Resolved knobs of one distance call (uf_tuning with the defaults filled in).
 struct Knobs {
     int32_t emb_batch, k_chunk, den_mode, variant, tile, count_width, k_split;
+    int32_t e_free;   // 1: emb_batch is the FP64 default and may shrink for branch splits
 };
 Knobs resolve_knobs(const uf_tuning *t, uf_precision prec, int32_t n_branches);
 uf_status check_enums(uf_context *ctx, uf_method method, uf_precision prec);
@@ -201,8 +203,7 @@ struct StripedWork {
 uf_status propagate_counts_into(uf_plan *plan, void *C, int32_t cw, hipStream_t st);
 StripeGeom striped_geometry(const uf_plan *plan, uf_precision prec, const Knobs &kn);
 size_t striped_state_bytes(const StripeGeom &g, int32_t s_begin, int32_t s_end, int32_t *t0, int32_t *t1);
-int32_t striped_k_split(const uf_plan *plan, const Knobs &kn, const StripeGeom &g, int32_t t0, int32_t t1,
-                        size_t state);
+int32_t striped_k_split(const uf_plan *plan, Knobs &kn, const StripeGeom &g, size_t state);
 uf_status striped_core(uf_plan *plan, uf_method method, uf_precision prec, const Knobs &kn,
                        const StripeGeom &g, int32_t t0, int32_t t1, int32_t kz, size_t state,
                        int32_t cw, const StripedWork &W, hipStream_t st);
