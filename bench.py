@@ -79,14 +79,14 @@ OPS_PER_UPDATE = {0: 4, 1: 2}   # den_mode 0: both stripes; 1: numerator only
 # it was measured on, and is reported as null once that source has changed.
 TRAFFIC = {
     "striped/4096x65534/fp32/den1/tile2/Edefault": {
-        "src_sha256": "7ac7fdd242d76870", "fetch": 44192166645, "write": 34360248000,
-        "bytes": 78552414645, "profile": "profiles/k_stripe_fused_wn_fp32_4096x65534.md"},
+        "src_sha256": "27e9406bdd1905f0", "fetch": 44629327019, "write": 34360367360,
+        "bytes": 78989694379, "profile": "profiles/k_stripe_fused_wn_fp32_4096x65534.md"},
     "mfma/25000x599998/k_chunk4096/variant0": {
-        "src_sha256": "0dafb66920d275d8", "fetch": 216550308040, "write": 102893162048,
-        "bytes": 319443470088, "profile": "profiles/k_mfma_gemm_uw_25000x599998.md"},
+        "src_sha256": "8790587f76fa0584", "fetch": 223273155563, "write": 102958535520,
+        "bytes": 326231691083, "profile": "profiles/k_mfma_gemm_uw_25000x599998.md"},
     "hbm/25000x16382/fp64/den0/tile2/E8": {
-        "src_sha256": "7ac7fdd242d76870", "fetch": 1868219062746, "write": 2016079277952,
-        "bytes": 3884298340698, "profile": "profiles/k_stripe_fused_hbm_regime_fp64_25000x16382.md"},
+        "src_sha256": "27e9406bdd1905f0", "fetch": 1908569702446, "write": 1959514515584,
+        "bytes": 3868084218030, "profile": "profiles/k_stripe_fused_hbm_regime_fp64_25000x16382.md"},
 }
 
 
@@ -510,10 +510,10 @@ def bench_mfma(args):
 def bench_batch(args):
     import torch
     import paper_2005_05826_amd as uf
-    from synth import batch_job_specs, build_job
+    from synth import batch_job_specs, build_jobs
     t0 = time.time()
     specs = batch_job_specs(n_jobs=args.jobs)
-    probs = [build_job(s) for s in specs]
+    probs = build_jobs(specs)
     log(f"generated {len(probs)} jobs in {time.time() - t0:.1f}s")
     ctx = uf.Context(0)
     jobs, outs = [], []
