@@ -13,9 +13,12 @@
 //
 // Layout: presence is stored once per sample as one bit per branch, [n_pad][k_pad / 8]
 // bytes (bit t of byte q = branch 8q + t).  A work-group stages 128 branches of its row and
-// column panels at a time and expands the bits to bytes (0x00 or 0xFF) on the way into LDS;
-// a byte pair becomes a pair of 16-bit masks with one byte permute, and a mask ANDed with
-// the bf16 pattern of hi, lo or 1.0 is exactly the MFMA operand.
+// column panels at a time and expands the bits to bytes on the way into LDS: 0x00 or 0xFF
+// for the row panel, 0x00 or 0x3F for the column panel.  A row-panel byte pair becomes a
+// pair of 16-bit masks with one byte permute, and a mask ANDed with the bf16 pattern of 2 hi
+// or 2 lo is the row operand; a column-panel byte pair placed in the high bytes of two
+// 16-bit halves by one byte permute is already the bf16 pair 0.5 / 0, the column operand.
+// Every product (2 hi) * 0.5 equals hi exactly, so the sums are those of P diag(hi) P^T.
 #include "uf_internal.h"
 
 namespace ufmi {
@@ -28,7 +31,8 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int GM = 128;            // work-group tile: GM x GM outputs, 4 waves of 64 x 64
 constexpr int GK = 128;            // branches per LDS stage (16 bytes of presence bits per row)
 constexpr int LDK = GK + 8;        // padded LDS row of expanded bytes (conflict-free operand reads)
-constexpr uint32_t kOne2 = 0x3F803F80u;  // two bf16 1.0
+constexpr uint32_t kRowByte = 0x0000FF00u;   // byte 1: the row-panel byte of a present branch
+constexpr uint32_t kColByte = 0x00003F00u;   // byte 1: high byte of bf16 0.5
 
 // round-to-nearest-even FP32 -> bf16 (finite, non-negative inputs)
 __device__ inline uint16_t bf16_rne(float x)
@@ -37,6 +41,9 @@ __device__ inline uint16_t bf16_rne(float x)
     return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
 }
 
+// Writes 2 hi and 2 lo (the column operand carries the factor 0.5 back); doubling a bf16 is
+// exact for every length below 2^127 (larger ones overflow, as lengths beyond the FP32 range
+// did already).
 __global__ void k_split_lengths(const double *__restrict__ len, int32_t B, int32_t k_pad,
                                 uint16_t *__restrict__ hi, uint16_t *__restrict__ lo)
 {
@@ -49,6 +56,9 @@ __global__ void k_split_lengths(const double *__restrict__ len, int32_t B, int32
         const float rest = L32 - __uint_as_float((uint32_t)h << 16);
         l = bf16_rne(rest < 0.f ? -rest : rest);
         if (rest < 0.f) l |= 0x8000u;
+        // the doubling is exact in FP32, and its result is a bf16 value again
+        h = bf16_rne(2.f * __uint_as_float((uint32_t)h << 16));
+        l = (uint16_t)((l & 0x8000u) | bf16_rne(2.f * __uint_as_float((uint32_t)(l & 0x7FFFu) << 16)));
     }
     hi[b] = h;
     lo[b] = l;
@@ -85,16 +95,16 @@ __global__ void k_bits_transpose(const uint32_t *__restrict__ bits, int64_t bstr
     *reinterpret_cast<uint2 *>(Pb + (int64_t)k * kb + b0 / 8) = make_uint2(lo, hi);
 }
 
-// 32 presence bits -> 32 bytes of 0x00 / 0xFF (byte t of dword d <- bit 4d + t).  A nibble
-// times 0x204081 puts its bit t at bit 8t (the other partial products land on bits that the
-// mask clears); selector byte 12 or 13 of v_perm yields 0x00 or 0xFF.
-__device__ inline void expand_bits(uint32_t x, uint32_t (&out)[8])
+// 32 presence bits -> 32 bytes (byte t of dword d <- bit 4d + t): byte 1 of `c` for a set
+// bit, byte 0 of `c` (zero) for a clear one.  A nibble times 0x204081 puts its bit t at bit 8t
+// (the other partial products land on bits that the mask clears), and the resulting 0 / 1
+// selector bytes pick bytes of c.
+__device__ inline void expand_bits(uint32_t x, uint32_t c, uint32_t (&out)[8])
 {
 #pragma unroll
     for (int d = 0; d < 8; ++d) {
         const uint32_t nib = (x >> (4 * d)) & 0xFu;
-        const uint32_t sel = ((nib * 0x204081u) & 0x01010101u) | 0x0C0C0C0Cu;
-        out[d] = __builtin_amdgcn_perm(0u, 0u, sel);
+        out[d] = __builtin_amdgcn_perm(c, c, (nib * 0x204081u) & 0x01010101u);
     }
 }
 
@@ -107,11 +117,25 @@ __device__ inline bf16x8 as_bf16x8(uint32_t a, uint32_t b, uint32_t c, uint32_t 
 
 // Two LDS stages: the next stage's global loads are in flight while this one computes.
 // hl holds the stage's hi splits followed by its lo splits.
+// lut[p][v] holds the eight expanded bytes of presence byte v for panel p (0 rows, 1 columns).
 struct MfmaSmem {
     __align__(16) uint8_t A[2][GM * LDK];
     __align__(16) uint8_t B[2][GM * LDK];
     __align__(16) uint16_t hl[2][2 * GK];
+    __align__(16) uint2 lut[2][256];
 };
+
+// Fills both expansion tables (one entry of each per thread of a 256-thread group); the
+// caller synchronizes before the first use.
+__device__ inline void fill_lut(MfmaSmem &sm)
+{
+    const uint32_t v = threadIdx.x;
+    uint32_t e[8];
+    expand_bits(v, kRowByte, e);
+    sm.lut[0][v] = make_uint2(e[0], e[1]);
+    expand_bits(v, kColByte, e);
+    sm.lut[1][v] = make_uint2(e[0], e[1]);
+}
 
 // One GM x GM tile of S = P diag(hi + lo) P^T (rows row0.., columns col0.., row0 <= col0):
 // writes S_ij (i < j) into the condensed array and S_ii into T.  The FP32 chunk sums are
@@ -155,80 +179,136 @@ __device__ void mfma_tile(const MfmaArgs &a, int32_t row0, int32_t col0, MfmaSme
     uint8_t *srow = (tid < 128 ? &sm.A[0][0] : &sm.B[0][0]) + (tid & 127) * LDK;
     const uint32_t *phl = reinterpret_cast<const uint32_t *>((tid & 64) ? a.lo : a.hi) + (tid & 63);
     const int hoff = tid & 127;
+    const uint2 *lut = sm.lut[tid < 128 ? 0 : 1];
     // Global loads run two stages ahead of the compute: stage ks + 2 is loaded into one
     // register set while stage ks + 1 (loaded one stage earlier) waits in the other and is
-    // expanded into the free LDS buffer after stage ks computes.  chunk_steps is even, so
+    // expanded into the free LDS buffer while stage ks computes.  chunk_steps is even, so
     // every chunk starts on an even stage and the two sets alternate with static names.
     struct Stage {
         uint4 bits;
         uint32_t hl;
     };
-    Stage R0, R1;
+    Stage R0{}, R1{};
     auto gload = [&](Stage &R, int32_t ks) {
         const int64_t k0 = (int64_t)ks * GK;
         R.bits = *reinterpret_cast<const uint4 *>(prow + k0 / 8);
         R.hl = phl[k0 / 2];
     };
-    auto lstore = [&](const Stage &R, int buf) {
-        // rows are LDK = 136 bytes apart: 8-byte aligned stores
+    // One eighth of a stage's expansion into LDS buffer buf: bytes 2h and 2h + 1 (h = part
+    // % 2) of bits word part / 2, i.e. branches 16 part .. 16 part + 15 of this thread's row,
+    // each byte looked up in the panel's table (rows are LDK = 136 bytes apart: 8-byte
+    // aligned stores).
+    auto store_part = [&](const Stage &R, int buf, int part) {
         uint2 *dst = reinterpret_cast<uint2 *>(srow + buf * (GM * LDK));
-        const uint32_t w4[4] = {R.bits.x, R.bits.y, R.bits.z, R.bits.w};
+        const int q = part >> 1, h = part & 1;
+        const uint32_t x = q == 0 ? R.bits.x : q == 1 ? R.bits.y : q == 2 ? R.bits.z : R.bits.w;
+        const uint2 e0 = lut[(x >> (16 * h)) & 0xFFu];
+        const uint2 e1 = lut[(x >> (16 * h + 8)) & 0xFFu];
+        dst[4 * q + 2 * h] = e0;
+        dst[4 * q + 2 * h + 1] = e1;
+        if (part == 0) reinterpret_cast<uint32_t *>(sm.hl[buf])[hoff] = R.hl;
+    };
+    auto lstore = [&](const Stage &R, int buf) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            uint32_t e[8];
-            expand_bits(w4[q], e);
+        for (int part = 0; part < GK / 16; ++part) store_part(R, buf, part);
+    };
+    // LDS words of one 16-branch step: the lane's hi and lo splits, its two row-panel and
+    // two column-panel byte runs; and the MFMA operands built from them
+    struct Raw {
+        uint4 h, l;
+        uint2 a[2], b[2];
+    };
+    struct Ops {
+        bf16x8 ahi[2], alo[2], bo[2];
+    };
+    auto lds_raw = [&](int buf, int kk, Raw &r) {
+        const int koff = kk * 16 + kg * 8;
+        const uint16_t *chl = sm.hl[buf];
+        r.h = *reinterpret_cast<const uint4 *>(chl + koff);
+        r.l = *reinterpret_cast<const uint4 *>(chl + GK + koff);
 #pragma unroll
-            for (int d = 0; d < 4; ++d) dst[4 * q + d] = make_uint2(e[2 * d], e[2 * d + 1]);
+        for (int mb = 0; mb < 2; ++mb)
+            r.a[mb] = *reinterpret_cast<const uint2 *>(sm.A[buf] + (wm * 64 + mb * 32 + lrow) * LDK + koff);
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+            r.b[nb] = *reinterpret_cast<const uint2 *>(sm.B[buf] + (wn * 64 + nb * 32 + lrow) * LDK + koff);
+    };
+    auto build = [&](const Raw &r, Ops &o) {
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) {
+            const uint2 m = r.a[mb];
+            const uint32_t m0 = __builtin_amdgcn_perm(m.x, m.x, 0x01010000u);
+            const uint32_t m1 = __builtin_amdgcn_perm(m.x, m.x, 0x03030202u);
+            const uint32_t m2 = __builtin_amdgcn_perm(m.y, m.y, 0x01010000u);
+            const uint32_t m3 = __builtin_amdgcn_perm(m.y, m.y, 0x03030202u);
+            o.ahi[mb] = as_bf16x8(m0 & r.h.x, m1 & r.h.y, m2 & r.h.z, m3 & r.h.w);
+            o.alo[mb] = as_bf16x8(m0 & r.l.x, m1 & r.l.y, m2 & r.l.z, m3 & r.l.w);
         }
-        reinterpret_cast<uint32_t *>(sm.hl[buf])[hoff] = R.hl;
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+            // bytes b0 b1 -> 16-bit halves b0 << 8, b1 << 8 (selector 12 gives a zero byte)
+            const uint2 m = r.b[nb];
+            o.bo[nb] = as_bf16x8(__builtin_amdgcn_perm(m.x, m.x, 0x010C000Cu),
+                                 __builtin_amdgcn_perm(m.x, m.x, 0x030C020Cu),
+                                 __builtin_amdgcn_perm(m.y, m.y, 0x010C000Cu),
+                                 __builtin_amdgcn_perm(m.y, m.y, 0x030C020Cu));
+        }
     };
     f32x16 acc[2][2];
-    auto compute = [&](int buf) {
-        const uint8_t *cA = sm.A[buf];
-        const uint8_t *cB = sm.B[buf];
-        const uint16_t *chl = sm.hl[buf];
+    auto mfma8 = [&](const Ops &o) {
 #pragma unroll
-        for (int kk = 0; kk < GK / 16; ++kk) {
-            const int koff = kk * 16 + kg * 8;
-            const uint4 h = *reinterpret_cast<const uint4 *>(chl + koff);
-            const uint4 l = *reinterpret_cast<const uint4 *>(chl + GK + koff);
-            bf16x8 ahi[2], alo[2], bo[2];
-#pragma unroll
-            for (int mb = 0; mb < 2; ++mb) {
-                const uint2 m = *reinterpret_cast<const uint2 *>(cA + (wm * 64 + mb * 32 + lrow) * LDK + koff);
-                const uint32_t m0 = __builtin_amdgcn_perm(m.x, m.x, 0x01010000u);
-                const uint32_t m1 = __builtin_amdgcn_perm(m.x, m.x, 0x03030202u);
-                const uint32_t m2 = __builtin_amdgcn_perm(m.y, m.y, 0x01010000u);
-                const uint32_t m3 = __builtin_amdgcn_perm(m.y, m.y, 0x03030202u);
-                ahi[mb] = as_bf16x8(m0 & h.x, m1 & h.y, m2 & h.z, m3 & h.w);
-                alo[mb] = as_bf16x8(m0 & l.x, m1 & l.y, m2 & l.z, m3 & l.w);
-            }
+        for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
             for (int nb = 0; nb < 2; ++nb) {
-                const uint2 m = *reinterpret_cast<const uint2 *>(cB + (wn * 64 + nb * 32 + lrow) * LDK + koff);
-                bo[nb] = as_bf16x8(__builtin_amdgcn_perm(m.x, m.x, 0x01010000u) & kOne2,
-                                   __builtin_amdgcn_perm(m.x, m.x, 0x03030202u) & kOne2,
-                                   __builtin_amdgcn_perm(m.y, m.y, 0x01010000u) & kOne2,
-                                   __builtin_amdgcn_perm(m.y, m.y, 0x03030202u) & kOne2);
+                acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.ahi[mb], o.bo[nb], acc[mb][nb], 0, 0, 0);
+                acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.alo[mb], o.bo[nb], acc[mb][nb], 0, 0, 0);
             }
-            // the wave issuing its matrix instructions gets issue priority over the waves
-            // still building operands (1.6 % on the 25,000-sample workload)
-            __builtin_amdgcn_s_setprio(1);
+    };
+    // Stage ks from LDS buffer buf, software-pipelined: the LDS words of step kk + 2 are read
+    // and the operands of step kk + 1 built while the matrix instructions of step kk run,
+    // and an eighth of the next stage's expansion (set Rn, into buffer nbuf) is interleaved
+    // with every step.  At the last stage Rn holds no stage and the writes land in a buffer
+    // nothing reads.
+    auto compute_store = [&](int buf, const Stage &Rn, int nbuf) {
+        constexpr int NKK = GK / 16;
+        Raw r0, r1;
+        Ops o;
+        lds_raw(buf, 0, r0);
+        lds_raw(buf, 1, r1);
+        build(r0, o);
 #pragma unroll
-            for (int mb = 0; mb < 2; ++mb)
+        for (int kk = 0; kk < NKK; ++kk) {
+            Raw r2;
+            if (kk + 2 < NKK) lds_raw(buf, kk + 2, r2);
+            mfma8(o);
+            store_part(Rn, nbuf, kk);
+            if (kk + 1 < NKK) build(r1, o);
+            if (kk + 2 < NKK) r1 = r2;
+            // each matrix instruction followed by the VALU work that runs beside it; the
+            // LDS reads early, the LDS writes of the expansion mid-way
 #pragma unroll
-                for (int nb = 0; nb < 2; ++nb) {
-                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[mb], bo[nb], acc[mb][nb], 0, 0, 0);
-                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo[mb], bo[nb], acc[mb][nb], 0, 0, 0);
-                }
-            __builtin_amdgcn_s_setprio(0);
+            for (int g = 0; g < 2; ++g) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x100, 3, 0);
+                __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);
+            }
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+            __builtin_amdgcn_sched_group_barrier(0x002, 5, 0);
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x200, 2, 0);
+            __builtin_amdgcn_sched_group_barrier(0x002, 5, 0);
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x002, 5, 0);
+            }
         }
     };
     // Rn holds stage ks + 1 (in flight), Rf is free
     auto step = [&](int32_t ks, Stage &Rn, Stage &Rf) {
         if (ks + 2 < n_kstep) gload(Rf, ks + 2);
-        compute(ks & 1);
-        if (ks + 1 < n_kstep) lstore(Rn, (ks + 1) & 1);
+        compute_store(ks & 1, Rn, (ks + 1) & 1);
         __syncthreads();
     };
 
@@ -365,6 +445,8 @@ __global__ __launch_bounds__(256, REG64 ? 1 : 2) void k_mfma_gemm(MfmaArgs a, co
     const int32_t per = (n_tiles + 7) / 8;
     const int32_t t = (int32_t)(blockIdx.x % 8) * per + (int32_t)(blockIdx.x / 8);
     if (t >= n_tiles) return;
+    fill_lut(sm);
+    __syncthreads();
     const int2 tile = tiles[t];
     mfma_tile<REG64>(a, tile.x * GM, tile.y * GM, sm);
 }
@@ -378,6 +460,7 @@ __global__ __launch_bounds__(256, REG64 ? 1 : 2) void k_mfma_queue(const MfmaArg
 {
     __shared__ MfmaSmem sm;
     __shared__ int32_t s_item;
+    fill_lut(sm);   // the loop's first barrier orders it before every use
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
