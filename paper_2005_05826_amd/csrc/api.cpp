@@ -360,6 +360,7 @@ uf_status striped_generated(uf_plan *plan, uf_method method, uf_precision prec, 
     UF_TRY(plan->rowdot_part.ensure(rowdot_scratch_elems(n, E) * sizeof(double)), "allocating sum scratch");
     UF_TRY(plan->gen_buf[0].ensure(rows), "allocating generated rows");
     UF_TRY(plan->gen_buf[1].ensure(rows), "allocating generated rows");
+    UF_TRY(plan->gen_tmp.ensure((size_t)E * n * cw), "allocating generated rows");
     double *num = plan->num.as<double>();
     double *den = kn.den_mode == 0 ? plan->den.as<double>() : nullptr;
     UF_TRY(launch_fill_u32(num, 0u, state / 4, st), "clearing stripes");
@@ -378,7 +379,7 @@ uf_status striped_generated(uf_plan *plan, uf_method method, uf_precision prec, 
                    return launch_range_counts(plan->indptr.as<int64_t>(), plan->gen_spos.as<int32_t>(),
                                               plan->gen_scum.as<int32_t>(), plan->gen_lo.as<int32_t>(),
                                               plan->gen_hi.as<int32_t>(), b0, eb, n, buf, cw,
-                                              plan->cstride, gs);
+                                              plan->cstride, plan->gen_tmp.p, gs);
                }), "generating count rows");
         UF_TRY(hipEventRecord(plan->gen_filled[x], gs), "ordering generated rows");
         UF_TRY(hipStreamWaitEvent(st, plan->gen_filled[x], 0), "ordering generated rows");
@@ -426,7 +427,7 @@ uf_status run_striped(uf_plan *plan, uf_method method, uf_precision prec, Knobs 
         bool gen = plan->mem_limit > 0 && resident > (size_t)plan->mem_limit;
         if (gen) {
             const size_t need = input_bytes(plan) + gen_table_bytes(plan) +
-                                2 * (size_t)kn.emb_batch * plan->cstride * cw +
+                                3 * (size_t)kn.emb_batch * plan->cstride * cw +
                                 state * (kn.den_mode == 0 ? 2 : 1) + (size_t)hp.n_samples * 16 +
                                 rowdot_scratch_elems(g.n, kn.emb_batch) * sizeof(double);
             if (need > (size_t)plan->mem_limit)
@@ -720,7 +721,7 @@ void uf_plan_destroy(uf_plan *plan)
         m->release();
     for (DevMem &m : plan->mfma_scratch) m.release();
     for (DevMem *m : {&plan->gen_spos, &plan->gen_scum, &plan->gen_lo, &plan->gen_hi, &plan->gen_buf[0],
-                      &plan->gen_buf[1]})
+                      &plan->gen_buf[1], &plan->gen_tmp})
         m->release();
     if (plan->gen_stream) (void)hipStreamDestroy(plan->gen_stream);
     for (hipEvent_t e : {plan->gen_start, plan->gen_filled[0], plan->gen_filled[1], plan->gen_used[0],
@@ -745,7 +746,7 @@ uf_status uf_plan_trim(uf_plan *plan)
     (void)enter_device(plan->ctx->device);
     for (DevMem *m : {&plan->counts, &plan->bits, &plan->emb, &plan->num, &plan->den, &plan->D,
                       &plan->inv_t, &plan->out_tmp, &plan->gather_tmp, &plan->rowdot_part,
-                      &plan->gen_buf[0], &plan->gen_buf[1]})
+                      &plan->gen_buf[0], &plan->gen_buf[1], &plan->gen_tmp})
         m->release();
     for (DevMem &m : plan->mfma_scratch) m.release();
     return UF_OK;

@@ -193,10 +193,11 @@ hipError_t launch_condense(int32_t method, const double *num, const double *den,
                            hipStream_t st);
 
 // Count rows generated from the range tables (no propagation): out[e][k] = reads of sample
-// k below slot slot0 + e, for e < E, k < n, as cw-byte counts in rows of ostride elements.
+// k below slot slot0 + e, for e < E, k < n, as cw-byte counts in rows of ostride elements;
+// tmp holds n * E counts (the sample-major rows before their transpose).
 hipError_t launch_range_counts(const int64_t *indptr, const int32_t *spos, const int32_t *scum,
                                const int32_t *lo, const int32_t *hi, int32_t slot0, int32_t E,
-                               int32_t n, void *out, int32_t cw, int64_t ostride, hipStream_t st);
+                               int32_t n, void *out, int32_t cw, int64_t ostride, void *tmp, hipStream_t st);
 // Presence bits of branch slots [slot0, slot0 + Bc) in the matrix-core layout: P[k][b / 8]
 // bit b % 8 for k < n_pad (rows k >= n are zero), b < kpad (bits b >= Bc are zero).
 hipError_t launch_range_bits(const int64_t *indptr, const int32_t *spos, const int32_t *scum,

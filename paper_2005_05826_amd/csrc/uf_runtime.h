@@ -118,7 +118,7 @@ struct uf_plan {
     // are computed from depth-first tip ranges on a second stream, double-buffered
     int64_t mem_limit = 0;   // device bytes the plan may hold (0: whatever the device has)
     bool gen_ready = false;
-    ufmi::DevMem gen_spos, gen_scum, gen_lo, gen_hi, gen_buf[2];
+    ufmi::DevMem gen_spos, gen_scum, gen_lo, gen_hi, gen_buf[2], gen_tmp;
     hipStream_t gen_stream = nullptr;
     hipEvent_t gen_start = nullptr, gen_filled[2] = {}, gen_used[2] = {};
 };

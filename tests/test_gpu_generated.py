@@ -48,7 +48,7 @@ def _row_limit(prob, count_width, emb_batch=128):
     state = (-(-(n // 2) // 96) * 96) * (-(-n // 512) * 512) * 8 * 2
     counts = N * cstride * count_width
     tables = nnz * 8 + N * 8
-    buffers = 2 * emb_batch * cstride * count_width
+    buffers = 3 * emb_batch * cstride * count_width   # two row buffers and the sample-major staging
     return inputs + state + n * 16 + (counts + tables + buffers) // 2
 
 
