@@ -106,7 +106,7 @@ typedef struct {
     int32_t emb_batch;  /* branches per embedding batch streamed through the striped kernel
                            (the batch depth of Section 3, Fig. 2)                            */
     int32_t k_chunk;    /* matrix-core path: branches per FP32 accumulation chain (rounded
-                           to an even number of 64-branch stages; default 4096).  Variant 1
+                           to an even number of 128-branch stages; default 4096).  Variant 1
                            adds every chain's sum into FP64.  Variant 0 adds four consecutive
                            chain sums together in FP32 (three roundings) before one FP64 add,
                            so each FP64 add takes 4 * k_chunk branches, while the FP32 error
