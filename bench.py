@@ -44,7 +44,9 @@ baseline, and the same sample gives the max and mean absolute error of every GPU
 The default run (the striped workload) also nests shorter records of the other targets in
 its JSON line (--extras none leaves them out): the matrix-core workload against plain FP64
 striped, the memory-bound regime against the HBM roof, the 256-sample FP64 workload with the
-full-matrix oracle, and the oracle over the full matrix of the striped workload itself.
+full-matrix oracle, the 64-job batch, the full unweighted matrix of the 113,000-sample
+workload on the matrix cores, and the oracle over the full matrix of the striped workload
+itself.
 """
 from __future__ import annotations
 
@@ -472,8 +474,7 @@ def bench_mfma(args):
     dt, prof = timed_runs(plan, "unweighted", "mfma_bf16x2", tuning, out, args.steps, args.warmup, stream)
     log(f"mfma: {dt * 1e3:.2f} ms/step; kernels {prof}")
     launches, total_ms = prof.get("mfma", (0, 0.0))
-    k_pad = (B + 63) // 64 * 64
-    flops = 4.0 * k_pad * n * (n + 1) / 2          # hi and lo, 2 flops each, upper triangle
+    flops = 4.0 * B * n * (n + 1) / 2          # hi and lo, 2 flops each, upper triangle; padding not counted
     achieved = flops / (total_ms / args.steps * 1e-3) / 1e12 if launches else 0.0
     res = base_record(args, updates / dt, dt, "bf16",
                       {"workload": f"unweighted UniFrac on bf16 matrix cores, {n} samples, random "
@@ -585,6 +586,8 @@ def bench_batch(args):
         res["error_vs_oracle"] = {"wn_fp32_largest_job": errors(outs[2 * big], p.n_samples, pi, pj, want)}
         _, pi, pj, want = oracle_sample(p, "unweighted", args.cpu_seconds / 4, 20050526 + 96)
         res["error_vs_oracle"]["uw_mfma_largest_job"] = errors(outs[2 * big + 1], p.n_samples, pi, pj, want)
+    b.close()
+    ctx.close()
     return res
 
 
@@ -613,8 +616,7 @@ def bench_large(args, part):
         dt, prof = timed_runs(plan, "unweighted", "mfma_bf16x2", dict(k_chunk=args.k_chunk, variant=args.variant), out,
                               args.steps, args.warmup, stream)
         launches, total_ms = prof.get("mfma", (0, 0.0))
-        k_pad = (B + 63) // 64 * 64
-        flops = 4.0 * k_pad * n * (n + 1) / 2
+        flops = 4.0 * B * n * (n + 1) / 2
         achieved = flops / (total_ms / args.steps * 1e-3) / 1e12 if launches else 0.0
         res = base_record(args, n_pairs * B / dt, dt, "bf16",
                           {"workload": f"unweighted UniFrac on bf16 matrix cores, {n} samples, random "
@@ -684,6 +686,8 @@ def bench_large(args, part):
             pi, pj, want = pi[keep], pj[keep], want[keep]
         if pi.size:
             res["error_vs_oracle"] = {method: errors(out, n, pi, pj, want)}
+    plan.close()
+    ctx.close()
     return res
 
 
@@ -771,7 +775,7 @@ def main():
         return
     extras = set()
     if args.workload == "striped" and args.extras != "none":
-        extras = {"mfma", "hbm", "binary_256", "full_oracle"} if args.extras == "all" \
+        extras = {"mfma", "hbm", "binary_256", "batch", "large_uw", "full_oracle"} if args.extras == "all" \
             else set(x for x in args.extras.split(",") if x)
     args.full_oracle = "full_oracle" in extras and not args.no_cpu
     if args.workload.startswith("large"):
@@ -787,7 +791,11 @@ def main():
                 ("hbm", bench_hbm, ["--workload", "hbm", "--steps", "3", "--warmup", "1",
                                     "--cpu-seconds", "5"]),
                 ("binary_256", bench_binary_256, ["--workload", "binary_256", "--steps", "20",
-                                                  "--warmup", "3"])]
+                                                  "--warmup", "3"]),
+                ("batch", bench_batch, ["--workload", "batch", "--steps", "2", "--warmup", "1",
+                                        "--cpu-seconds", "6"]),
+                ("large_uw", lambda a: bench_large(a, "uw"), ["--workload", "large-uw", "--steps", "1",
+                                                              "--warmup", "0", "--cpu-seconds", "6"])]
         for name, fn, argv in runs:
             if name not in extras:
                 continue
