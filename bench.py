@@ -84,7 +84,7 @@ TRAFFIC = {
         "src_sha256": "27e9406bdd1905f0", "fetch": 44629327019, "write": 34360367360,
         "bytes": 78989694379, "profile": "profiles/k_stripe_fused_wn_fp32_4096x65534.md"},
     "mfma/25000x599998/k_chunk4096/variant0": {
-        "src_sha256": "5044526a183905da", "fetch": 196697375872, "write": 103828393344,
+        "src_sha256": "3fb828a01a44df1a", "fetch": 196697375872, "write": 103828393344,
         "bytes": 300525769216, "profile": "profiles/k_mfma_gemm_uw_25000x599998.md"},
     "hbm/25000x16382/fp64/den0/tile2/E8": {
         "src_sha256": "27e9406bdd1905f0", "fetch": 1908569702446, "write": 1959514515584,

@@ -18,7 +18,11 @@
 // pair of 16-bit masks with one byte permute, and a mask ANDed with the bf16 pattern of 2 hi
 // or 2 lo is the row operand; a column-panel byte pair placed in the high bytes of two
 // 16-bit halves by one byte permute is already the bf16 pair 0.5 / 0, the column operand.
-// Every product (2 hi) * 0.5 equals hi exactly, so the sums are those of P diag(hi) P^T.
+// Every product (2 hi) * 0.5 equals hi exactly (and (2 lo) * 0.5 equals lo), so the sums are
+// those of the operands hi, lo and 1.0.  Each presence byte is expanded through a 256-entry
+// table in LDS, and the steps of a stage are software-pipelined: while the matrix
+// instructions of one 16-branch step run, the LDS words of the step after next are read, the
+// operands of the next one built and an eighth of the next stage expanded.
 #include "uf_internal.h"
 
 namespace ufmi {
