@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <limits>
 #include <numeric>
+#include <thread>
 
 #include "uf_internal.h"
 
@@ -146,26 +147,66 @@ uf_status validate_and_prepare(const uf_tree *tree, const uf_table *table, HostP
     hp->entry_slot.resize(nnz);
     hp->entry_count.resize(nnz);
     hp->totals.assign(n, 0);
-    for (int32_t k = 0; k < n; ++k) {
-        int64_t tot = 0;
-        for (int64_t e = ip[k]; e < ip[k + 1]; ++e) {
-            int32_t f = table->indices[e];
-            if (f < 0 || f >= F)
-                return fail(err, UF_E_TABLE, "feature id %lld out of range in row %lld", f, k);
-            int32_t c = table->counts[e];
-            if (c < 0) return fail(err, UF_E_TABLE, "negative count in row %lld entry %lld", k, e);
-            int32_t v = fnode ? fnode[f] : f;
-            if (cptr[v + 1] != cptr[v])
-                return fail(err, UF_E_TABLE, "feature %lld sits on internal node %lld", f, v);
-            hp->entry_slot[e] = hp->slot_of_node[v];
-            hp->entry_count[e] = c;
-            tot += c;
+    // The table pass runs on up to 16 host threads over contiguous sample ranges (each writes
+    // the entries of its own samples); the error reported is the first one in sample order,
+    // the one a single pass would meet.
+    const int32_t n_thr = (int32_t)std::max<int64_t>(
+        1, std::min<int64_t>({(int64_t)std::max(1u, std::thread::hardware_concurrency()), 16, nnz / 65536 + 1, n}));
+    struct Bad {
+        uf_status code = UF_OK;
+        std::string msg;
+    };
+    std::vector<Bad> bad(n_thr);
+    auto table_pass = [&](int32_t t) {
+        const int32_t k0 = (int32_t)((int64_t)n * t / n_thr), k1 = (int32_t)((int64_t)n * (t + 1) / n_thr);
+        std::string *msg = &bad[t].msg;
+        for (int32_t k = k0; k < k1; ++k) {
+            int64_t tot = 0;
+            for (int64_t e = ip[k]; e < ip[k + 1]; ++e) {
+                int32_t f = table->indices[e];
+                if (f < 0 || f >= F) {
+                    bad[t].code = fail(msg, UF_E_TABLE, "feature id %lld out of range in row %lld", f, k);
+                    return;
+                }
+                int32_t c = table->counts[e];
+                if (c < 0) {
+                    bad[t].code = fail(msg, UF_E_TABLE, "negative count in row %lld entry %lld", k, e);
+                    return;
+                }
+                int32_t v = fnode ? fnode[f] : f;
+                if (cptr[v + 1] != cptr[v]) {
+                    bad[t].code = fail(msg, UF_E_TABLE, "feature %lld sits on internal node %lld", f, v);
+                    return;
+                }
+                hp->entry_slot[e] = hp->slot_of_node[v];
+                hp->entry_count[e] = c;
+                tot += c;
+            }
+            if (tot == 0) {
+                bad[t].code = fail(msg, UF_E_EMPTY_SAMPLE, "sample %lld has no reads", k);
+                return;
+            }
+            if (tot > std::numeric_limits<int32_t>::max()) {
+                bad[t].code = fail(msg, UF_E_TABLE, "sample %lld total %lld exceeds int32", k, tot);
+                return;
+            }
+            hp->totals[k] = (int32_t)tot;
         }
-        if (tot == 0) return fail(err, UF_E_EMPTY_SAMPLE, "sample %lld has no reads", k);
-        if (tot > std::numeric_limits<int32_t>::max())
-            return fail(err, UF_E_TABLE, "sample %lld total %lld exceeds int32", k, tot);
-        hp->totals[k] = (int32_t)tot;
+    };
+    if (n_thr == 1) {
+        table_pass(0);
+    } else {
+        std::vector<std::thread> pool;
+        pool.reserve(n_thr - 1);
+        for (int32_t t = 1; t < n_thr; ++t) pool.emplace_back(table_pass, t);
+        table_pass(0);
+        for (std::thread &th : pool) th.join();
     }
+    for (const Bad &b : bad)
+        if (b.code != UF_OK) {
+            if (err) *err = b.msg;
+            return b.code;
+        }
     return UF_OK;
 }
 

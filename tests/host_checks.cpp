@@ -390,6 +390,54 @@ int main(int argc, char **argv)
         check(validate_and_prepare(&t, &b, &hp, &err) == UF_OK, "three chains");
         check_prepared(in, hp);
     }
+    // a table large enough for the threaded table pass: counts against the walk-up definition,
+    // and with two planted errors the one of the earlier sample is reported
+    {
+        Rng rb{7};
+        Input in = random_input(rb, 3001, 1);
+        in.n_samples = 400;
+        in.indices.clear();
+        in.counts.clear();
+        in.indptr.assign(1, 0);
+        for (int32_t k = 0; k < in.n_samples; ++k) {
+            for (int32_t e = 0; e < 1500; ++e) {
+                in.indices.push_back(rb.below(in.n_features));
+                in.counts.push_back(1 + rb.below(9));
+            }
+            in.indptr.push_back((int64_t)in.indices.size());
+        }
+        const uf_tree t = in.tree();
+        const uf_table b = in.table();
+        HostPrep hp;
+        std::string err;
+        check(validate_and_prepare(&t, &b, &hp, &err) == UF_OK, "large table");
+        const std::vector<int64_t> want = walk_up_counts(in);
+        std::vector<int64_t> C((size_t)hp.n_nodes * in.n_samples, 0);
+        const int32_t n = in.n_samples;
+        for (int32_t k = 0; k < n; ++k) {
+            int64_t tot = 0;
+            for (int64_t e = hp.indptr[k]; e < hp.indptr[k + 1]; ++e) {
+                C[(size_t)hp.entry_slot[e] * n + k] += hp.entry_count[e];
+                tot += hp.entry_count[e];
+            }
+            check(tot == hp.totals[k], "large table total", k);
+        }
+        for (int32_t h = 1; h < hp.n_levels; ++h)
+            for (int32_t s = hp.level_ptr[h]; s < hp.level_ptr[h + 1]; ++s)
+                for (int32_t q = hp.child_ptr[s - hp.n_leaf]; q < hp.child_ptr[s - hp.n_leaf + 1]; ++q)
+                    for (int32_t k = 0; k < n; ++k) C[(size_t)s * n + k] += C[(size_t)hp.child_slot[q] * n + k];
+        for (int32_t v = 0; v < hp.n_nodes; ++v)
+            for (int32_t k = 0; k < n; ++k)
+                check(C[(size_t)hp.slot_of_node[v] * n + k] == want[(size_t)v * n + k], "large table counts", v, k);
+        Input bad = in;
+        bad.counts[bad.indptr[350] + 3] = -5;                 // late sample
+        bad.indices[bad.indptr[120] + 7] = bad.n_features;    // earlier sample
+        const uf_table bb = bad.table();
+        HostPrep hp2;
+        std::string err2;
+        check(validate_and_prepare(&t, &bb, &hp2, &err2) == UF_E_TABLE, "large table error code");
+        check(err2.find("row 120") != std::string::npos, "first error in sample order");
+    }
     std::printf("host checks: %d rounds, %d failures\n", rounds, g_failures);
     return g_failures == 0 ? 0 : 1;
 }

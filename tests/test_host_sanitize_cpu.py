@@ -24,7 +24,7 @@ def test_host_prep_under_sanitizers(tmp_path):
     if gxx is None or not os.path.exists(os.path.join(ROCM, "include", "hip", "hip_runtime.h")):
         pytest.skip("g++ or the HIP headers are not available")
     exe = str(tmp_path / "host_checks")
-    build = [gxx, "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+    build = [gxx, "-std=c++17", "-O1", "-g", "-pthread", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
              "-fno-omit-frame-pointer", "-D__HIP_PLATFORM_AMD__", f"-I{ROCM}/include",
              f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}",
              os.path.join(ROOT, "tests", "host_checks.cpp"), os.path.join(CSRC, "host_prep.cpp"), "-o", exe]
