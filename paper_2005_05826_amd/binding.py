@@ -163,6 +163,20 @@ def _ptr(a):
     return None if a is None else c_p(a.ctypes.data)
 
 
+def _host_array(n, dtype):
+    """A new host array of n elements for results copied back from the device: page-locked
+    (torch's pinned-memory allocator, which caches the blocks) when a GPU is in use, so the
+    copy runs at full link rate, else ordinary memory.  The array keeps the block alive."""
+    try:
+        import torch
+        if torch.cuda.is_available() and torch.cuda.is_initialized():
+            tdt = torch.float64 if np.dtype(dtype) == np.float64 else torch.float32
+            return torch.empty(max(int(n), 1), dtype=tdt, pin_memory=True).numpy()[:n]
+    except ImportError:
+        pass
+    return np.empty(n, dtype)
+
+
 class _Inputs:
     """Contiguous typed copies of the inputs plus the ABI structs pointing at them."""
 
@@ -323,7 +337,7 @@ class Plan:
         array, or a device tensor of n*(n-1)/2 elements (torch; its pointer is passed)."""
         n_pairs = self.info.n_pairs
         if out is None:
-            out = np.empty(n_pairs, np.float64 if out_dtype == "f64" else np.float32)
+            out = _host_array(n_pairs, np.float64 if out_dtype == "f64" else np.float32)
         if isinstance(out, np.ndarray):
             if out.size != n_pairs or not out.flags.c_contiguous:
                 raise ValueError("out must be a contiguous array of n*(n-1)/2 elements")
@@ -446,7 +460,7 @@ def distance(ctx: Context, prob, method="unweighted", precision="fp64", out_dtyp
     """One-shot uf_distance on a host output array."""
     inp = _Inputs(*_problem_args(prob))
     n = inp.indptr.shape[0] - 1
-    out = np.empty(n * (n - 1) // 2, np.float64 if out_dtype == "f64" else np.float32)
+    out = _host_array(n * (n - 1) // 2, np.float64 if out_dtype == "f64" else np.float32)
     ctx._check(_lib.uf_distance(ctx.handle, ctypes.byref(inp.tree), ctypes.byref(inp.table),
                                 METHODS[method], PRECISIONS[precision], DTYPES[out_dtype],
                                 _ptr(out), 0, None))
