@@ -121,6 +121,31 @@ def test_generated_presence_bits_equal_resident(uf, ctx, k_chunk, variant):
     limited.close()
 
 
+def test_generated_rows_dense_samples(uf, ctx):
+    """Samples with 2,044-2,125 distinct tips each, one at or below the 2,048 entries a
+    work-group stages in LDS and the others above (they search their entries in place), and
+    batch depths that leave a partial last pass of the branch loop."""
+    prob = workload_problem("binary_256", n=40, tips=12000, p_nonzero=0.5, depth=2850, seed=403)
+    sizes = np.diff(prob.indptr)
+    print(f"[dense samples] entries per sample {sizes.min()}..{sizes.max()}", flush=True)
+    assert sizes.min() <= 2048 < sizes.max()
+    resident = uf.Plan.from_problem(ctx, prob)
+    limited = uf.Plan.from_problem(ctx, prob)
+    limited.set_memory_limit(_row_limit(prob, 2, emb_batch=300))
+    ref = oracle.problem_condensed(prob, oracle.WEIGHTED_NORMALIZED)
+    for E in (300, 129):
+        tuning = dict(den_mode=0, tile=2, emb_batch=E, count_width=2, k_split=1)
+        want = resident.distance(WN, "fp64", tuning=tuning)
+        limited.set_profiling(True)
+        got = limited.distance(WN, "fp64", tuning=tuning)
+        assert _generated(limited) > 0, "the limit did not force generated rows"
+        limited.set_profiling(False)
+        np.testing.assert_array_equal(got, want)
+        assert np.abs(got - ref).max() <= 1e-12
+    resident.close()
+    limited.close()
+
+
 def test_limit_too_small_is_reported(uf, ctx):
     prob = CASES["binary_ragged_257"]()
     plan = uf.Plan.from_problem(ctx, prob)
