@@ -758,6 +758,47 @@ def bench_hbm(args):
     return res
 
 
+def _sig(x, n=3):
+    return float(f"{x:.{n}g}") if isinstance(x, float) else x
+
+
+def compact_target(rec):
+    """The figures of a nested target record (its own run prints the full record): time,
+    roofline, comparison, kernel times, CPU baseline and errors, without the descriptive
+    strings, so that the one JSON line stays a few kilobytes long."""
+    if "error" in rec and "value" not in rec:
+        return rec
+    out = {k: rec[k] for k in ("value", "ms_per_step", "dtype", "eager_run_ms", "wall_s") if k in rec}
+    if "value" in out:
+        out["value"] = _sig(out["value"], 5)
+    c = rec.get("config", {})
+    out["config"] = {k: c[k] for k in ("n_samples", "branches", "jobs", "stripes", "precision", "emb_batch")
+                     if k in c}
+    if "roofline" in rec:
+        r = rec["roofline"]
+        out["roofline"] = {k: r[k] for k in ("kernel", "bound", "achieved", "peak", "unit", "frac",
+                                             "algorithmic_bytes", "traffic") if k in r}
+    if "compare" in rec:
+        cm = rec["compare"]
+        out["compare"] = {k: cm[k] for k in ("precision", "ms_per_step", "speedup_of_headline") if k in cm}
+    if "methods" in rec:
+        out["methods_ms_per_step"] = {m: v["ms_per_step"] for m, v in rec["methods"].items()}
+    if "kernels_ms_per_step" in rec:
+        out["kernels_ms_per_step"] = rec["kernels_ms_per_step"]
+    if "end_to_end" in rec:
+        out["end_to_end_ms"] = rec["end_to_end"]["ms"]
+    if "tuning" in rec:
+        out["tuning"] = rec["tuning"].get("used")
+    if "cpu_baseline" in rec:
+        cb = rec["cpu_baseline"]
+        out["cpu_baseline"] = {k: _sig(cb[k], 4) for k in ("value", "cores", "seconds") if k in cb}
+        if "one_thread" in cb:
+            out["cpu_baseline"]["one_thread_value"] = _sig(cb["one_thread"]["value"], 4)
+    if "error_vs_oracle" in rec:
+        out["error_vs_oracle"] = {m: {k: _sig(v) for k, v in e.items()} for m, e in rec["error_vs_oracle"].items()}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -809,8 +850,12 @@ def main():
             for k in ("metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data"):
                 rec.pop(k, None)
             rec["wall_s"] = round(time.time() - t, 1)
-            res["targets"][name] = rec
+            res["targets"][name] = compact_target(rec)
             torch.cuda.empty_cache()
+    if res.get("targets"):
+        for r in (res, res.get("compare", {})):   # described in the module docstring
+            if isinstance(r.get("end_to_end"), dict):
+                r["end_to_end"].pop("what", None)
     print(json.dumps(res), flush=True)
 
 
