@@ -163,17 +163,22 @@ def _ptr(a):
     return None if a is None else c_p(a.ctypes.data)
 
 
+_PINNED_MAX_BYTES = 2 << 30
+
+
 def _host_array(n, dtype):
     """A new host array of n elements for results copied back from the device: page-locked
-    (torch's pinned-memory allocator, which caches the blocks) when a GPU is in use, so the
-    copy runs at full link rate, else ordinary memory.  The array keeps the block alive."""
-    try:
-        import torch
-        if torch.cuda.is_available() and torch.cuda.is_initialized():
-            tdt = torch.float64 if np.dtype(dtype) == np.float64 else torch.float32
-            return torch.empty(max(int(n), 1), dtype=tdt, pin_memory=True).numpy()[:n]
-    except ImportError:
-        pass
+    (torch's pinned-memory allocator, which caches the blocks) when a GPU is in use and the
+    array is at most 2 GiB, so the copy runs at full link rate, else ordinary memory.  The
+    array keeps its block alive."""
+    if int(n) * np.dtype(dtype).itemsize <= _PINNED_MAX_BYTES:
+        try:
+            import torch
+            if torch.cuda.is_available() and torch.cuda.is_initialized():
+                tdt = torch.float64 if np.dtype(dtype) == np.float64 else torch.float32
+                return torch.empty(max(int(n), 1), dtype=tdt, pin_memory=True).numpy()[:n]
+        except (ImportError, RuntimeError):
+            pass
     return np.empty(n, dtype)
 
 
