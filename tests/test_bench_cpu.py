@@ -47,3 +47,31 @@ def test_oracle_sample_grows_to_the_target_and_reports_its_size():
     assert want.shape == pi.shape and np.all((want >= 0) & (want <= 1))
     assert cpu["one_thread"]["pairs"] >= 16 and cpu["one_thread"]["value"] > 0
     assert str(pi.size) in cpu["sample"]
+
+
+def test_nested_target_records_keep_their_figures_compactly():
+    rec = {"metric": "m", "value": 441765807614559.3, "unit": "pair-branch updates/s", "steps": 3,
+           "warmup": 1, "ms_per_step": 424.415, "dtype": "bf16",
+           "config": {"workload": "x" * 200, "n_samples": 25000, "branches": 599998, "precision": "mfma_bf16x2"},
+           "full_matrix_wall_ms": 424.415, "kernels_ms_per_step": {"mfma": 414.3},
+           "roofline": {"kernel": "k_mfma_gemm", "bound": "mfma", "achieved": 1810.19, "peak": 2500.0,
+                        "unit": "TFLOP/s", "frac": 0.7241, "traffic": 300525769216,
+                        "traffic_detail": {"profile": "p" * 80}},
+           "compare": {"precision": "fp64", "ms_per_step": 27704.0, "speedup_of_headline": 65.3,
+                       "kernels_ms_per_step": {"stripe": 27676.8}},
+           "end_to_end": {"ms": 819.2, "runs": 1, "what": "w" * 150},
+           "cpu_baseline": {"value": 3969486239.6, "unit": "u", "cores": 16, "kind": "oracle",
+                            "sample": "s" * 200, "seconds": 5.79, "one_thread": {"value": 124926253.6}},
+           "error_vs_oracle": {"mfma_bf16x2": {"max_abs": 3.07580687142206e-07, "mean_abs": 6.1e-08,
+                                               "pairs": 38301}},
+           "wall_s": 68.9}
+    out = bench.compact_target(rec)
+    assert out["ms_per_step"] == 424.415 and out["roofline"]["frac"] == 0.7241
+    assert out["roofline"]["traffic"] == 300525769216 and "traffic_detail" not in out["roofline"]
+    assert out["compare"]["speedup_of_headline"] == 65.3 and out["end_to_end_ms"] == 819.2
+    assert out["cpu_baseline"]["cores"] == 16 and out["cpu_baseline"]["one_thread_value"] > 0
+    assert out["error_vs_oracle"]["mfma_bf16x2"]["max_abs"] == 3.08e-07
+    assert out["config"] == {"n_samples": 25000, "branches": 599998, "precision": "mfma_bf16x2"}
+    assert len(json.dumps(out)) < 1000
+    err = {"error": "RuntimeError: boom", "wall_s": 1.0}
+    assert bench.compact_target(err) == err
