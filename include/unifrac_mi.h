@@ -338,7 +338,8 @@ uf_status uf_batch_capture(uf_batch *batch);
 uf_status uf_batch_set_profiling(uf_batch *batch, int32_t enable);
 uf_status uf_batch_get_profile(uf_batch *batch, uf_kernel_stat *out, int32_t cap, int32_t *n_out);
 void uf_batch_destroy(uf_batch *batch);
-/* One-shot: create, run, destroy. */
+/* One-shot: create, run on `stream`, wait for the stream, destroy.  Blocks until every
+ * output is valid; the same errors as uf_batch_create and uf_batch_run. */
 uf_status uf_distance_batch(uf_context *ctx, const uf_job *jobs, int32_t n_jobs, void *stream);
 
 /* One-shot convenience: plan_create + plan_distance + plan_destroy. */

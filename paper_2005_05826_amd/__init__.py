@@ -14,6 +14,7 @@ from .binding import (  # noqa: F401
     UfTuning,
     UniFracError,
     distance,
+    distance_batch,
     library,
     mantel,
     merge_block,

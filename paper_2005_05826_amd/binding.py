@@ -472,6 +472,15 @@ def distance(ctx: Context, prob, method="unweighted", precision="fp64", out_dtyp
     return out
 
 
+def distance_batch(ctx: Context, jobs, stream=None):
+    """One-shot uf_distance_batch: the jobs (dicts as for Batch; outputs given) computed
+    together and the call's scratch released again.  Blocks until the outputs are valid."""
+    arr, keep = _job_array(jobs)
+    ctx._check(_lib.uf_distance_batch(ctx.handle, arr, len(jobs), _stream_handle(stream)))
+    del keep
+    return [j.get("out") for j in jobs]
+
+
 def _job_array(jobs):
     """ABI job array for a list of dicts (problem, method, precision, out, out_dtype); `out`
     is a device tensor, a host numpy array, or None.  Returns the array and the objects that

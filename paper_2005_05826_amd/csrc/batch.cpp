@@ -571,6 +571,11 @@ uf_status uf_distance_batch(uf_context *ctx, const uf_job *jobs, int32_t n_jobs,
     uf_status s = uf_batch_create(ctx, jobs, n_jobs, nullptr, stream, &b);
     if (s != UF_OK) return s;
     s = uf_batch_run(b, stream);
+    // the batch's buffers are released below: wait for the work that reads them
+    if (s == UF_OK) {
+        const hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+        if (e != hipSuccess) s = hip_fail(ctx, e, "synchronizing the batch");
+    }
     uf_batch_destroy(b);
     return s;
 }

@@ -200,3 +200,22 @@ def test_batch_int32_counts_deep_batches_and_unnormalized(uf, ctx):
         print(f"[int32/E512] n={p.n_samples} {m} {pr} max_abs_err={err:.3e} (tol {tol:.1e})", flush=True)
         assert err <= tol, (p.n_samples, m, pr, err)
     b.close()
+
+
+def test_distance_batch_one_shot_equals_batch(uf, ctx, jobs):
+    """uf_distance_batch (create, run, wait, destroy in one call) with device and host
+    outputs gives the persistent batch's results bit for bit."""
+    import torch
+    want_outs = _outs(jobs)
+    b = uf.Batch(ctx, [dict(problem=p, method=m, precision=pr, out=o) for (p, m, pr), o in zip(jobs, want_outs)])
+    b.run()
+    torch.cuda.synchronize()
+    b.close()
+    outs = [o if i % 2 == 0 else np.full(o.numel(), -1.0) for i, o in enumerate(_outs(jobs))]
+    uf.distance_batch(ctx, [dict(problem=p, method=m, precision=pr, out=o)
+                            for (p, m, pr), o in zip(jobs, outs)])
+    for o, w in zip(outs, want_outs):
+        got = o if isinstance(o, np.ndarray) else o.cpu().numpy()
+        np.testing.assert_array_equal(got, w.cpu().numpy())
+    _check(jobs, [torch.from_numpy(o).to("cuda:0") if isinstance(o, np.ndarray) else o for o in outs],
+           _want(jobs), "distance_batch")

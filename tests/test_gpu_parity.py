@@ -464,3 +464,15 @@ def test_stripe_blocks_from_independent_plans_merge(uf, ctx, problems, case, out
         c2.close()
     torch.cuda.synchronize()
     np.testing.assert_array_equal(merged.cpu().numpy(), full)
+
+
+def test_trim_releases_scratch_and_keeps_results(uf, ctx, problems):
+    """uf_plan_trim frees the plan's scratch (count rows, stripe state, matrix-core buffers);
+    the next call rebuilds it and gives the same distances bit for bit."""
+    plan = uf.Plan.from_problem(ctx, problems["coalescent_513"])
+    for method, prec in ((WN, "fp32"), (UW, "mfma_bf16x2"), (WN, "fp64")):
+        a = plan.distance(method, prec)
+        plan.trim()
+        b = plan.distance(method, prec)
+        np.testing.assert_array_equal(a, b)
+    plan.close()
