@@ -149,19 +149,36 @@ __global__ __launch_bounds__(kBlock, 2) void k_stripe(
             for (int r = 0; r < TKT; ++r) u[r] = su[e * TKW + lane * TKT + r];
 #pragma unroll
             for (int c = 0; c < NV; ++c) v[c] = sv[e * VW + lane * TKT + w * TST + c];
+            // an += |u - v| L and, with the pair-wise denominator, ad += (u + v) L or max(u, v) L.
+            // With the numerator alone the differences of four samples are formed before their
+            // four FMAs: measured about 1 % faster on the FP32 weighted normalized stripes than
+            // pairing each difference with its FMA.
+            if constexpr (DEN == 1 && TKT % 4 == 0) {
 #pragma unroll
-            for (int s = 0; s < TST; ++s)
+                for (int s = 0; s < TST; ++s)
 #pragma unroll
-                for (int r = 0; r < TKT; ++r) {
-                    const T x = v[r + s];
-                    an[s][r] = fma(fabs(u[r] - x), L, an[s][r]);
-                    if (DEN == 0) {
-                        if (METHOD == UF_WEIGHTED_NORMALIZED)
-                            ad[s][r] = fma(u[r] + x, L, ad[s][r]);
-                        else
-                            ad[s][r] = fma(fmax(u[r], x), L, ad[s][r]);
+                    for (int r = 0; r < TKT; r += 4) {
+                        T d[4];
+#pragma unroll
+                        for (int g = 0; g < 4; ++g) d[g] = u[r + g] - v[r + g + s];
+#pragma unroll
+                        for (int g = 0; g < 4; ++g) an[s][r + g] = fma(fabs(d[g]), L, an[s][r + g]);
                     }
-                }
+            } else {
+#pragma unroll
+                for (int s = 0; s < TST; ++s)
+#pragma unroll
+                    for (int r = 0; r < TKT; ++r) {
+                        const T x = v[r + s];
+                        an[s][r] = fma(fabs(u[r] - x), L, an[s][r]);
+                        if (DEN == 0) {
+                            if (METHOD == UF_WEIGHTED_NORMALIZED)
+                                ad[s][r] = fma(u[r] + x, L, ad[s][r]);
+                            else
+                                ad[s][r] = fma(fmax(u[r], x), L, ad[s][r]);
+                        }
+                    }
+            }
         }
     }
 
@@ -338,19 +355,36 @@ __device__ void stripe_tile(const StripeArgs &a, int32_t k0, int32_t s0, int32_t
             T u[TKT], v[NV];
             lds_read_vec<T, TKT>(su + e * TKW + lane * TKT, u);
             lds_read_vec<T, NV>(sv + e * VW + lane * TKT + w * TST, v);
+            // an += |u - v| L and, with the pair-wise denominator, ad += (u + v) L or max(u, v) L.
+            // With the numerator alone the differences of four samples are formed before their
+            // four FMAs: measured about 1 % faster on the FP32 weighted normalized stripes than
+            // pairing each difference with its FMA.
+            if constexpr (DEN == 1 && TKT % 4 == 0) {
 #pragma unroll
-            for (int s = 0; s < TST; ++s)
+                for (int s = 0; s < TST; ++s)
 #pragma unroll
-                for (int r = 0; r < TKT; ++r) {
-                    const T x = v[r + s];
-                    an[s][r] = fma(fabs(u[r] - x), L, an[s][r]);
-                    if (DEN == 0) {
-                        if (METHOD == UF_WEIGHTED_NORMALIZED)
-                            ad[s][r] = fma(u[r] + x, L, ad[s][r]);
-                        else
-                            ad[s][r] = fma(fmax(u[r], x), L, ad[s][r]);
+                    for (int r = 0; r < TKT; r += 4) {
+                        T d[4];
+#pragma unroll
+                        for (int g = 0; g < 4; ++g) d[g] = u[r + g] - v[r + g + s];
+#pragma unroll
+                        for (int g = 0; g < 4; ++g) an[s][r + g] = fma(fabs(d[g]), L, an[s][r + g]);
                     }
-                }
+            } else {
+#pragma unroll
+                for (int s = 0; s < TST; ++s)
+#pragma unroll
+                    for (int r = 0; r < TKT; ++r) {
+                        const T x = v[r + s];
+                        an[s][r] = fma(fabs(u[r] - x), L, an[s][r]);
+                        if (DEN == 0) {
+                            if (METHOD == UF_WEIGHTED_NORMALIZED)
+                                ad[s][r] = fma(u[r] + x, L, ad[s][r]);
+                            else
+                                ad[s][r] = fma(fmax(u[r], x), L, ad[s][r]);
+                        }
+                    }
+            }
         }
         if (e0 + eb >= b1) {   // end of a batch: add the register tile into the FP64 state
             // the offset passes through an empty asm so that the row addresses are formed
