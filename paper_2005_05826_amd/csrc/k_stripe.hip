@@ -12,6 +12,8 @@
 // LDS, the window of samples k (TKW values) and the window of samples k + s + 1
 // (TKW + TSW - 1 values) with coalesced loads; every lane then owns TKT consecutive samples
 // of TST consecutive stripes, which need only TKT + TKT + TST - 1 values per branch.
+#include <type_traits>
+
 #include "uf_internal.h"
 
 namespace ufmi {
@@ -150,10 +152,13 @@ __global__ __launch_bounds__(kBlock, 2) void k_stripe(
 #pragma unroll
             for (int c = 0; c < NV; ++c) v[c] = sv[e * VW + lane * TKT + w * TST + c];
             // an += |u - v| L and, with the pair-wise denominator, ad += (u + v) L or max(u, v) L.
-            // With the numerator alone the differences of four samples are formed before their
-            // four FMAs: measured about 1 % faster on the FP32 weighted normalized stripes than
-            // pairing each difference with its FMA.
-            if constexpr (DEN == 1 && TKT % 4 == 0) {
+            // Where measured faster (interleaved runs on one GPU) the non-FMA operations of a
+            // lane's samples are formed before their FMAs: FP32 with the numerator alone at
+            // four samples per lane (1-1.5 %), FP64 with both stripes at two samples per lane
+            // (1-1.4 %).  Grouping was slower for FP32 at eight samples per lane, for the FP32
+            // num + den form and for FP64 at four samples per lane, which keep each operation
+            // beside its FMA.
+            if constexpr (DEN == 1 && std::is_same_v<T, float> && TKT == 4) {
 #pragma unroll
                 for (int s = 0; s < TST; ++s)
 #pragma unroll
@@ -164,6 +169,22 @@ __global__ __launch_bounds__(kBlock, 2) void k_stripe(
 #pragma unroll
                         for (int g = 0; g < 4; ++g) an[s][r + g] = fma(fabs(d[g]), L, an[s][r + g]);
                     }
+            } else if constexpr (DEN == 0 && std::is_same_v<T, double> && TKT == 2) {
+#pragma unroll
+                for (int s = 0; s < TST; ++s) {
+                    T d[2], q[2];
+#pragma unroll
+                    for (int g = 0; g < 2; ++g) {
+                        const T x = v[g + s];
+                        d[g] = u[g] - x;
+                        q[g] = METHOD == UF_WEIGHTED_NORMALIZED ? u[g] + x : fmax(u[g], x);
+                    }
+#pragma unroll
+                    for (int g = 0; g < 2; ++g) {
+                        an[s][g] = fma(fabs(d[g]), L, an[s][g]);
+                        ad[s][g] = fma(q[g], L, ad[s][g]);
+                    }
+                }
             } else {
 #pragma unroll
                 for (int s = 0; s < TST; ++s)
@@ -356,10 +377,13 @@ __device__ void stripe_tile(const StripeArgs &a, int32_t k0, int32_t s0, int32_t
             lds_read_vec<T, TKT>(su + e * TKW + lane * TKT, u);
             lds_read_vec<T, NV>(sv + e * VW + lane * TKT + w * TST, v);
             // an += |u - v| L and, with the pair-wise denominator, ad += (u + v) L or max(u, v) L.
-            // With the numerator alone the differences of four samples are formed before their
-            // four FMAs: measured about 1 % faster on the FP32 weighted normalized stripes than
-            // pairing each difference with its FMA.
-            if constexpr (DEN == 1 && TKT % 4 == 0) {
+            // Where measured faster (interleaved runs on one GPU) the non-FMA operations of a
+            // lane's samples are formed before their FMAs: FP32 with the numerator alone at
+            // four samples per lane (1-1.5 %), FP64 with both stripes at two samples per lane
+            // (1-1.4 %).  Grouping was slower for FP32 at eight samples per lane, for the FP32
+            // num + den form and for FP64 at four samples per lane, which keep each operation
+            // beside its FMA.
+            if constexpr (DEN == 1 && std::is_same_v<T, float> && TKT == 4) {
 #pragma unroll
                 for (int s = 0; s < TST; ++s)
 #pragma unroll
@@ -370,6 +394,22 @@ __device__ void stripe_tile(const StripeArgs &a, int32_t k0, int32_t s0, int32_t
 #pragma unroll
                         for (int g = 0; g < 4; ++g) an[s][r + g] = fma(fabs(d[g]), L, an[s][r + g]);
                     }
+            } else if constexpr (DEN == 0 && std::is_same_v<T, double> && TKT == 2) {
+#pragma unroll
+                for (int s = 0; s < TST; ++s) {
+                    T d[2], q[2];
+#pragma unroll
+                    for (int g = 0; g < 2; ++g) {
+                        const T x = v[g + s];
+                        d[g] = u[g] - x;
+                        q[g] = METHOD == UF_WEIGHTED_NORMALIZED ? u[g] + x : fmax(u[g], x);
+                    }
+#pragma unroll
+                    for (int g = 0; g < 2; ++g) {
+                        an[s][g] = fma(fabs(d[g]), L, an[s][g]);
+                        ad[s][g] = fma(q[g], L, ad[s][g]);
+                    }
+                }
             } else {
 #pragma unroll
                 for (int s = 0; s < TST; ++s)
