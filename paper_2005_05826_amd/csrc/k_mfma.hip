@@ -22,7 +22,11 @@
 // those of the operands hi, lo and 1.0.  Each presence byte is expanded through a 256-entry
 // table in LDS, and the steps of a stage are software-pipelined: while the matrix
 // instructions of one 16-branch step run, the LDS words of the step after next are read, the
-// operands of the next one built and an eighth of the next stage expanded.
+// operands of the next one built and an eighth of the next stage expanded.  The lengths of a
+// step are the same for the 32 lanes of each K half: a stage's length words are stored so that
+// each lane reads its eight (one per step) at once, and each step takes the four hi and four lo
+// words of its K half from lanes 0-7 of the lane's 16-lane row by DPP broadcast, folded into
+// the ANDs that mask them.
 #include "uf_internal.h"
 
 namespace ufmi {
@@ -112,6 +116,13 @@ __device__ inline void expand_bits(uint32_t x, uint32_t c, uint32_t (&out)[8])
     }
 }
 
+// x of lane N of the calling lane's 16-lane row (DPP row_newbcast)
+template <int N>
+__device__ inline uint32_t row_bcast(uint32_t x)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x150 + N, 0xF, 0xF, false);
+}
+
 __device__ inline bf16x8 as_bf16x8(uint32_t a, uint32_t b, uint32_t c, uint32_t d)
 {
     typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -120,7 +131,8 @@ __device__ inline bf16x8 as_bf16x8(uint32_t a, uint32_t b, uint32_t c, uint32_t 
 }
 
 // Two LDS stages: the next stage's global loads are in flight while this one computes.
-// hl holds the stage's hi splits followed by its lo splits.
+// hl holds the stage's hi and lo split words (two branches each) in reading order: the word
+// of step kk (16 branches), K half g and position p (0-3 hi, 4-7 lo) at (8 g + p) * 8 + kk.
 // lut[p][v] holds the eight expanded bytes of presence byte v for panel p (0 rows, 1 columns).
 struct MfmaSmem {
     __align__(16) uint8_t A[2][GM * LDK];
@@ -150,7 +162,6 @@ template <bool REG64>
 __device__ void mfma_tile(const MfmaArgs &a, int32_t row0, int32_t col0, MfmaSmem &sm)
 {
     const uint8_t *__restrict__ P = a.P;
-    const int64_t k_pad = a.k_pad;
     const int32_t n_kstep = a.n_kstep, chunk_steps = a.chunk_steps, n = a.n;
     double *__restrict__ S = a.S;
     double *__restrict__ T = a.T;
@@ -177,12 +188,15 @@ __device__ void mfma_tile(const MfmaArgs &a, int32_t row0, int32_t col0, MfmaSme
 
     // each thread stages the 16 bytes of presence bits of one row (threads 0..127 the row
     // panel, 128..255 the column panel) and one dword of the hi or lo splits (threads 128..
-    // repeat the dwords of threads 0..127, writing the same values)
+    // repeat the dwords of threads 0..127, writing the same values): dword hd of the stage's
+    // 64 holds branches 2 hd and 2 hd + 1, i.e. step hd / 8, K half (hd % 8) / 4, position
+    // hd % 4 (+ 4 for lo)
     const int64_t kb = a.k_pad / 8;
     const uint8_t *prow = P + (int64_t)((tid < 128 ? row0 : col0) + (tid & 127)) * kb;
     uint8_t *srow = (tid < 128 ? &sm.A[0][0] : &sm.B[0][0]) + (tid & 127) * LDK;
     const uint32_t *phl = reinterpret_cast<const uint32_t *>((tid & 64) ? a.lo : a.hi) + (tid & 63);
-    const int hoff = tid & 127;
+    const int hd = tid & 63;
+    const int hpos = (((hd & 7) >> 2) * 8 + (hd & 3) + ((tid & 64) ? 4 : 0)) * 8 + (hd >> 3);
     const uint2 *lut = sm.lut[tid < 128 ? 0 : 1];
     // Global loads run two stages ahead of the compute: stage ks + 2 is loaded into one
     // register set while stage ks + 1 (loaded one stage earlier) waits in the other and is
@@ -210,26 +224,30 @@ __device__ void mfma_tile(const MfmaArgs &a, int32_t row0, int32_t col0, MfmaSme
         const uint2 e1 = lut[(x >> (16 * h + 8)) & 0xFFu];
         dst[4 * q + 2 * h] = e0;
         dst[4 * q + 2 * h + 1] = e1;
-        if (part == 0) reinterpret_cast<uint32_t *>(sm.hl[buf])[hoff] = R.hl;
+        if (part == 0) reinterpret_cast<uint32_t *>(sm.hl[buf])[hpos] = R.hl;
     };
     auto lstore = [&](const Stage &R, int buf) {
 #pragma unroll
         for (int part = 0; part < GK / 16; ++part) store_part(R, buf, part);
     };
-    // LDS words of one 16-branch step: the lane's hi and lo splits, its two row-panel and
-    // two column-panel byte runs; and the MFMA operands built from them
+    // LDS words of one 16-branch step: the lane's two row-panel and two column-panel byte
+    // runs; and the MFMA operands built from them and the step's length words
     struct Raw {
-        uint4 h, l;
         uint2 a[2], b[2];
     };
     struct Ops {
         bf16x8 ahi[2], alo[2], bo[2];
     };
+    // the lane's length word of every step of the stage (position lane % 8 of its K half)
+    static_assert(GK / 16 == 8, "a lane's length words of one stage are two 16-byte reads");
+    auto lds_hl = [&](int buf, uint32_t (&hl8)[GK / 16]) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(sm.hl[buf]) + (kg * 8 + (lane & 7)) * 2;
+        const uint4 x = src[0], y = src[1];
+        hl8[0] = x.x; hl8[1] = x.y; hl8[2] = x.z; hl8[3] = x.w;
+        hl8[4] = y.x; hl8[5] = y.y; hl8[6] = y.z; hl8[7] = y.w;
+    };
     auto lds_raw = [&](int buf, int kk, Raw &r) {
         const int koff = kk * 16 + kg * 8;
-        const uint16_t *chl = sm.hl[buf];
-        r.h = *reinterpret_cast<const uint4 *>(chl + koff);
-        r.l = *reinterpret_cast<const uint4 *>(chl + GK + koff);
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb)
             r.a[mb] = *reinterpret_cast<const uint2 *>(sm.A[buf] + (wm * 64 + mb * 32 + lrow) * LDK + koff);
@@ -237,7 +255,7 @@ __device__ void mfma_tile(const MfmaArgs &a, int32_t row0, int32_t col0, MfmaSme
         for (int nb = 0; nb < 2; ++nb)
             r.b[nb] = *reinterpret_cast<const uint2 *>(sm.B[buf] + (wn * 64 + nb * 32 + lrow) * LDK + koff);
     };
-    auto build = [&](const Raw &r, Ops &o) {
+    auto build = [&](const Raw &r, uint32_t hl, Ops &o) {
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb) {
             const uint2 m = r.a[mb];
@@ -245,8 +263,10 @@ __device__ void mfma_tile(const MfmaArgs &a, int32_t row0, int32_t col0, MfmaSme
             const uint32_t m1 = __builtin_amdgcn_perm(m.x, m.x, 0x03030202u);
             const uint32_t m2 = __builtin_amdgcn_perm(m.y, m.y, 0x01010000u);
             const uint32_t m3 = __builtin_amdgcn_perm(m.y, m.y, 0x03030202u);
-            o.ahi[mb] = as_bf16x8(m0 & r.h.x, m1 & r.h.y, m2 & r.h.z, m3 & r.h.w);
-            o.alo[mb] = as_bf16x8(m0 & r.l.x, m1 & r.l.y, m2 & r.l.z, m3 & r.l.w);
+            o.ahi[mb] = as_bf16x8(m0 & row_bcast<0>(hl), m1 & row_bcast<1>(hl),
+                                  m2 & row_bcast<2>(hl), m3 & row_bcast<3>(hl));
+            o.alo[mb] = as_bf16x8(m0 & row_bcast<4>(hl), m1 & row_bcast<5>(hl),
+                                  m2 & row_bcast<6>(hl), m3 & row_bcast<7>(hl));
         }
 #pragma unroll
         for (int nb = 0; nb < 2; ++nb) {
@@ -275,18 +295,20 @@ __device__ void mfma_tile(const MfmaArgs &a, int32_t row0, int32_t col0, MfmaSme
     // nothing reads.
     auto compute_store = [&](int buf, const Stage &Rn, int nbuf) {
         constexpr int NKK = GK / 16;
+        uint32_t hl8[NKK];
         Raw r0, r1;
         Ops o;
+        lds_hl(buf, hl8);
         lds_raw(buf, 0, r0);
         lds_raw(buf, 1, r1);
-        build(r0, o);
+        build(r0, hl8[0], o);
 #pragma unroll
         for (int kk = 0; kk < NKK; ++kk) {
             Raw r2;
             if (kk + 2 < NKK) lds_raw(buf, kk + 2, r2);
             mfma8(o);
             store_part(Rn, nbuf, kk);
-            if (kk + 1 < NKK) build(r1, o);
+            if (kk + 1 < NKK) build(r1, hl8[kk + 1], o);
             if (kk + 2 < NKK) r1 = r2;
             // each matrix instruction followed by the VALU work that runs beside it; the
             // LDS reads early, the LDS writes of the expansion mid-way
@@ -297,7 +319,6 @@ __device__ void mfma_tile(const MfmaArgs &a, int32_t row0, int32_t col0, MfmaSme
                 __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);
             }
             __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-            __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
             __builtin_amdgcn_sched_group_barrier(0x002, 5, 0);
             __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
             __builtin_amdgcn_sched_group_barrier(0x200, 2, 0);
