@@ -279,14 +279,19 @@ __device__ void mfma_tile(const MfmaArgs &a, int32_t row0, int32_t col0, MfmaSme
         }
     };
     f32x16 acc[2][2];
+    // the four hi products first, then the four lo ones: no matrix instruction waits on the
+    // accumulator of the one just issued (0.4 % faster than hi and lo of a block back to back)
     auto mfma8 = [&](const Ops &o) {
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-            for (int nb = 0; nb < 2; ++nb) {
+            for (int nb = 0; nb < 2; ++nb)
                 acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.ahi[mb], o.bo[nb], acc[mb][nb], 0, 0, 0);
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb)
                 acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(o.alo[mb], o.bo[nb], acc[mb][nb], 0, 0, 0);
-            }
     };
     // Stage ks from LDS buffer buf, software-pipelined: the LDS words of step kk + 2 are read
     // and the operands of step kk + 1 built while the matrix instructions of step kk run,
