@@ -132,7 +132,7 @@ typedef struct {
     int32_t count_width; /* striped path: bytes per embedding count; 0 = 2 when every sample
                            total fits in 16 bits (halves count memory and traffic), else 4;
                            4 = int32; 2 = uint16 (UF_E_ARG if a total exceeds 65535)         */
-    int32_t k_split;    /* fused striped kernel (single plans): the branches are split into
+    int32_t k_split;    /* fused and queued striped kernels: the branches are split into
                            this many contiguous ranges, each accumulated by its own grid
                            slice into its own copy of the stripe state, and the copies are
                            summed in order afterwards (more work-groups when the stripe
@@ -141,8 +141,10 @@ typedef struct {
                            stripe tiles, also for stripe ranges; at most 16 splits, 64 when
                            16 would not fill the device once; at least two batches per
                            split, an FP64 batch depth left at its default shrinking to as
-                           few as 64 branches to allow that; the state copies within 4 GB),
-                           1 = no split                                                      */
+                           few as 64 branches to allow that; the state copies within 4 GB;
+                           in a batch only while all its jobs' stripe tiles come to fewer
+                           than ten device rounds, so a job splits as it would alone), 1 =
+                           no split                                                          */
 } uf_tuning;
 
 typedef struct {
@@ -326,8 +328,10 @@ typedef struct {
 } uf_job;
 typedef struct uf_batch uf_batch;
 /* tuning: when non-NULL its knobs (emb_batch, den_mode, tile, count_width, k_chunk,
- * variant) apply to every job; when NULL every job takes the knobs uf_autotune stored in the
- * context for a problem of its kind and size, or the library defaults. */
+ * variant, k_split) apply to every job; when NULL every job takes the knobs uf_autotune
+ * stored in the context for a problem of its kind and size, or the library defaults.  A
+ * striped job's branch splits are queue items of their own, each into its own copy of the
+ * job's stripe state, summed in split order before the condense. */
 uf_status uf_batch_create(uf_context *ctx, const uf_job *jobs, int32_t n_jobs,
                           const uf_tuning *tuning, void *stream, uf_batch **out);
 /* Runs every job (replaying the captured graph if there is one) and waits for it. */

@@ -6,7 +6,8 @@
 // persistent queue-driven striped launch per kernel form (precision, method, count width,
 // denominator mode, tile shape), one persistent queue-driven MFMA launch per accumulation
 // variant on a second stream beside them, and per-job condense/normalize launches.  Every
-// job carries its own knobs (batch depth, MFMA chunk), so one batch can mix tunings.  The
+// job carries its own knobs (batch depth, MFMA chunk, branch splits), so one batch can mix
+// tunings; a batch too small to fill the device splits its jobs' branches as single plans do.  The
 // queues are ordered largest job first, so idle work-groups always pick the most expensive
 // remaining tile (a longest-processing-time-first schedule).  The whole sequence can be captured
 // once into a HIP graph and replayed; it allocates nothing and uses fill kernels (not
@@ -24,6 +25,8 @@ using namespace ufmi;
 // library defaults.
 struct JobKnobs {
     int32_t E, den_mode, tile, count_width, k_chunk, variant;
+    int32_t k_split;   // striped branch splits: 0 automatic, else at most this many
+    int32_t e_free;    // 1: E is the FP64 default and may shrink for branch splits
 };
 
 struct uf_batch {
@@ -31,6 +34,7 @@ struct uf_batch {
     std::vector<uf_plan *> plans;
     std::vector<uf_job> jobs;
     std::vector<JobKnobs> knobs;
+    std::vector<int32_t> kz;              // branch splits of every striped job (state copies)
     std::vector<void *> dev_out;          // device output of every job (its own or staging)
     int32_t n_cus = 256;
     // propagation tables
@@ -146,7 +150,7 @@ uf_status enqueue(uf_batch *b, hipStream_t st)
         uf_plan *p = b->plans[j];
         const JobKnobs &K = b->knobs[j];
         const StripeGeom g = stripe_geometry(p->hp.n_samples, b->jobs[j].prec == UF_PREC_FP64, K.den_mode, K.tile);
-        const size_t words = (size_t)g.spad * g.sstride * 2;
+        const size_t words = (size_t)g.spad * g.sstride * 2 * b->kz[j];
         UF_TRY(launch_fill_u32(p->num.p, 0u, words, st), "clearing stripes");
         if (K.den_mode == 0) UF_TRY(launch_fill_u32(p->den.p, 0u, words, st), "clearing stripes");
         UF_TRY(launch_inv_totals(p->totals.as<int32_t>(), p->hp.n_samples, p->inv_t.as<double>(), st),
@@ -173,6 +177,15 @@ uf_status enqueue(uf_batch *b, hipStream_t st)
         const uf_job &J = b->jobs[j];
         const JobKnobs &K = b->knobs[j];
         const StripeGeom g = stripe_geometry(p->hp.n_samples, J.prec == UF_PREC_FP64, K.den_mode, K.tile);
+        if (b->kz[j] > 1) {   // the branch splits' state copies, summed in split order
+            const int64_t cnt = (int64_t)g.spad * g.sstride;
+            UF_TRY(timed(b->prof, "stripe", st, [&] {
+                       hipError_t r = launch_reduce_z(p->num.as<double>(), cnt, b->kz[j], cnt, st);
+                       if (r == hipSuccess && K.den_mode == 0)
+                           r = launch_reduce_z(p->den.as<double>(), cnt, b->kz[j], cnt, st);
+                       return r;
+                   }), "summing branch splits");
+        }
         if (K.den_mode != 0 && J.method != UF_WEIGHTED_UNNORMALIZED)
             UF_TRY(launch_rowdot(J.method, p->counts.p, p->cw, p->cstride, 0, p->hp.n_nodes - 1,
                                  p->totals.as<int32_t>(), p->len_slot.as<double>(), g.n,
@@ -272,6 +285,19 @@ uf_status build_tables(uf_batch *b, hipStream_t st)
     });
     std::vector<std::vector<StripeArgs>> sj(uf_batch::kQueues);
     std::vector<std::vector<int32_t>> items(uf_batch::kQueues);
+    // Branch splits: a tuning's k_split, else the single plan's automatic rule while all the
+    // batch's stripe tiles come to fewer than ten rounds of the device (a job then gets the
+    // splits and batch depth, and so the results, it gets when run alone); none once the
+    // tiles fill the device by themselves.
+    double rounds = 0.0;
+    for (int32_t j = 0; j < nj; ++j) {
+        if (!is_striped(b->jobs[j])) continue;
+        const StripeGeom g = stripe_geometry(b->plans[j]->hp.n_samples, b->jobs[j].prec == UF_PREC_FP64,
+                                             b->knobs[j].den_mode, b->knobs[j].tile);
+        rounds += (double)(g.sstride / g.tkw) * (g.spad / g.tsw) / ((double)b->n_cus * std::max(g.occ, 1));
+    }
+    const bool device_full = rounds >= 10.0;
+    b->kz.assign(nj, 1);
     for (int32_t j : order) {
         const uf_job &J = b->jobs[j];
         if (!is_striped(J)) continue;
@@ -284,25 +310,43 @@ uf_status build_tables(uf_batch *b, hipStream_t st)
         const int q = queue_of(!fp64, km == UF_WEIGHTED_NORMALIZED, p->cw == 2, K.den_mode, K.tile);
         const StripeGeom g = stripe_geometry(hp.n_samples, fp64, K.den_mode, K.tile);
         const size_t state = (size_t)g.spad * g.sstride * sizeof(double);
-        UF_TRY(p->num.ensure(state), "allocating stripes");
-        if (K.den_mode == 0) UF_TRY(p->den.ensure(state), "allocating stripes");
+        int32_t E = std::max(1, std::min({K.E, 4096, std::max(1, hp.n_nodes - 1)}));
+        int32_t kz = 1;
+        if (K.k_split > 0 || !device_full) {
+            Knobs kn{};
+            kn.emb_batch = E;
+            kn.k_chunk = K.k_chunk;
+            kn.den_mode = K.den_mode;
+            kn.variant = 0;   // the queues always run the fused form
+            kn.tile = K.tile;
+            kn.count_width = K.count_width;
+            kn.k_split = K.k_split;
+            kn.e_free = K.e_free;
+            kz = striped_k_split(p, kn, g, state);
+            E = kn.emb_batch;
+        }
+        b->kz[j] = kz;
+        UF_TRY(p->num.ensure(state * kz), "allocating stripes");
+        if (K.den_mode == 0) UF_TRY(p->den.ensure(state * kz), "allocating stripes");
         UF_TRY(p->D.ensure((size_t)hp.n_samples * sizeof(double)), "allocating sums");
         if (K.den_mode != 0)
             UF_TRY(p->rowdot_part.ensure(rowdot_scratch_elems(hp.n_samples, hp.n_nodes - 1) * sizeof(double)),
                    "allocating sum scratch");
         UF_TRY(p->inv_t.ensure((size_t)hp.n_samples * sizeof(double)), "allocating totals");
-        const int32_t E = std::max(1, std::min(K.E, std::max(1, hp.n_nodes - 1)));
         const int32_t idx = (int32_t)sj[q].size();
         sj[q].push_back(make_stripe_args(km, p->counts.p, p->cw, p->cstride,
                                          p->inv_t.as<double>(), p->len_slot.as<double>(),
                                          hp.n_nodes - 1, E, p->num.as<double>(),
                                          K.den_mode == 0 ? p->den.as<double>() : nullptr, g));
+        sj[q].back().kz = kz;
+        sj[q].back().zstride = (int64_t)(state / sizeof(double));
         if (hp.n_nodes - 1 <= 0 || g.S == 0) continue;  // nothing to accumulate
         const int32_t n_tiles = sj[q].back().tiles_k * sj[q].back().tiles_s;
-        for (int32_t t = 0; t < n_tiles; ++t) {
-            items[q].push_back(idx);
-            items[q].push_back(t);
-        }
+        for (int32_t z = 0; z < kz; ++z)
+            for (int32_t t = 0; t < n_tiles; ++t) {
+                items[q].push_back(idx);
+                items[q].push_back(z * n_tiles + t);
+            }
     }
     for (int q = 0; q < uf_batch::kQueues; ++q) {
         b->n_stripe_items[q] = (int32_t)(items[q].size() / 2);
@@ -437,10 +481,16 @@ uf_status uf_batch_create(uf_context *ctx, const uf_job *jobs, int32_t n_jobs,
         K.count_width = t ? t->count_width : 0;
         K.k_chunk = (t && t->k_chunk > 0) ? t->k_chunk : 4096;
         K.variant = t ? t->variant : 0;
+        K.k_split = t ? t->k_split : 0;
+        K.e_free = (t && t->emb_batch > 0) || J.prec != UF_PREC_FP64 ? 0 : 1;
         if ((K.den_mode != 0 && K.den_mode != 1) || K.tile < 0 || K.tile > 2 ||
             (K.variant != 0 && K.variant != 1)) {
             uf_batch_destroy(b);
             return set_err(ctx, UF_E_ARG, "den_mode and variant must be 0 or 1, tile 0, 1 or 2");
+        }
+        if (K.k_split < 0 || K.k_split > 64) {
+            uf_batch_destroy(b);
+            return set_err(ctx, UF_E_ARG, "k_split must be in [0, 64]");
         }
         if (J.method == UF_WEIGHTED_UNNORMALIZED) K.den_mode = 1;   // no denominator at all
         b->knobs.push_back(K);

@@ -483,9 +483,14 @@ __global__ __launch_bounds__(kBlock, (StripeCfg<T, DEN, TILE>::OCC)) void k_stri
         if (it >= n_items) break;
         const int2 item = items[it];
         const StripeArgs a = jobs[item.x];
-        const int32_t kt = item.y % a.tiles_k, stile = item.y / a.tiles_k;
+        // item.y = z * (tiles of the job) + tile: branch split z of a.kz, into its own state copy
+        const int32_t nt = a.tiles_k * a.tiles_s;
+        const int32_t z = item.y / nt, t = item.y - z * nt;
+        const int32_t kt = t % a.tiles_k, stile = t / a.tiles_k;
         const int32_t k0 = kt * SM::TKW, s0 = a.s_base + stile * SM::TSW;
-        stripe_tile<T, METHOD, DEN, TILE, CT>(a, k0, s0, 0, a.B, a.num, a.den, sm);
+        const int32_t bb = (int32_t)((int64_t)a.B * z / a.kz), be = (int32_t)((int64_t)a.B * (z + 1) / a.kz);
+        stripe_tile<T, METHOD, DEN, TILE, CT>(a, k0, s0, bb, be, a.num + z * a.zstride,
+                                              a.den ? a.den + z * a.zstride : nullptr, sm);
     }
 }
 

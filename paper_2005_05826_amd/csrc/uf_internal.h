@@ -153,7 +153,8 @@ struct StripeArgs {
 StripeArgs make_stripe_args(int32_t method, const void *C, int32_t cw, int64_t cstride,
                             const double *inv_t, const double *len, int32_t B, int32_t E,
                             double *num, double *den, const StripeGeom &g);
-// items_xy: (job index, tile index) pairs, tile = s_tile * tiles_k + k_tile; *counter == 0.
+// items_xy: (job index, item) pairs, item = z * tiles_k * tiles_s + s_tile * tiles_k + k_tile
+// for branch split z of the job's kz (state copy z at num + z * zstride); *counter == 0.
 hipError_t launch_stripe_queue(bool fp64, int32_t method, int32_t cw, int32_t den_mode, int32_t tile,
                                const StripeArgs *jobs, const int32_t *items_xy, int32_t n_items,
                                int32_t *counter, int32_t n_groups, hipStream_t st);

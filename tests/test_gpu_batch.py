@@ -79,15 +79,39 @@ def test_batch_matches_oracle(uf, ctx, jobs, den_mode, tile, variant):
     b.close()
 
 
-def test_batch_equals_single_plans_bitwise(uf, ctx, jobs):
+@pytest.mark.parametrize("k_split", [1, 0])
+def test_batch_equals_single_plans_bitwise(uf, ctx, jobs, k_split):
+    # k_split 1: neither side splits branches; 0: this batch is far too small to fill the
+    # device, so every striped job splits its branches (and sets its FP64 batch depth) by the
+    # single plan's automatic rule
+    tuning = dict(den_mode=0, tile=2, k_split=k_split)
     outs = _outs(jobs)
-    b = uf.Batch(ctx, [dict(problem=p, method=m, precision=pr, out=o) for (p, m, pr), o in zip(jobs, outs)])
+    b = uf.Batch(ctx, [dict(problem=p, method=m, precision=pr, out=o) for (p, m, pr), o in zip(jobs, outs)],
+                 tuning=tuning)
     b.run()
     for (p, m, pr), o in zip(jobs, outs):
         if p.n_samples < 2:
             continue
-        # the batch queues do not split branches; neither does this single plan
-        single = uf.Plan.from_problem(ctx, p).distance(m, pr, tuning=dict(k_split=1))
+        single = uf.Plan.from_problem(ctx, p).distance(m, pr, tuning=tuning)
+        np.testing.assert_array_equal(o.cpu().numpy(), single)
+    b.close()
+
+
+@pytest.mark.parametrize("k_split", [3, 16])
+def test_batch_branch_splits(uf, ctx, jobs, k_split):
+    """Explicit branch splits in the queues: the oracle's results to the usual bounds, and
+    bit for bit those of single plans with the same splits."""
+    tuning = dict(den_mode=1, tile=2, k_split=k_split)
+    outs = _outs(jobs)
+    b = uf.Batch(ctx, [dict(problem=p, method=m, precision=pr, out=o) for (p, m, pr), o in zip(jobs, outs)],
+                 tuning=tuning)
+    b.capture()
+    b.run()
+    _check(jobs, outs, _want(jobs), f"batch k_split={k_split}")
+    for (p, m, pr), o in zip(jobs, outs):
+        if p.n_samples < 2:
+            continue
+        single = uf.Plan.from_problem(ctx, p).distance(m, pr, tuning=tuning)
         np.testing.assert_array_equal(o.cpu().numpy(), single)
     b.close()
 
@@ -135,6 +159,9 @@ def test_batch_errors(uf, ctx, jobs):
         uf.Batch(ctx, [dict(problem=p, method="unweighted", precision="fp64", out=out),
                        dict(problem=bad, method="unweighted", precision="fp64", out=out)])
     assert ei.value.status_name == "UF_E_TREE"
+    with pytest.raises(uf.UniFracError) as ei:
+        uf.Batch(ctx, [dict(problem=p, method="unweighted", precision="fp64", out=out)], tuning=dict(k_split=65))
+    assert ei.value.status_name == "UF_E_ARG"
 
 
 @pytest.mark.parametrize("method,prec", [("weighted_normalized", "fp32"), ("unweighted", "mfma_bf16x2"),
