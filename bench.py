@@ -81,14 +81,14 @@ OPS_PER_UPDATE = {0: 4, 1: 2}   # den_mode 0: both stripes; 1: numerator only
 # it was measured on, and is reported as null once that source has changed.
 TRAFFIC = {
     "striped/4096x65534/fp32/den1/tile2/Edefault": {
-        "src_sha256": "88dd5e81b7dc8613", "fetch": 44847291904, "write": 34360240768,
-        "bytes": 79207532672, "profile": "profiles/k_stripe_fused_wn_fp32_4096x65534.md"},
+        "src_sha256": "4feb6c3f1359b372", "fetch": 44762635648, "write": 34360131328,
+        "bytes": 79122766976, "profile": "profiles/k_stripe_fused_wn_fp32_4096x65534.md"},
     "mfma/25000x599998/k_chunk4096/variant0": {
         "src_sha256": "50b963d3b08070fc", "fetch": 214780838976, "write": 104080554176,
         "bytes": 318861393152, "profile": "profiles/k_mfma_gemm_uw_25000x599998.md"},
     "hbm/25000x16382/fp64/den0/tile2/E8": {
-        "src_sha256": "88dd5e81b7dc8613", "fetch": 1830929088192, "write": 1964168561984,
-        "bytes": 3795097650176, "profile": "profiles/k_stripe_fused_hbm_regime_fp64_25000x16382.md"},
+        "src_sha256": "4feb6c3f1359b372", "fetch": 1899178808832, "write": 2013146971136,
+        "bytes": 3912325779968, "profile": "profiles/k_stripe_fused_hbm_regime_fp64_25000x16382.md"},
 }
 
 
