@@ -141,11 +141,10 @@ def test_batch_takes_per_job_tuned_knobs(uf):
     b.run()
     for (p, m, pr), o in zip(jobs, outs):
         got = o.cpu().numpy()
-        # the batch queues do not split branches; a single plan with the same knobs and no
-        # split gives the same bits
+        # a batch this small splits each striped job's branches as a single plan does, so a
+        # single plan with the same knobs gives the same bits
         t = ctx.tuned(m, pr, p.n_samples, p.n_nodes)
-        single = uf.Plan.from_problem(ctx, p).distance(m, pr, tuning=dict(t or {}, k_split=1) if t
-                                                         else dict(tile=2, k_split=1))
+        single = uf.Plan.from_problem(ctx, p).distance(m, pr, tuning=dict(t) if t else dict(tile=2))
         np.testing.assert_array_equal(got, single)
     b.close()
     ctx.close()
