@@ -143,8 +143,9 @@ typedef struct {
                            split, an FP64 batch depth left at its default shrinking to as
                            few as 64 branches to allow that; the state copies within 4 GB;
                            in a batch only while all its jobs' stripe tiles come to fewer
-                           than ten device rounds, so a job splits as it would alone), 1 =
-                           no split                                                          */
+                           than ten device rounds and the extra state copies of all its
+                           automatically split jobs stay within 16 GB, so a job splits as
+                           it would alone), 1 = no split                                     */
 } uf_tuning;
 
 typedef struct {

@@ -288,7 +288,9 @@ uf_status build_tables(uf_batch *b, hipStream_t st)
     // Branch splits: a tuning's k_split, else the single plan's automatic rule while all the
     // batch's stripe tiles come to fewer than ten rounds of the device (a job then gets the
     // splits and batch depth, and so the results, it gets when run alone); none once the
-    // tiles fill the device by themselves.
+    // tiles fill the device by themselves, or when the automatic splits' extra state copies
+    // would pass kSplitStateBudget over the whole batch (many small jobs).
+    constexpr size_t kSplitStateBudget = (size_t)16 << 30;
     double rounds = 0.0;
     for (int32_t j = 0; j < nj; ++j) {
         if (!is_striped(b->jobs[j])) continue;
@@ -298,6 +300,36 @@ uf_status build_tables(uf_batch *b, hipStream_t st)
     }
     const bool device_full = rounds >= 10.0;
     b->kz.assign(nj, 1);
+    std::vector<int32_t> job_E(nj, 1);
+    size_t auto_extra = 0;
+    for (int32_t j = 0; j < nj; ++j) {
+        if (!is_striped(b->jobs[j])) continue;
+        const JobKnobs &K = b->knobs[j];
+        uf_plan *p = b->plans[j];
+        const StripeGeom g = stripe_geometry(p->hp.n_samples, b->jobs[j].prec == UF_PREC_FP64, K.den_mode, K.tile);
+        const size_t state = (size_t)g.spad * g.sstride * sizeof(double);
+        job_E[j] = std::max(1, std::min({K.E, 4096, std::max(1, p->hp.n_nodes - 1)}));
+        if (K.k_split > 0 || !device_full) {
+            Knobs kn{};
+            kn.emb_batch = job_E[j];
+            kn.k_chunk = K.k_chunk;
+            kn.den_mode = K.den_mode;
+            kn.variant = 0;   // the queues always run the fused form
+            kn.tile = K.tile;
+            kn.count_width = K.count_width;
+            kn.k_split = K.k_split;
+            kn.e_free = K.e_free;
+            b->kz[j] = striped_k_split(p, kn, g, state);
+            job_E[j] = kn.emb_batch;   // the rule may shrink an FP64 default batch depth
+            if (K.k_split == 0) auto_extra += (size_t)(b->kz[j] - 1) * state * (K.den_mode == 0 ? 2 : 1);
+        }
+    }
+    if (auto_extra > kSplitStateBudget)
+        for (int32_t j = 0; j < nj; ++j)
+            if (is_striped(b->jobs[j]) && b->knobs[j].k_split == 0) {
+                b->kz[j] = 1;
+                job_E[j] = std::max(1, std::min({b->knobs[j].E, 4096, std::max(1, b->plans[j]->hp.n_nodes - 1)}));
+            }
     for (int32_t j : order) {
         const uf_job &J = b->jobs[j];
         if (!is_striped(J)) continue;
@@ -310,22 +342,8 @@ uf_status build_tables(uf_batch *b, hipStream_t st)
         const int q = queue_of(!fp64, km == UF_WEIGHTED_NORMALIZED, p->cw == 2, K.den_mode, K.tile);
         const StripeGeom g = stripe_geometry(hp.n_samples, fp64, K.den_mode, K.tile);
         const size_t state = (size_t)g.spad * g.sstride * sizeof(double);
-        int32_t E = std::max(1, std::min({K.E, 4096, std::max(1, hp.n_nodes - 1)}));
-        int32_t kz = 1;
-        if (K.k_split > 0 || !device_full) {
-            Knobs kn{};
-            kn.emb_batch = E;
-            kn.k_chunk = K.k_chunk;
-            kn.den_mode = K.den_mode;
-            kn.variant = 0;   // the queues always run the fused form
-            kn.tile = K.tile;
-            kn.count_width = K.count_width;
-            kn.k_split = K.k_split;
-            kn.e_free = K.e_free;
-            kz = striped_k_split(p, kn, g, state);
-            E = kn.emb_batch;
-        }
-        b->kz[j] = kz;
+        const int32_t E = job_E[j];
+        const int32_t kz = b->kz[j];
         UF_TRY(p->num.ensure(state * kz), "allocating stripes");
         if (K.den_mode == 0) UF_TRY(p->den.ensure(state * kz), "allocating stripes");
         UF_TRY(p->D.ensure((size_t)hp.n_samples * sizeof(double)), "allocating sums");
