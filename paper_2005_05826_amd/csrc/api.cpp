@@ -273,15 +273,15 @@ uf_status striped_core(uf_plan *plan, uf_method method, uf_precision prec, const
     }
     uf_status s = propagate_counts_into(plan, W.C, cw, st);
     if (s != UF_OK) return s;
-    // the stripe kernels add every batch into the state, so it starts at zero
-    UF_TRY(launch_fill_u32(num, 0u, state * kz / 4, st), "clearing stripes");
-    if (den) UF_TRY(launch_fill_u32(den, 0u, state * kz / 4, st), "clearing stripes");
+    // no clearing: the first batch of every split writes its state copy (every split has at
+    // least one branch, kz <= B, and the tiles cover the copy)
     const double *len = plan->len_slot.as<double>();
     UF_TRY(launch_inv_totals(plan->totals.as<int32_t>(), hp.n_samples, W.inv_t, st), "reciprocal totals");
     UF_TRY(timed(plan, "stripe", st, [&] {
                hipError_t r = launch_stripe_fused(fp64, method, kn.den_mode, kn.tile, W.C, cw,
                                                   plan->cstride, W.inv_t, len, B, kn.emb_batch, num,
-                                                  den, g, t0, t1, kz, (int64_t)(state / sizeof(double)), st);
+                                                  den, g, t0, t1, kz, (int64_t)(state / sizeof(double)),
+                                                  true, st);
                if (r == hipSuccess)
                    r = launch_reduce_z(num, (int64_t)(state / sizeof(double)), kz,
                                        (int64_t)(state / sizeof(double)), st);
@@ -386,7 +386,7 @@ uf_status striped_generated(uf_plan *plan, uf_method method, uf_precision prec, 
         UF_TRY(timed(plan, "stripe", st, [&] {
                    return launch_stripe_fused(fp64, method, kn.den_mode, kn.tile, buf, cw, plan->cstride,
                                               plan->inv_t.as<double>(), len + b0, eb, eb, num, den, g, t0,
-                                              t1, 1, (int64_t)(state / sizeof(double)), st);
+                                              t1, 1, (int64_t)(state / sizeof(double)), false, st);
                }), "striped accumulation");
         if (kn.den_mode != 0 && !unnorm)
             UF_TRY(timed(plan, "rowdot", st, [&] {

@@ -150,9 +150,13 @@ uf_status enqueue(uf_batch *b, hipStream_t st)
         uf_plan *p = b->plans[j];
         const JobKnobs &K = b->knobs[j];
         const StripeGeom g = stripe_geometry(p->hp.n_samples, b->jobs[j].prec == UF_PREC_FP64, K.den_mode, K.tile);
-        const size_t words = (size_t)g.spad * g.sstride * 2 * b->kz[j];
-        UF_TRY(launch_fill_u32(p->num.p, 0u, words, st), "clearing stripes");
-        if (K.den_mode == 0) UF_TRY(launch_fill_u32(p->den.p, 0u, words, st), "clearing stripes");
+        // a job with branches needs no clearing: the first batch of each of its splits writes
+        // that split's state copy; a single-node tree's zero state is cleared here
+        if (p->hp.n_nodes - 1 <= 0) {
+            const size_t words = (size_t)g.spad * g.sstride * 2;
+            UF_TRY(launch_fill_u32(p->num.p, 0u, words, st), "clearing stripes");
+            if (K.den_mode == 0) UF_TRY(launch_fill_u32(p->den.p, 0u, words, st), "clearing stripes");
+        }
         UF_TRY(launch_inv_totals(p->totals.as<int32_t>(), p->hp.n_samples, p->inv_t.as<double>(), st),
                "reciprocal totals");
     }
@@ -358,6 +362,7 @@ uf_status build_tables(uf_batch *b, hipStream_t st)
                                          K.den_mode == 0 ? p->den.as<double>() : nullptr, g));
         sj[q].back().kz = kz;
         sj[q].back().zstride = (int64_t)(state / sizeof(double));
+        sj[q].back().store_first = 1;
         if (hp.n_nodes - 1 <= 0 || g.S == 0) continue;  // nothing to accumulate
         const int32_t n_tiles = sj[q].back().tiles_k * sj[q].back().tiles_s;
         for (int32_t z = 0; z < kz; ++z)

@@ -54,13 +54,27 @@ __device__ inline T pin(T x)
 }
 
 // Adds a lane's register tile (TST stripe rows of TKT consecutive samples) into the FP64
-// stripe state (cleared before the first batch), one row at a time.
+// stripe state, one row at a time; with `store` (the first batch of a branch range whose
+// state was not cleared) writes it instead.
 template <int TST, int TKT, int DEN, typename T>
 __device__ inline void add_tile(const T (&an)[TST][TKT], const T (&ad)[TST][TKT],
                                 double *__restrict__ num, double *__restrict__ den,
-                                int64_t off, int64_t sstride)
+                                int64_t off, int64_t sstride, bool store)
 {
     static_assert(TKT % 2 == 0, "rows are written as double2");
+    if (store) {
+#pragma unroll
+        for (int s = 0; s < TST; ++s) {
+            double2 *pn = reinterpret_cast<double2 *>(num + off + s * sstride);
+            double2 *pd = reinterpret_cast<double2 *>(den + off + s * sstride);
+#pragma unroll
+            for (int r = 0; r < TKT; r += 2) {
+                pn[r / 2] = make_double2((double)pin(an[s][r]), (double)pin(an[s][r + 1]));
+                if (DEN == 0) pd[r / 2] = make_double2((double)pin(ad[s][r]), (double)pin(ad[s][r + 1]));
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int s = 0; s < TST; ++s) {
         double2 *pn = reinterpret_cast<double2 *>(num + off + s * sstride);
@@ -204,7 +218,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_stripe(
     }
 
     add_tile<TST, TKT, DEN>(an, ad, num, den, (int64_t)(s0 + w * TST) * sstride + k0 + lane * TKT,
-                            sstride);
+                            sstride, false);
 }
 
 // Fused form of (a2) + (b): one work-group tile covers every batch of branches.  The
@@ -355,6 +369,7 @@ __device__ void stripe_tile(const StripeArgs &a, int32_t k0, int32_t s0, int32_t
             ad[s][r] = T(0);
         }
     // stages: windows of at most EB branches inside batches [b0, b1) of E branches
+    bool store = a.store_first != 0;   // the range's first batch writes the state
     int32_t b1 = E < be - bb ? bb + E : be;
     int32_t e0 = bb;
     int32_t eb = (b1 - e0) < EB ? (b1 - e0) : EB;
@@ -431,7 +446,8 @@ __device__ void stripe_tile(const StripeArgs &a, int32_t k0, int32_t s0, int32_t
             // here rather than hoisted out of the stage loop into live registers
             int64_t off = (int64_t)(s0 - a.s_base + w * TST) * sstride + k0 + lane * TKT;
             asm volatile("" : "+v"(off));
-            add_tile<TST, TKT, DEN>(an, ad, num, den, off, sstride);
+            add_tile<TST, TKT, DEN>(an, ad, num, den, off, sstride, store);
+            store = false;
 #pragma unroll
             for (int s = 0; s < TST; ++s)
 #pragma unroll
@@ -787,7 +803,7 @@ hipError_t launch_stripe_fused(bool fp64, int32_t method, int32_t den_mode, int3
                                const void *C, int32_t cw, int64_t cstride, const double *inv_t,
                                const double *len, int32_t B, int32_t E, double *num, double *den,
                                const StripeGeom &g, int32_t tile_s0, int32_t tile_s1,
-                               int32_t kz, int64_t zstride, hipStream_t st)
+                               int32_t kz, int64_t zstride, bool store_first, hipStream_t st)
 {
     if (B <= 0 || tile_s1 <= tile_s0) return hipSuccess;
     StripeArgs a = make_stripe_args(method, C, cw, cstride, inv_t, len, B, E, num, den, g);
@@ -795,6 +811,7 @@ hipError_t launch_stripe_fused(bool fp64, int32_t method, int32_t den_mode, int3
     a.tiles_s = tile_s1 - tile_s0;
     a.kz = kz < 1 ? 1 : kz;
     a.zstride = zstride;
+    a.store_first = store_first ? 1 : 0;
     const int key = (fp64 ? 6 : 0) + 2 * (tile == 1 ? 1 : tile == 2 ? 2 : 0) + (cw == 2 ? 1 : 0);
     switch (key) {
     case 0: return fused_dispatch<float, 0, int32_t>(a, den_mode, g, st);
@@ -835,7 +852,7 @@ StripeArgs make_stripe_args(int32_t method, const void *C, int32_t cw, int64_t c
     a.tiles_s = g.spad / g.tsw;
     a.s_base = 0;
     a.kz = 1;
-    a.pad2 = 0;
+    a.store_first = 0;
     a.zstride = 0;
     return a;
 }

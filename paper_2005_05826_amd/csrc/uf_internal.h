@@ -147,7 +147,9 @@ struct StripeArgs {
     double *num, *den;       // stripe state [spad][sstride]
     int64_t sstride;
     int32_t method, tiles_k, tiles_s, s_base;   // s_base: stripe held by state row 0
-    int32_t kz, pad2;        // branch splits (grid z), each with its own state copy
+    int32_t kz;              // branch splits (grid z), each with its own state copy
+    int32_t store_first;     // 1: the first batch of each split writes its state copy
+                             // instead of adding into it, so the copies need no clearing
     int64_t zstride;         // elements between state copies
 };
 StripeArgs make_stripe_args(int32_t method, const void *C, int32_t cw, int64_t cstride,
@@ -164,7 +166,7 @@ hipError_t launch_stripe_fused(bool fp64, int32_t method, int32_t den_mode, int3
                                const void *C, int32_t cw, int64_t cstride, const double *inv_t,
                                const double *len, int32_t B, int32_t E, double *num, double *den,
                                const StripeGeom &g, int32_t tile_s0, int32_t tile_s1,
-                               int32_t kz, int64_t zstride, hipStream_t st);
+                               int32_t kz, int64_t zstride, bool store_first, hipStream_t st);
 // x[i] = sum over z of x[z * zstride + i] (z in order), for i < count.
 hipError_t launch_reduce_z(double *x, int64_t zstride, int32_t kz, int64_t count, hipStream_t st);
 // Writes the pairs of stripes [s_begin, s_end) (the state block's row 0 holds stripe
