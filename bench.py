@@ -81,14 +81,14 @@ OPS_PER_UPDATE = {0: 4, 1: 2}   # den_mode 0: both stripes; 1: numerator only
 # it was measured on, and is reported as null once that source has changed.
 TRAFFIC = {
     "striped/4096x65534/fp32/den1/tile2/Edefault": {
-        "src_sha256": "4feb6c3f1359b372", "fetch": 44762635648, "write": 34360131328,
-        "bytes": 79122766976, "profile": "profiles/k_stripe_fused_wn_fp32_4096x65534.md"},
+        "src_sha256": "07474d3cf4293234", "fetch": 42444018304, "write": 34360588032,
+        "bytes": 76804606336, "profile": "profiles/k_stripe_fused_wn_fp32_4096x65534.md"},
     "mfma/25000x599998/k_chunk4096/variant0": {
         "src_sha256": "50b963d3b08070fc", "fetch": 214780838976, "write": 104080554176,
         "bytes": 318861393152, "profile": "profiles/k_mfma_gemm_uw_25000x599998.md"},
     "hbm/25000x16382/fp64/den0/tile2/E8": {
-        "src_sha256": "4feb6c3f1359b372", "fetch": 1899178808832, "write": 2013146971136,
-        "bytes": 3912325779968, "profile": "profiles/k_stripe_fused_hbm_regime_fp64_25000x16382.md"},
+        "src_sha256": "07474d3cf4293234", "fetch": 1621896851008, "write": 2005536641472,
+        "bytes": 3627433492480, "profile": "profiles/k_stripe_fused_hbm_regime_fp64_25000x16382.md"},
 }
 
 
