@@ -358,8 +358,16 @@ def build_jobs(specs: list[dict], workers: int = 0) -> list[Problem]:
     import multiprocessing as mp
     # largest jobs first so the pool's tail is short; results go back in spec order
     order = sorted(range(len(specs)), key=lambda j: -int(specs[j]["n"]) * int(specs[j]["tips"]))
-    with mp.get_context("spawn").Pool(workers) as pool:
+    # the workers are closed and joined, not terminated: they exit by themselves once the
+    # work is done, with no signal (a profiler preloaded into them may not survive one)
+    pool = mp.get_context("spawn").Pool(workers)
+    try:
         built = pool.map(build_job, [specs[j] for j in order], chunksize=1)
+    except BaseException:
+        pool.terminate()
+        raise
+    pool.close()
+    pool.join()
     out: list = [None] * len(specs)
     for j, prob in zip(order, built):
         out[j] = prob
