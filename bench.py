@@ -77,32 +77,39 @@ OPS_PER_UPDATE = {0: 4, 1: 2}   # den_mode 0: both stripes; 1: numerator only
 # then WRITE_SIZE, KiB per dispatch) of this script's default configuration of each
 # workload, each scaled by what the same counter reads for a 1 GiB device copy
 # (--copy-calibration: FETCH_SIZE reads 0.5 GiB, WRITE_SIZE 1 GiB, so x2.0 and x1.0).
-# Keyed by workload and configuration; each entry records the SHA-256 of the kernel source
-# it was measured on, and is reported as null once that source has changed.
+# Keyed by workload and configuration; each entry records the SHA-256 of the sources it was
+# measured on (the kernel file, and for the striped kernels also api.cpp, which sets their
+# branch splits), and is reported as null once any of them has changed.
 TRAFFIC = {
     "striped/4096x65534/fp32/den1/tile2/Edefault": {
-        "src_sha256": "07474d3cf4293234", "fetch": 42444018304, "write": 34360588032,
-        "bytes": 76804606336, "profile": "profiles/k_stripe_fused_wn_fp32_4096x65534.md"},
+        "src_sha256": "64071a8f2bc53609", "fetch": 40617685504, "write": 34360988416,
+        "bytes": 74978673920, "profile": "profiles/k_stripe_fused_wn_fp32_4096x65534.md"},
     "mfma/25000x599998/k_chunk4096/variant0": {
         "src_sha256": "50b963d3b08070fc", "fetch": 214780838976, "write": 104080554176,
         "bytes": 318861393152, "profile": "profiles/k_mfma_gemm_uw_25000x599998.md"},
     "hbm/25000x16382/fp64/den0/tile2/E8": {
-        "src_sha256": "07474d3cf4293234", "fetch": 1621896851008, "write": 2005536641472,
-        "bytes": 3627433492480, "profile": "profiles/k_stripe_fused_hbm_regime_fp64_25000x16382.md"},
+        "src_sha256": "64071a8f2bc53609", "fetch": 1723584764096, "write": 1990136533568,
+        "bytes": 3713721297664, "profile": "profiles/k_stripe_fused_hbm_regime_fp64_25000x16382.md"},
 }
 
 
-def add_traffic(roofline, key, source, launch_ms):
+def sources_sha(sources):
+    """First 16 hex digits of the SHA-256 of the named csrc files, concatenated in order."""
+    import hashlib
+    h = hashlib.sha256()
+    for source in sources:
+        with open(os.path.join(ROOT, "paper_2005_05826_amd", "csrc", source), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def add_traffic(roofline, key, sources, launch_ms):
     """Sets roofline["traffic"] (HBM bytes per launch, or None) and, when known, the HBM
     bandwidth that traffic implies at the launch time measured here."""
-    import hashlib
     roofline["traffic"] = None
     ent = TRAFFIC.get(key)
-    if not ent:
+    if not ent or sources_sha(sources) != ent["src_sha256"]:
         return
-    with open(os.path.join(ROOT, "paper_2005_05826_amd", "csrc", source), "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest()[:16] != ent["src_sha256"]:
-            return
     roofline["traffic"] = ent["bytes"]
     gbs = ent["bytes"] / (launch_ms * 1e-3) / 1e9
     roofline["traffic_detail"] = {"fetch_bytes": ent["fetch"], "write_bytes": ent["write"],
@@ -345,7 +352,7 @@ def bench_striped(args):
         roofline = stripe_roofline(prec, total_ms, args.steps, den_mode)
         roofline.update({"launches_per_step": launches // args.steps,
                          "avg_launch_ms": round(total_ms / launches, 4)})
-        add_traffic(roofline, key, "k_stripe.hip", total_ms / launches)
+        add_traffic(roofline, key, ("k_stripe.hip", "api.cpp"), total_ms / launches)
     res = base_record(args, updates / dt, dt, "f32" if prec == "fp32" else "f64",
                       {"workload": f"{method.replace('_', '-')} striped UniFrac, {n} samples, "
                                    f"coalescent tree with {(prob.n_nodes + 1) // 2} tips ({B} branches)",
@@ -503,7 +510,7 @@ def bench_mfma(args):
                        "frac": round(achieved / MFMA_BF16_PEAK_TFLOPS, 4),
                        "avg_launch_ms": round(total_ms / max(1, launches), 3)}
     if launches:
-        add_traffic(res["roofline"], key, "k_mfma.hip", total_ms / launches)
+        add_traffic(res["roofline"], key, ("k_mfma.hip",), total_ms / launches)
     if compare:
         out2 = torch.empty_like(out)
         dt2, prof2 = timed_runs(plan, "unweighted", compare, dict(den_mode=0, tile=2), out2, 1, 0, stream)
@@ -758,7 +765,7 @@ def bench_hbm(args):
                        "algorithmic_bytes": alg,
                        "avg_launch_ms": round(total_ms / max(1, launches), 3)}
     if launches:
-        add_traffic(res["roofline"], f"hbm/{n}x{B}/fp64/den0/tile{tile}/E{E}", "k_stripe.hip",
+        add_traffic(res["roofline"], f"hbm/{n}x{B}/fp64/den0/tile{tile}/E{E}", ("k_stripe.hip", "api.cpp"),
                     total_ms / launches)
     if not args.no_cpu:
         cpu, pi, pj, want = oracle_sample(prob, "weighted_normalized", args.cpu_seconds, 20050526 + 94,

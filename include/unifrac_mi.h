@@ -137,8 +137,8 @@ typedef struct {
                            slice into its own copy of the stripe state, and the copies are
                            summed in order afterwards (more work-groups when the stripe
                            tiles alone do not fill the device many times over); 0 =
-                           automatic (about ten device rounds from the whole problem's
-                           stripe tiles, also for stripe ranges; at most 16 splits, 64 when
+                           automatic (about twenty device rounds from the whole problem's
+                           stripe tiles, also for stripe ranges; at most 32 splits, 64 when
                            16 would not fill the device once; at least two batches per
                            split, an FP64 batch depth left at its default shrinking to as
                            few as 64 branches to allow that; the state copies within 4 GB;

@@ -196,20 +196,21 @@ Knobs resolve_knobs(const uf_tuning *t, uf_precision prec, int32_t n_branches)
     return k;
 }
 
-// Branch splits of the fused striped kernel: enough work-groups for about ten rounds of the
-// device, so that the work-groups that finish last hold a small part of the run (two rounds
-// left a measured 5 % behind), at most 16 splits, at least two batches per split, and the
-// copies of the stripe state within 4 GB.  No split when the stripe tiles alone give ten
-// rounds.
+// Branch splits of the fused striped kernel: enough work-groups for about twenty rounds of
+// the device, so that the work-groups that finish last hold a small part of the run (two
+// rounds left a measured 5 % behind; on 4,096 samples 32 splits beat 16 by 1-1.5 % in FP32
+// and FP64 once the copies were no longer cleared), at most 32 splits, at least two batches
+// per split, and the copies of the stripe state within 4 GB.  No split when the stripe tiles
+// alone give twenty rounds.
 int32_t auto_k_split(const uf_context *ctx, const StripeGeom &g, int64_t tiles, int32_t B, int32_t *E,
                      bool e_free, size_t state_bytes)
 {
     const int64_t slots = (int64_t)std::max(ctx->n_cu, 1) * std::max(g.occ, 1);
-    constexpr int64_t kRounds = 10;
+    constexpr int64_t kRounds = 20;
     if (tiles <= 0 || tiles >= kRounds * slots) return 1;
     int64_t kz = (kRounds * slots + tiles - 1) / tiles;
-    // up to 16 splits; up to 64 when even 16 would not give the device one round
-    kz = std::min<int64_t>(kz, tiles * 16 < slots ? 64 : 16);
+    // up to 32 splits; up to 64 when even 16 would not give the device one round
+    kz = std::min<int64_t>(kz, tiles * 16 < slots ? 64 : 32);
     // >= 2 batches per split; a batch depth the caller left free (FP64, where it only
     // trades state traffic) shrinks, down to 64 branches, to allow the splits
     if (e_free && B / std::max(2 * *E, 1) < kz) *E = (int32_t)std::max<int64_t>(64, std::min<int64_t>(*E, B / (2 * kz)));
