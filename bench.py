@@ -82,13 +82,13 @@ OPS_PER_UPDATE = {0: 4, 1: 2}   # den_mode 0: both stripes; 1: numerator only
 # branch splits), and is reported as null once any of them has changed.
 TRAFFIC = {
     "striped/4096x65534/fp32/den1/tile2/Edefault": {
-        "src_sha256": "64071a8f2bc53609", "fetch": 40617685504, "write": 34360988416,
+        "src_sha256": "3689552ba0fdb464", "fetch": 40617685504, "write": 34360988416,
         "bytes": 74978673920, "profile": "profiles/k_stripe_fused_wn_fp32_4096x65534.md"},
     "mfma/25000x599998/k_chunk4096/variant0": {
         "src_sha256": "50b963d3b08070fc", "fetch": 214780838976, "write": 104080554176,
         "bytes": 318861393152, "profile": "profiles/k_mfma_gemm_uw_25000x599998.md"},
     "hbm/25000x16382/fp64/den0/tile2/E8": {
-        "src_sha256": "64071a8f2bc53609", "fetch": 1723584764096, "write": 1990136533568,
+        "src_sha256": "3689552ba0fdb464", "fetch": 1723584764096, "write": 1990136533568,
         "bytes": 3713721297664, "profile": "profiles/k_stripe_fused_hbm_regime_fp64_25000x16382.md"},
 }
 

@@ -267,8 +267,9 @@ uf_status uf_plan_trim(uf_plan *plan);
 uf_status uf_plan_set_memory_limit(uf_plan *plan, int64_t max_device_bytes);
 
 /* Per-kernel timing with HIP events recorded on the launch stream around every device
- * launch of the plan, grouped by kernel class ("propagate", "transform", "stripe",
- * "rowdot", "condense", "bits_transpose", "mfma", "normalize").  enable != 0 turns it on
+ * launch of the plan, grouped by kernel class ("propagate", "transform", "stripe", "reduce"
+ * (the sum of the branch splits' state copies), "rowdot", "condense", "bits_transpose",
+ * "mfma", "normalize").  enable != 0 turns it on
  * and clears the totals; enable == 0 turns it off.  Costs one event pair per launch. */
 typedef struct {
     char name[32];

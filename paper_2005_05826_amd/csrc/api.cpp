@@ -279,18 +279,19 @@ uf_status striped_core(uf_plan *plan, uf_method method, uf_precision prec, const
     const double *len = plan->len_slot.as<double>();
     UF_TRY(launch_inv_totals(plan->totals.as<int32_t>(), hp.n_samples, W.inv_t, st), "reciprocal totals");
     UF_TRY(timed(plan, "stripe", st, [&] {
-               hipError_t r = launch_stripe_fused(fp64, method, kn.den_mode, kn.tile, W.C, cw,
-                                                  plan->cstride, W.inv_t, len, B, kn.emb_batch, num,
-                                                  den, g, t0, t1, kz, (int64_t)(state / sizeof(double)),
-                                                  true, st);
-               if (r == hipSuccess)
-                   r = launch_reduce_z(num, (int64_t)(state / sizeof(double)), kz,
-                                       (int64_t)(state / sizeof(double)), st);
-               if (r == hipSuccess && den)
-                   r = launch_reduce_z(den, (int64_t)(state / sizeof(double)), kz,
-                                       (int64_t)(state / sizeof(double)), st);
-               return r;
+               return launch_stripe_fused(fp64, method, kn.den_mode, kn.tile, W.C, cw,
+                                          plan->cstride, W.inv_t, len, B, kn.emb_batch, num, den, g,
+                                          t0, t1, kz, (int64_t)(state / sizeof(double)), true, st);
            }), "striped accumulation");
+    if (kz > 1)   // the split copies, summed in split order
+        UF_TRY(timed(plan, "reduce", st, [&] {
+                   hipError_t r = launch_reduce_z(num, (int64_t)(state / sizeof(double)), kz,
+                                                  (int64_t)(state / sizeof(double)), st);
+                   if (r == hipSuccess && den)
+                       r = launch_reduce_z(den, (int64_t)(state / sizeof(double)), kz,
+                                           (int64_t)(state / sizeof(double)), st);
+                   return r;
+               }), "summing branch splits");
     if (kn.den_mode != 0 && !unnorm)
         UF_TRY(timed(plan, "rowdot", st, [&] {
                    return launch_rowdot(method, W.C, cw, plan->cstride, 0, B, plan->totals.as<int32_t>(),

@@ -183,7 +183,7 @@ uf_status enqueue(uf_batch *b, hipStream_t st)
         const StripeGeom g = stripe_geometry(p->hp.n_samples, J.prec == UF_PREC_FP64, K.den_mode, K.tile);
         if (b->kz[j] > 1) {   // the branch splits' state copies, summed in split order
             const int64_t cnt = (int64_t)g.spad * g.sstride;
-            UF_TRY(timed(b->prof, "stripe", st, [&] {
+            UF_TRY(timed(b->prof, "reduce", st, [&] {
                        hipError_t r = launch_reduce_z(p->num.as<double>(), cnt, b->kz[j], cnt, st);
                        if (r == hipSuccess && K.den_mode == 0)
                            r = launch_reduce_z(p->den.as<double>(), cnt, b->kz[j], cnt, st);
